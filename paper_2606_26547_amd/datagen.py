@@ -1,0 +1,280 @@
+"""Seeded synthetic inputs for the HDC classification hot path.
+
+This module only draws inputs: feature matrices, labels and the random +-1
+projection matrix that random-projection encoding multiplies by (Sec. 2.2,
+Listing 1: a ``hypermatrix<D, F>`` of random projections).  It contains none
+of the HDC arithmetic (no encoding, bundling, distance or argmin), so both the
+CPU oracle and the HIP path can consume exactly the same arrays.
+
+Every generator is driven by ``numpy.random.Generator(PCG64)`` seeded with a
+``SeedSequence([seed, stream])`` so that each item (mixture parameters, sample
+draws, projection matrix, query draws, sweep sampling, arrival process) has
+its own independent stream.
+
+The datasets the paper evaluates on (ISOLET, Cora, genome reads) are not
+available here; the workloads below are synthetic stand-ins with the shapes,
+value distributions and class structure described for each configuration:
+
+* ``c1``  plain classify: 10 isotropic Gaussian clusters, 64 fp32 features,
+  1000 train / 200 test, D = 2048.
+* ``c2``  speech-feature shaped (ISOLET's 617 features, 26 classes,
+  6238 / 1559 split): a 3-component Gaussian mixture per class, quantised to
+  int8 with a per-feature symmetric scale, D = 10240.
+* ``c3``  image shaped (784 = 28x28 uint8 features, 10 classes,
+  60000 / 10000): ~80% zeros, nonzeros uniform in [1, 255] under a
+  class-dependent spatial mask, D = 8192.
+* ``c4``  2000 fresh queries from the ``c2`` mixture for the configuration
+  sweep.
+* ``serving_models``  8 models of differing (F, K, D) for the serving loop.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+# Stream identifiers (second word of the SeedSequence entropy).
+_S_MIX, _S_TRAIN, _S_TEST, _S_PROJ, _S_LABELS, _S_EXTRA, _S_MASK = range(1, 8)
+
+
+def rng(seed: int, stream: int, *sub: int) -> np.random.Generator:
+    """Independent PCG64 stream for (seed, stream, *sub)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream), *map(int, sub)])))
+
+
+def projection_matrix(D: int, F: int, seed: int) -> np.ndarray:
+    """Seeded +-1 projection matrix stored as P[D][F] int8 (P = B^T)."""
+    bits = rng(seed, _S_PROJ, D, F).integers(0, 2, size=(D, F), dtype=np.int8)
+    return (1 - 2 * bits).astype(np.int8)
+
+
+def balanced_labels(n: int, K: int, g: np.random.Generator) -> np.ndarray:
+    """Labels assigned round-robin (i mod K) and then shuffled."""
+    lab = (np.arange(n) % K).astype(np.int32)
+    g.shuffle(lab)
+    return lab
+
+
+def quantize_scales(X_train: np.ndarray) -> np.ndarray:
+    """Per-feature symmetric scale s_f = max_i |x_if| / 127 over the train set."""
+    s = np.abs(X_train.astype(np.float64)).max(axis=0) / 127.0
+    s[s == 0] = 1.0
+    return s
+
+
+def quantize_int8(X: np.ndarray, scales: np.ndarray) -> np.ndarray:
+    """q = clamp(round_half_even(x / s_f), -127, 127) computed in float64."""
+    q = np.rint(X.astype(np.float64) / scales[None, :])
+    return np.clip(q, -127, 127).astype(np.int8)
+
+
+@dataclasses.dataclass
+class Dataset:
+    name: str
+    X_train: np.ndarray          # [n_train][F]  fp32 / int8 / uint8
+    y_train: np.ndarray          # [n_train] int32
+    X_test: np.ndarray           # [n_test][F]
+    y_test: np.ndarray           # [n_test] int32
+    P: np.ndarray                # [D][F] int8 +-1
+    K: int
+    meta: dict
+
+    @property
+    def F(self) -> int:
+        return int(self.X_train.shape[1])
+
+    @property
+    def D(self) -> int:
+        return int(self.P.shape[0])
+
+
+# ---------------------------------------------------------------- mixtures
+class GaussianMixture:
+    """K classes, each a mixture of ``comps`` isotropic Gaussian components.
+
+    Class means mu_c ~ N(0, I); component means mu_c + tau * N(0, I), except
+    that the last component of every class is pulled a fraction ``overlap``
+    of the way towards the mean of another class (a random derangement), so
+    that classes overlap the way real feature data does; samples =
+    component mean + sigma * N(0, I)."""
+
+    def __init__(self, K: int, F: int, comps: int, tau: float, sigma: float, seed: int,
+                 overlap: float = 0.0):
+        self.K, self.F, self.comps, self.tau, self.sigma, self.seed = K, F, comps, tau, sigma, seed
+        g = rng(seed, _S_MIX)
+        mu = g.standard_normal((K, F))
+        self.means = mu[:, None, :] + tau * g.standard_normal((K, comps, F))
+        if overlap > 0 and K > 1:
+            other = (np.arange(K) + 1 + g.integers(0, K - 1, size=K)) % K
+            self.means[:, -1, :] += overlap * (mu[other] - mu)
+
+    def sample(self, labels: np.ndarray, g: np.random.Generator, chunk: int = 1 << 16) -> np.ndarray:
+        n = labels.shape[0]
+        out = np.empty((n, self.F), dtype=np.float32)
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            lab = labels[a:b]
+            comp = g.integers(0, self.comps, size=b - a)
+            noise = g.standard_normal((b - a, self.F), dtype=np.float32)
+            out[a:b] = self.means[lab, comp].astype(np.float32) + np.float32(self.sigma) * noise
+        return out
+
+
+# ---------------------------------------------------------------- configs
+C1 = dict(K=10, F=64, D=2048, n_train=1000, n_test=200, sigma=0.5)
+# tau / sigma / overlap fixed once so that the exact plain model lands in the
+# 0.85-0.92 accuracy band of the paper's ISOLET baselines (measured: 0.914 at
+# D = 10240, 0.908 at D' = 4096, 0.894 at D' = 2048).
+C2 = dict(K=26, F=617, D=10240, n_train=6238, n_test=1559, comps=3, tau=0.55, sigma=3.0,
+          overlap=0.55)
+C3 = dict(K=10, F=784, D=8192, n_train=60000, n_test=10000, side=28, mask_frac=0.30,
+          p_in=0.6, p_out=0.02)
+C4 = dict(n_queries=2000, n_slots=256,
+          d_trunc=(1024, 2048, 4096, 8192, 10240), stride=(1, 2, 4, 8), dtype=("int8", "bf16", "fp8"))
+
+
+def config_c1(seed: int = 1) -> Dataset:
+    c = C1
+    g = rng(seed, _S_MIX)
+    mu = g.standard_normal((c["K"], c["F"]))
+    ytr = np.repeat(np.arange(c["K"], dtype=np.int32), c["n_train"] // c["K"])
+    yte = np.repeat(np.arange(c["K"], dtype=np.int32), c["n_test"] // c["K"])
+    rng(seed, _S_LABELS).shuffle(ytr)
+    gtr, gte = rng(seed, _S_TRAIN), rng(seed, _S_TEST)
+    Xtr = (mu[ytr] + c["sigma"] * gtr.standard_normal((ytr.size, c["F"]))).astype(np.float32)
+    Xte = (mu[yte] + c["sigma"] * gte.standard_normal((yte.size, c["F"]))).astype(np.float32)
+    return Dataset("c1", Xtr, ytr, Xte, yte, projection_matrix(c["D"], c["F"], seed), c["K"],
+                   dict(x_type="fp32", seed=seed, **c))
+
+
+class SpeechLike:
+    """The c2 mixture with its train-set quantisation scales; can draw any
+    number of further quantised queries (c4 and the scaled bench batches)."""
+
+    def __init__(self, seed: int = 2, **over):
+        c = dict(C2, **over)
+        self.c, self.seed = c, seed
+        self.mix = GaussianMixture(c["K"], c["F"], c["comps"], c["tau"], c["sigma"], seed,
+                                   c.get("overlap", 0.0))
+        self.y_train = balanced_labels(c["n_train"], c["K"], rng(seed, _S_LABELS, 0))
+        self.X_train_f = self.mix.sample(self.y_train, rng(seed, _S_TRAIN))
+        self.scales = quantize_scales(self.X_train_f)
+
+    def queries(self, n: int, stream: int) -> tuple[np.ndarray, np.ndarray]:
+        y = balanced_labels(n, self.c["K"], rng(self.seed, _S_LABELS, 1 + stream))
+        Xf = self.mix.sample(y, rng(self.seed, _S_EXTRA, stream))
+        return quantize_int8(Xf, self.scales), y
+
+    def dataset(self) -> Dataset:
+        c = self.c
+        yte = balanced_labels(c["n_test"], c["K"], rng(self.seed, _S_LABELS, 1000))
+        Xte = quantize_int8(self.mix.sample(yte, rng(self.seed, _S_TEST)), self.scales)
+        return Dataset("c2", quantize_int8(self.X_train_f, self.scales), self.y_train, Xte, yte,
+                       projection_matrix(c["D"], c["F"], self.seed), c["K"],
+                       dict(x_type="int8", seed=self.seed, **c))
+
+
+def config_c2(seed: int = 2) -> Dataset:
+    return SpeechLike(seed).dataset()
+
+
+def class_masks(K: int, side: int, frac: float, g: np.random.Generator) -> np.ndarray:
+    """Per-class boolean masks over a side x side grid: unions of random
+    rectangles grown until they cover ``frac`` of the grid."""
+    masks = np.zeros((K, side, side), dtype=bool)
+    for k in range(K):
+        m = masks[k]
+        while m.mean() < frac:
+            h, w = g.integers(3, side // 2, size=2)
+            r, c = g.integers(0, side - h + 1), g.integers(0, side - w + 1)
+            m[r:r + h, c:c + w] = True
+    return masks.reshape(K, side * side)
+
+
+class ImageLike:
+    """c3: uint8 images with ~80% zeros under class-dependent spatial masks."""
+
+    def __init__(self, seed: int = 3, **over):
+        c = dict(C3, **over)
+        self.c, self.seed = c, seed
+        self.masks = class_masks(c["K"], c["side"], c["mask_frac"], rng(seed, _S_MASK))
+
+    def draw(self, y: np.ndarray, g: np.random.Generator) -> np.ndarray:
+        p = np.where(self.masks[y], self.c["p_in"], self.c["p_out"])
+        nz = g.random(p.shape) < p
+        vals = g.integers(1, 256, size=p.shape, dtype=np.int16)
+        return np.where(nz, vals, 0).astype(np.uint8)
+
+    def queries(self, n: int, stream: int) -> tuple[np.ndarray, np.ndarray]:
+        y = balanced_labels(n, self.c["K"], rng(self.seed, _S_LABELS, 1 + stream))
+        return self.draw(y, rng(self.seed, _S_EXTRA, stream)), y
+
+    def dataset(self) -> Dataset:
+        c = self.c
+        ytr = balanced_labels(c["n_train"], c["K"], rng(self.seed, _S_LABELS, 0))
+        yte = balanced_labels(c["n_test"], c["K"], rng(self.seed, _S_LABELS, 1000))
+        F = c["side"] * c["side"]
+        return Dataset("c3", self.draw(ytr, rng(self.seed, _S_TRAIN)), ytr,
+                       self.draw(yte, rng(self.seed, _S_TEST)), yte,
+                       projection_matrix(c["D"], F, self.seed), c["K"],
+                       dict(x_type="uint8", seed=self.seed, **c))
+
+
+def config_c3(seed: int = 3) -> Dataset:
+    return ImageLike(seed).dataset()
+
+
+def sweep_grid() -> list[tuple[int, int, str]]:
+    """The 5 x 4 x 3 = 60-point grid of (D', stride, dtype)."""
+    c = C4
+    return [(d, k, t) for d in c["d_trunc"] for k in c["stride"] for t in c["dtype"]]
+
+
+def sweep_slots(seed: int = 4, n_slots: int = C4["n_slots"]) -> list[tuple[int, int, str]]:
+    """``n_slots`` configurations drawn with replacement from the 60-point
+    grid (the grid has fewer points than slots, so duplicates occur)."""
+    grid = sweep_grid()
+    idx = rng(seed, _S_EXTRA, 99).integers(0, len(grid), size=n_slots)
+    return [grid[i] for i in idx]
+
+
+# ---------------------------------------------------------------- serving
+SERVING_SHAPES = [(64, 2, 1024), (96, 5, 1024), (128, 10, 2048), (256, 26, 4096),
+                  (512, 50, 8192), (617, 26, 10240), (784, 10, 8192), (1024, 100, 16384)]
+
+
+class ClusterModelData:
+    """Gaussian-cluster data for one serving model, int8-quantised."""
+
+    def __init__(self, F: int, K: int, D: int, seed: int, sigma: float = 1.6, per_class: int = 64):
+        self.F, self.K, self.D, self.seed = F, K, D, seed
+        g = rng(seed, _S_MIX, F, K, D)
+        self.mu = g.standard_normal((K, F))
+        self.sigma = sigma
+        self.y_train = balanced_labels(per_class * K, K, rng(seed, _S_LABELS, F, K, D))
+        Xf = self._draw(self.y_train, rng(seed, _S_TRAIN, F, K, D))
+        self.scales = quantize_scales(Xf)
+        self.X_train = quantize_int8(Xf, self.scales)
+        self.P = projection_matrix(D, F, seed * 1000 + F)
+
+    def _draw(self, y, g):
+        return (self.mu[y] + self.sigma * g.standard_normal((y.size, self.F))).astype(np.float32)
+
+    def queries(self, n: int, stream: int) -> tuple[np.ndarray, np.ndarray]:
+        y = rng(self.seed, _S_LABELS, self.F, 7, stream).integers(0, self.K, size=n).astype(np.int32)
+        return quantize_int8(self._draw(y, rng(self.seed, _S_EXTRA, self.F, stream)), self.scales), y
+
+
+def serving_models(seed: int = 5) -> list[ClusterModelData]:
+    return [ClusterModelData(F, K, D, seed + i) for i, (F, K, D) in enumerate(SERVING_SHAPES)]
+
+
+def random_case(n: int, F: int, D: int, x_type: str, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Small unstructured case for parity tests: features and a projection."""
+    g = rng(seed, _S_EXTRA, n, F, D)
+    if x_type == "int8":
+        X = g.integers(-128, 128, size=(n, F), dtype=np.int16).astype(np.int8)
+    elif x_type == "uint8":
+        X = g.integers(0, 256, size=(n, F), dtype=np.int16).astype(np.uint8)
+    else:
+        X = g.standard_normal((n, F)).astype(np.float32)
+    return X, projection_matrix(D, F, seed + 17)

@@ -1,0 +1,220 @@
+/*
+ * hdc.h -- C ABI of libhdc.so, the MI355X (gfx950) HDC classification hot
+ * path: random-projection encoding with binarisation, majority bundling,
+ * Hamming distance under reduction perforation, argmin, the fused
+ * classifier and a one-launch evaluation of many approximation
+ * configurations (arXiv 2606.26547).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller,
+ *   except where a comment says "host".  The library allocates no device
+ *   memory in any call; scratch comes from the caller's `ws` buffer, sized
+ *   by the matching *_workspace_bytes() function.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  Every call only enqueues work on that stream and returns;
+ *   outputs are valid once the stream has reached that point.  Calls on one
+ *   stream are ordered; calls sharing a workspace must not overlap.
+ * Errors.  Arguments are validated synchronously before anything is
+ *   enqueued: HDC_ERR_INVALID for a NULL required pointer, a negative count,
+ *   non-positive F / D / K, a leading dimension that is too small or
+ *   misaligned, or an empty/out-of-range dimension set; HDC_ERR_UNSUPPORTED
+ *   for a feature-type / compute-type pair or a size outside the compiled
+ *   kernels; HDC_ERR_WORKSPACE when ws_bytes is below the required size;
+ *   HDC_ERR_DEVICE when a launch fails.  n == 0 enqueues nothing and returns
+ *   HDC_OK.  No exception crosses the ABI.
+ * Hypervectors.  A binary hypervector is a row of uint64 words; bit j of
+ *   word w is element 64*w + j (LSB first, little-endian words).  A set bit
+ *   encodes the bipolar value -1, a clear bit +1.  Bits past the last
+ *   element of a row are written as 0 and must be 0 on input.
+ * Dimension sets.  hdc_dims {start, end, stride} selects the dimensions
+ *   S = { start + j*stride : start + j*stride < end } of a D-dimensional
+ *   hypervector, in that order; {0, D, 1} is "no approximation".  This is
+ *   the paper's reduction perforation (start offset, end offset, stride;
+ *   Sec. 2.2 Listing 1 and Sec. 4.2 "Reduction Perforation"); truncating
+ *   the encoding dimensionality to D' (Sec. 4.2 "Encoding Dimensionality")
+ *   is {0, D', 1}.  Requires 0 <= start < end <= D and stride >= 1.
+ * Features.  X is row-major [n][ldx] of `x_type` elements.  Only columns
+ *   [0, F) are read as features; ldx must be >= F rounded up to 64 and a
+ *   multiple of 16 elements, and X 16-byte aligned (the pad columns are
+ *   read but ignored).
+ * Projection.  P is the random +-1 projection hypermatrix stored
+ *   row-major [D][ldp] int8 (row d holds the F weights of dimension d, i.e.
+ *   P = B^T for the paper's random-projection matrix B; Sec. 2.2 Listing
+ *   1's hypermatrix<D, F>).  ldp >= F rounded up to 64, a multiple of 16,
+ *   P 16-byte aligned; columns [0, F) must hold +1 or -1.
+ */
+#ifndef HDC_H
+#define HDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HDC_OK = 0,
+    HDC_ERR_INVALID = 1,
+    HDC_ERR_UNSUPPORTED = 2,
+    HDC_ERR_WORKSPACE = 3,
+    HDC_ERR_DEVICE = 4
+} hdc_status;
+
+/* Feature types (x_type) and encoding compute types (compute).
+ * Supported (x_type -> compute) pairs:
+ *   HDC_INT8 / HDC_UINT8 -> HDC_INT8     exact: int8 MFMA, int32 accumulation
+ *                                        (uint8 runs as x-128 plus a column-sum
+ *                                        correction, also exact)
+ *   HDC_INT8 / HDC_UINT8 -> HDC_BF16     bf16 MFMA, fp32 accumulation
+ *   HDC_INT8 / HDC_UINT8 -> HDC_FP8_E4M3 OCP E4M3 MFMA, fp32 accumulation
+ *   HDC_FP32 -> HDC_FP32 / HDC_BF16 / HDC_FP8_E4M3   (F <= 256)
+ * The reduced types round each feature to the compute type (round to nearest
+ * even) and multiply by the exactly representable +-1 weights (Sec. 4.2
+ * "Element Type Representation"). */
+typedef enum {
+    HDC_INT8 = 0,
+    HDC_UINT8 = 1,
+    HDC_BF16 = 2,
+    HDC_FP8_E4M3 = 3,
+    HDC_FP32 = 4
+} hdc_dtype;
+
+typedef struct {
+    int32_t start, end, stride;
+} hdc_dims;
+
+/* Human-readable name of a status code (static string). */
+const char *hdc_status_string(hdc_status s);
+
+/* Number of dimensions in a dimension set (0 when it is empty/invalid). */
+int32_t hdc_dims_count(hdc_dims dims);
+
+/* ---------------------------------------------------------------------
+ * hdc_encode -- random-projection encoding followed by binarisation
+ * (Sec. 2.2 Listing 1, the matmul primitive; Sec. 4.2 "Automatic
+ * Binarization").  For each query row i and the j-th dimension d = S_j:
+ *     y = sum_{f<F} x'[i][f] * P[d][f],   bit j of H row i = (y < 0)
+ * where x' is the feature under `compute`; y == 0 gives +1 (bit 0).  Only
+ * the |S| selected dimensions are computed; they are packed densely, so a
+ * row holds ceil(|S|/64) words.
+ *   H   [n][ldh] uint64, ldh >= ceil(|S|/64); words past that are untouched.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_encode(void *stream,
+                      const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                      const int8_t *P, int32_t D, int64_t ldp,
+                      hdc_dtype compute, hdc_dims dims,
+                      uint64_t *H, int64_t ldh);
+
+/* ---------------------------------------------------------------------
+ * hdc_bundle -- class bundling (Sec. 2.1: same-class hypervectors are
+ * aggregated into one class hypervector), as the per-dimension majority:
+ *     n_k = #{i : labels[i] == k},  cnt[k][d] = #{i in class k : bit d set}
+ *     C bit d of class k = (2 * cnt[k][d] > n_k)
+ * so a tie gives +1 and an empty class is all +1.  Exact and deterministic.
+ *   H       [n][ldh] uint64 hypervectors of nbits elements each
+ *   labels  [n] int32 in [0, K) (precondition; out-of-range rows are skipped)
+ *   C       [K][ldc] uint64 output, ldc >= ceil(nbits/64)
+ *   counts  [K] int32 output n_k, may be NULL
+ *   ws      >= hdc_bundle_workspace_bytes(nbits, K) bytes
+ * ------------------------------------------------------------------- */
+size_t hdc_bundle_workspace_bytes(int32_t nbits, int32_t K);
+hdc_status hdc_bundle(void *stream,
+                      const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                      const int32_t *labels, int32_t K,
+                      uint64_t *C, int64_t ldc, int32_t *counts,
+                      void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
+ * hdc_hamming_argmin -- Hamming distance of each query hypervector to every
+ * class hypervector with reduction perforation, then argmin (Sec. 2.2
+ * Listing 1: hamming_distance, red_perf, arg_min; Sec. 4.2).
+ *     dist[i][k] = #{ d in S(perf) : bit d of Q row i != bit d of C row k }
+ * The count is used as-is (not rescaled).  argmin[i] is the lowest k with
+ * the smallest distance.  Q and C both hold >= perf.end valid bits.
+ *   Q        [n][ldq] uint64,  C [K][ldc] uint64
+ *   argmin   [n] int32 output
+ *   min_dist [n] int32 output, may be NULL
+ *   dists    [n][K] int32 output, may be NULL
+ * Supports K <= 128.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_hamming_argmin(void *stream,
+                              const uint64_t *Q, int64_t n, int64_t ldq,
+                              const uint64_t *C, int32_t K, int64_t ldc,
+                              hdc_dims perf,
+                              int32_t *argmin, int32_t *min_dist, int32_t *dists);
+
+/* ---------------------------------------------------------------------
+ * hdc_classify -- the fused inference path: encode each query over the
+ * dimensions S(dims) under `compute`, compare bit j of the query with bit
+ * S_j of each (full-D) class hypervector, argmin.  Equal, bit for bit, to
+ * hdc_encode(dims) followed by hdc_hamming_argmin over the gathered class
+ * bits, without writing the query hypervectors anywhere.
+ *   C       [K][ldc] uint64 class hypervectors over all D dimensions
+ *           (as written by hdc_bundle with nbits = D)
+ *   labels  [n] int32 output;  dists [n][K] int32 output, may be NULL
+ *   ws      >= hdc_classify_workspace_bytes(hdc_dims_count(dims), K)
+ * Supports K <= 128, F <= 1024.
+ * ------------------------------------------------------------------- */
+size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K);
+hdc_status hdc_classify(void *stream,
+                        const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                        const int8_t *P, int32_t D, int64_t ldp,
+                        hdc_dtype compute, hdc_dims dims,
+                        const uint64_t *C, int32_t K, int64_t ldc,
+                        int32_t *labels, int32_t *dists,
+                        void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
+ * hdc_eval_configs -- one persistent launch that evaluates many
+ * approximation configurations on the same queries: the inner loop of the
+ * paper's tuning system, which runs each candidate configuration and reads
+ * back its quality of service and time (Sec. 3, Sec. 4.1).  For every
+ * configuration c, the queries are classified exactly as hdc_classify with
+ * dims {cfg.start, cfg.d_trunc, cfg.stride} and compute = cfg.dtype, and
+ *     out[c].correct = #{i : label_i == truth[i]}
+ *     out[c].ticks   = sum over c's work items of device wall-clock ticks
+ * (ticks / hdc_device_clock_hz() seconds of device time; several items run
+ * concurrently, so this is busy time, not elapsed time).
+ *   cfgs   HOST array [ncfg]; read before the call returns
+ *   out    [ncfg] hdc_config_result, device memory, zeroed by the call
+ *   ws     >= hdc_eval_configs_workspace_bytes(...) with the same arguments
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t d_trunc, stride, start;
+    int32_t dtype;          /* hdc_dtype compute type */
+} hdc_config;
+
+typedef struct {
+    int32_t correct;
+    int32_t n;
+    uint64_t ticks;
+} hdc_config_result;
+
+size_t hdc_eval_configs_workspace_bytes(const hdc_config *cfgs, int32_t ncfg, int32_t K);
+hdc_status hdc_eval_configs(void *stream,
+                            const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                            const int32_t *truth,
+                            const int8_t *P, int32_t D, int64_t ldp,
+                            const uint64_t *C, int32_t K, int64_t ldc,
+                            const hdc_config *cfgs, int32_t ncfg,
+                            hdc_config_result *out,
+                            void *ws, size_t ws_bytes);
+
+/* Frequency in Hz of the device wall clock that hdc_eval_configs reads. */
+double hdc_device_clock_hz(void);
+
+/* ---------------------------------------------------------------------
+ * hdc_convert_features -- diagnostic: the value each feature takes inside
+ * the encoder under `compute` (the device conversion the kernels use),
+ * written as float: out[i][f] for f < F.  out is [n][F] float.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_convert_features(void *stream,
+                                const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                hdc_dtype compute, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

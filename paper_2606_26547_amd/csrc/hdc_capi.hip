@@ -1,0 +1,282 @@
+// C ABI of libhdc.so: argument validation and launch of the gfx950 kernels.
+// Nothing here allocates device memory; every scratch byte comes from the
+// caller's workspace.
+#include <string.h>
+
+#include "hdc_internal.h"
+
+namespace hdc {
+hipError_t launch_encode_i8(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
+hipError_t launch_encode_fp8(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
+hipError_t launch_encode_bf16(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
+hipError_t launch_encode_f32(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
+
+hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st)
+{
+    switch (compute) {
+    case C_I8: return launch_encode_i8(a, mode, tile, st);
+    case C_FP8: return launch_encode_fp8(a, mode, tile, st);
+    case C_BF16: return launch_encode_bf16(a, mode, tile, st);
+    case C_F32: return launch_encode_f32(a, mode, tile, st);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace hdc
+
+using namespace hdc;
+
+namespace {
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Feature storage type of an hdc_dtype used as x_type, or -1.
+int xtype_of(hdc_dtype t)
+{
+    switch (t) {
+    case HDC_INT8: return X_INT8;
+    case HDC_UINT8: return X_UINT8;
+    case HDC_FP32: return X_FP32;
+    default: return -1;
+    }
+}
+
+// Kernel compute type for a (feature, compute) pair, or -1 if unsupported.
+int compute_of(hdc_dtype x, hdc_dtype c)
+{
+    const bool integer = x == HDC_INT8 || x == HDC_UINT8;
+    if (integer) {
+        if (c == HDC_INT8) return C_I8;
+        if (c == HDC_BF16) return C_BF16;
+        if (c == HDC_FP8_E4M3) return C_FP8;
+        return -1;
+    }
+    if (x == HDC_FP32) {
+        if (c == HDC_FP32) return C_F32;
+        if (c == HDC_BF16) return C_BF16;
+        if (c == HDC_FP8_E4M3) return C_FP8;
+    }
+    return -1;
+}
+
+int32_t dims_count(hdc_dims d)
+{
+    if (d.stride < 1 || d.start < 0 || d.end <= d.start)
+        return 0;
+    return (int32_t)(((int64_t)d.end - d.start + d.stride - 1) / d.stride);
+}
+
+hdc_status from_hip(hipError_t e) { return e == hipSuccess ? HDC_OK : HDC_ERR_DEVICE; }
+
+// Shared checks of the feature / projection operands.
+hdc_status check_encode_operands(const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                 const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
+                                 int *ct, int *xt)
+{
+    if (n < 0 || F <= 0 || D <= 0)
+        return HDC_ERR_INVALID;
+    *xt = xtype_of(x_type);
+    *ct = compute_of(x_type, compute);
+    if (*xt < 0)
+        return HDC_ERR_INVALID;
+    if (*ct < 0)
+        return HDC_ERR_UNSUPPORTED;
+    if (F > (*xt == X_FP32 ? kMaxFFloat : kMaxF))
+        return HDC_ERR_UNSUPPORTED;
+    if (dims.stride < 1 || dims.start < 0 || dims.end <= dims.start || dims.end > D)
+        return HDC_ERR_INVALID;
+    if (!P || ldp < round_up(F, 64) || ldp % 16 || !aligned(P, 16))
+        return HDC_ERR_INVALID;
+    if (n > 0 && (!X || ldx < round_up(F, 64) || ldx % 16 || !aligned(X, 16)))
+        return HDC_ERR_INVALID;
+    return HDC_OK;
+}
+
+EncodeArgs make_args(const void *X, int xt, int64_t n, int32_t F, int64_t ldx, const int8_t *P, int64_t ldp,
+                     hdc_dims dims)
+{
+    EncodeArgs a;
+    memset(&a, 0, sizeof a);
+    a.X = X;
+    a.x_type = xt;
+    a.n = n;
+    a.F = F;
+    a.ldx = ldx;
+    a.P = P;
+    a.ldp = ldp;
+    a.s0 = dims.start;
+    a.stride = dims.stride;
+    a.nd = dims_count(dims);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hdc_status_string(hdc_status s)
+{
+    switch (s) {
+    case HDC_OK: return "HDC_OK";
+    case HDC_ERR_INVALID: return "HDC_ERR_INVALID: invalid argument";
+    case HDC_ERR_UNSUPPORTED: return "HDC_ERR_UNSUPPORTED: type pair or size not supported";
+    case HDC_ERR_WORKSPACE: return "HDC_ERR_WORKSPACE: workspace too small or misaligned";
+    case HDC_ERR_DEVICE: return "HDC_ERR_DEVICE: kernel launch failed";
+    }
+    return "unknown hdc_status";
+}
+
+int32_t hdc_dims_count(hdc_dims dims) { return dims_count(dims); }
+
+hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                      const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims, uint64_t *H,
+                      int64_t ldh)
+{
+    int ct, xt;
+    hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
+    if (s != HDC_OK)
+        return s;
+    const int32_t nd = dims_count(dims);
+    if (n > 0 && (!H || ldh < (nd + 63) / 64 || !aligned(H, 8)))
+        return HDC_ERR_INVALID;
+    if (n == 0)
+        return HDC_OK;
+    EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
+    a.H32 = (uint32_t *)H;
+    a.ldh32 = 2 * ldh;
+    return from_hip(launch_encode(a, ct, M_ENCODE, Tile{0}, (hipStream_t)stream));
+}
+
+size_t hdc_bundle_workspace_bytes(int32_t nbits, int32_t K)
+{
+    if (nbits <= 0 || K <= 0)
+        return 0;
+    return (size_t)4 * K * ((size_t)nbits + 1);
+}
+
+hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                      const int32_t *labels, int32_t K, uint64_t *C, int64_t ldc, int32_t *counts, void *ws,
+                      size_t ws_bytes)
+{
+    if (n < 0 || nbits <= 0 || K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK)
+        return HDC_ERR_UNSUPPORTED;
+    const int64_t W = (nbits + 63) / 64;
+    if (!C || ldc < W || (n > 0 && (!H || !labels || ldh < W)))
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_bundle_workspace_bytes(nbits, K) || !aligned(ws, 4))
+        return HDC_ERR_WORKSPACE;
+    return from_hip(launch_bundle(H, n, nbits, ldh, labels, K, C, ldc, counts, (int32_t *)ws,
+                                  (hipStream_t)stream));
+}
+
+hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C,
+                              int32_t K, int64_t ldc, hdc_dims perf, int32_t *argmin, int32_t *min_dist,
+                              int32_t *dists)
+{
+    if (n < 0 || K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK || perf.end > 65536)
+        return HDC_ERR_UNSUPPORTED;
+    if (perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)
+        return HDC_ERR_INVALID;
+    const int64_t W = (perf.end + 63) / 64;
+    if (!C || ldc < W)
+        return HDC_ERR_INVALID;
+    if (n == 0)
+        return HDC_OK;
+    if (!Q || ldq < W || !argmin)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_hamming(Q, n, ldq, C, K, ldc, perf.start, perf.end, perf.stride, argmin, min_dist,
+                                   dists, (hipStream_t)stream));
+}
+
+size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
+{
+    if (n_dims <= 0 || K <= 0 || K > kMaxK)
+        return 0;
+    return class_table_bytes(n_dims, K) + 4 * 32 * 4;
+}
+
+hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                        const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
+                        const uint64_t *C, int32_t K, int64_t ldc, int32_t *labels, int32_t *dists, void *ws,
+                        size_t ws_bytes)
+{
+    int ct, xt;
+    hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
+    if (s != HDC_OK)
+        return s;
+    if (K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK)
+        return HDC_ERR_UNSUPPORTED;
+    if (!C || ldc < (dims.end + 63) / 64)
+        return HDC_ERR_INVALID;
+    if (n > 0 && !labels)
+        return HDC_ERR_INVALID;
+    const int32_t nd = dims_count(dims);
+    if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int8_t *tab = (int8_t *)ws;
+    int32_t *cpop = (int32_t *)((uint8_t *)ws + class_table_bytes(nd, K));
+    hipError_t e = launch_class_table(C, K, ldc, dims.start, dims.stride, nd, tab, cpop, st);
+    if (e != hipSuccess)
+        return HDC_ERR_DEVICE;
+    EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
+    a.ctab = tab;
+    a.cpop = cpop;
+    a.K = K;
+    a.labels = labels;
+    a.dists = dists;
+    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{0}, st));
+}
+
+size_t hdc_eval_configs_workspace_bytes(const hdc_config *cfgs, int32_t ncfg, int32_t K)
+{
+    (void)cfgs;
+    (void)ncfg;
+    (void)K;
+    return 0;
+}
+
+hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                            const int32_t *truth, const int8_t *P, int32_t D, int64_t ldp, const uint64_t *C,
+                            int32_t K, int64_t ldc, const hdc_config *cfgs, int32_t ncfg,
+                            hdc_config_result *out, void *ws, size_t ws_bytes)
+{
+    (void)stream; (void)X; (void)x_type; (void)n; (void)F; (void)ldx; (void)truth; (void)P; (void)D;
+    (void)ldp; (void)C; (void)K; (void)ldc; (void)cfgs; (void)ncfg; (void)out; (void)ws; (void)ws_bytes;
+    return HDC_ERR_UNSUPPORTED;
+}
+
+double hdc_device_clock_hz(void)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0.0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return 0.0;
+    return (double)khz * 1000.0;
+}
+
+hdc_status hdc_convert_features(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F,
+                                int64_t ldx, hdc_dtype compute, float *out)
+{
+    const int xt = xtype_of(x_type), ct = compute_of(x_type, compute);
+    if (n < 0 || F <= 0 || xt < 0)
+        return HDC_ERR_INVALID;
+    if (ct < 0)
+        return HDC_ERR_UNSUPPORTED;
+    if (n == 0)
+        return HDC_OK;
+    if (!X || !out || ldx < F)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_convert(X, xt, n, F, ldx, ct, out, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Kernel entry points and launch dispatch of the encoder for one compute
+// type.  Each hdc_encode_<type>.hip defines HDC_CT and includes this file,
+// so the instantiations of the four compute types compile in parallel.
+#pragma once
+
+#include "hdc_encoder.h"
+
+namespace hdc {
+
+template <int CT, int XF, int QT, int KS, int KT, int MODE>
+__global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
+{
+    typedef Encoder<CT, XF, QT, KS, KT, MODE> E;
+    __shared__ __align__(16) uint8_t smem[E::LDS];
+    const int64_t qblock = (int64_t)blockIdx.x * E::QPB;
+    v16i dacc[KT][QT];
+    E::run(a, smem, qblock, dacc);
+    if constexpr (MODE == M_CLASSIFY) {
+        int32_t lab[QT];
+        E::finish(a, qblock, dacc, lab);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt) {
+            const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
+            if (lane < 32 && q < a.n)
+                a.labels[q] = lab[qt];
+        }
+    }
+}
+
+template <int CT, int XF, int QT, int KS, int KT, int MODE>
+static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
+{
+    typedef Encoder<CT, XF, QT, KS, KT, MODE> E;
+    const int64_t blocks = (a.n + E::QPB - 1) / E::QPB;
+    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Largest QT whose query registers fit comfortably beside the accumulators.
+template <int CT, int KS> struct QtMax {
+    static constexpr int value = (KS * Tr<CT>::DW <= 80 && CT != C_BF16) ? 2 : 1;
+};
+
+template <int CT, int XF, int KS>
+static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStream_t st)
+{
+    constexpr int QM = QtMax<CT, KS>::value;
+    const int qt = (tile.qt == 1 || QM == 1) ? 1 : 2;
+    if (mode == M_ENCODE) {
+        if (qt == 2)
+            return launch_one<CT, XF, QM, KS, 1, M_ENCODE>(a, st);
+        return launch_one<CT, XF, 1, KS, 1, M_ENCODE>(a, st);
+    }
+    const int kt = class_tiles(a.K);
+    if (kt == 1) {
+        if (qt == 2)
+            return launch_one<CT, XF, QM, KS, 1, M_CLASSIFY>(a, st);
+        return launch_one<CT, XF, 1, KS, 1, M_CLASSIFY>(a, st);
+    }
+    if (kt == 2) {
+        if (qt == 2)
+            return launch_one<CT, XF, QM, KS, 2, M_CLASSIFY>(a, st);
+        return launch_one<CT, XF, 1, KS, 2, M_CLASSIFY>(a, st);
+    }
+    return launch_one<CT, XF, 1, KS, 4, M_CLASSIFY>(a, st);
+}
+
+// Feature-count buckets: the smallest compiled width >= F is used.
+template <int CT>
+static hipError_t launch_encode_ct(const EncodeArgs &a, int mode, Tile tile, hipStream_t st)
+{
+    constexpr int KSTEP = Tr<CT>::KSTEP;
+    const int F = a.F;
+    if (a.x_type == X_FP32) {
+        if constexpr (CT == C_I8) {
+            return hipErrorInvalidValue;
+        } else {
+            if (F <= 64) return launch_bucket<CT, 1, 64 / KSTEP>(a, mode, tile, st);
+            if (F <= 128) return launch_bucket<CT, 1, 128 / KSTEP>(a, mode, tile, st);
+            if (F <= 256) return launch_bucket<CT, 1, 256 / KSTEP>(a, mode, tile, st);
+            return hipErrorInvalidValue;
+        }
+    }
+    if constexpr (CT == C_F32) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int K1 = 64 / KSTEP > 0 ? 64 / KSTEP : 1;
+        if (F <= 64) return launch_bucket<CT, 0, K1>(a, mode, tile, st);
+        if (F <= 128) return launch_bucket<CT, 0, 128 / KSTEP>(a, mode, tile, st);
+        if (F <= 256) return launch_bucket<CT, 0, 256 / KSTEP>(a, mode, tile, st);
+        if (F <= 512) return launch_bucket<CT, 0, 512 / KSTEP>(a, mode, tile, st);
+        if (F <= 640) return launch_bucket<CT, 0, 640 / KSTEP>(a, mode, tile, st);
+        if (F <= 832) return launch_bucket<CT, 0, 832 / KSTEP>(a, mode, tile, st);
+        if (F <= 1024) return launch_bucket<CT, 0, 1024 / KSTEP>(a, mode, tile, st);
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hdc

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP kernel sources and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hdc.h"
+
+namespace hdc {
+
+// Encoding compute type of a kernel instantiation.
+enum Compute : int { C_I8 = 0, C_BF16 = 1, C_FP8 = 2, C_F32 = 3 };
+
+// Feature storage type.
+enum XType : int { X_INT8 = 0, X_UINT8 = 1, X_FP32 = 2 };
+
+// Operands of one encode / classify launch.  Dimension j of the launch is
+// dimension s0 + j*stride of the projection, for j < nd.
+struct EncodeArgs {
+    const void *X;
+    int x_type;            // XType
+    int64_t n;
+    int32_t F;
+    int64_t ldx;           // elements
+    const int8_t *P;
+    int64_t ldp;           // bytes (= elements)
+    int32_t s0, stride, nd;
+    // encode mode: packed output, viewed as uint32 halves of the words
+    uint32_t *H32;
+    int64_t ldh32;         // row pitch in uint32
+    // classify mode
+    const int8_t *ctab;    // class operand table, [nchunk][KT][64 lanes][16 B]
+    const int32_t *cpop;   // [KT*32] count of -1 elements of each class over S
+    int32_t K;
+    int32_t *labels;       // [n]
+    int32_t *dists;        // [n][K] or null
+};
+
+// Mode of the encode kernel.
+enum Mode : int { M_ENCODE = 0, M_CLASSIFY = 1 };
+
+// Kernel shape choice for one launch (queries per wave in 32-query tiles).
+struct Tile {
+    int qt;                // 1 or 2
+};
+
+constexpr int kDimChunk = 32;       // dimensions per MFMA row tile / LDS chunk
+constexpr int kWaves = 4;           // waves per workgroup of the encoder
+constexpr int kMaxF = 1024;
+constexpr int kMaxFFloat = 256;
+constexpr int kMaxK = 128;
+
+inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
+inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
+inline size_t class_table_bytes(int nd, int K) { return (size_t)chunks(nd) * class_tiles(K) * 1024; }
+
+hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st);
+hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,
+                              int8_t *tab, int32_t *cpop, hipStream_t st);
+hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K,
+                          int64_t ldc, int start, int end, int stride, int32_t *argmin,
+                          int32_t *min_dist, int32_t *dists, hipStream_t st);
+hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
+                         int K, uint64_t *C, int64_t ldc, int32_t *counts, int32_t *ws_cnt,
+                         hipStream_t st);
+hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute,
+                          float *out, hipStream_t st);
+
+// Persistent configuration sweep.
+struct SweepArgs {
+    const void *X;
+    int x_type;
+    int64_t n;
+    int32_t F;
+    int64_t ldx;
+    const int32_t *truth;
+    const int8_t *P;
+    int64_t ldp;
+    int32_t D;
+    const uint64_t *C;
+    int32_t K;
+    int64_t ldc;
+    const hdc_config *cfgs;   // device
+    int32_t ncfg;
+    hdc_config_result *out;   // device
+    uint8_t *ws;
+    size_t ws_bytes;
+};
+size_t sweep_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
+
+}  // namespace hdc

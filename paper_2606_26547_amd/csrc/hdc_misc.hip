@@ -1,0 +1,295 @@
+// Hamming-distance argmin over packed hypervectors, majority bundling,
+// the class-operand tables of the fused classifier and the feature
+// conversion diagnostic.
+#include <limits.h>
+
+#include "hdc_device.h"
+
+namespace hdc {
+
+// ---------------------------------------------------------------------------
+// Class operand table for the fused classifier.  For chunk c (dimensions
+// S_{32c .. 32c+31}), class tile kt and lane l, the 16 bytes are the +-1
+// values of class kt*32 + l%32 at the dimensions that the encoder's sign
+// bytes occupy in lane l: byte b <-> dimension 32c + 8*(b/4) + 4*(l/32) + b%4.
+// Classes >= K and dimensions >= nd are 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_class_table(const uint64_t *__restrict__ C, int K, int64_t ldc,
+                                                     int s0, int stride, int nd, int KT, int64_t total,
+                                                     int8_t *__restrict__ tab)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total)
+        return;
+    const int lane = (int)(idx & 63);
+    const int kt = (int)((idx >> 6) % KT);
+    const int64_t c = (idx >> 6) / KT;
+    const int k = kt * 32 + (lane & 31), g = lane >> 5;
+    uint32_t out[4] = {0, 0, 0, 0};
+    if (k < K) {
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const int64_t dl = c * kDimChunk + 8 * (b >> 2) + 4 * g + (b & 3);
+            if (dl < nd) {
+                const int64_t d = s0 + dl * stride;
+                const uint32_t bit = (uint32_t)(C[k * ldc + (d >> 6)] >> (d & 63)) & 1u;
+                out[b >> 2] |= (bit ? 0xffu : 0x01u) << (8 * (b & 3));
+            }
+        }
+    }
+    *(uint4 *)(tab + idx * 16) = make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+// popc[k] = number of -1 elements of class k over S (0 for k >= K).
+__global__ __launch_bounds__(256) void k_class_popc(const uint64_t *__restrict__ C, int K, int64_t ldc,
+                                                    int s0, int stride, int nd, int32_t *__restrict__ popc)
+{
+    __shared__ int part[256];
+    const int k = blockIdx.x;
+    int s = 0;
+    if (k < K)
+        for (int64_t dl = threadIdx.x; dl < nd; dl += 256) {
+            const int64_t d = s0 + dl * stride;
+            s += (int)((C[k * ldc + (d >> 6)] >> (d & 63)) & 1u);
+        }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        popc[k] = part[0];
+}
+
+hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,
+                              int8_t *tab, int32_t *cpop, hipStream_t st)
+{
+    const int KT = class_tiles(K);
+    const int64_t total = chunks(nd) * KT * 64;
+    hipLaunchKernelGGL(k_class_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc,
+                       s0, stride, nd, KT, total, tab);
+    hipLaunchKernelGGL(k_class_popc, dim3(KT * 32), dim3(256), 0, st, C, K, ldc, s0, stride, nd, cpop);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Hamming distance + argmin over packed hypervectors (unfused path).  One
+// query per lane; the wave's 64 query rows are staged through LDS a window
+// of 16 words at a time with coalesced loads; the class words are uniform
+// across the wave; the perforation mask of every word is precomputed per
+// workgroup.  Distances accumulate in KB registers per lane.
+// ---------------------------------------------------------------------------
+constexpr int kHamWin = 16;
+constexpr int kHamMaxWords = 1024;   // hypervectors up to 65536 bits
+
+template <int KB>
+__global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq,
+                                                 const uint64_t *__restrict__ C, int K, int64_t ldc,
+                                                 int start, int end, int stride, int32_t *__restrict__ argmin,
+                                                 int32_t *__restrict__ min_dist, int32_t *__restrict__ dists)
+{
+    __shared__ uint64_t qs[kWaves][64][kHamWin + 1];
+    __shared__ uint64_t msk[kHamMaxWords];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int w_lo = start >> 6, w_hi = (end + 63) >> 6;
+    for (int w = w_lo + t; w < w_hi; w += 256) {
+        uint64_t m = 0;
+        const int64_t lo = (int64_t)w * 64 > start ? (int64_t)w * 64 : start;
+        const int64_t hi = (int64_t)w * 64 + 64 < end ? (int64_t)w * 64 + 64 : end;
+        int64_t d = start + ((lo - start + stride - 1) / stride) * (int64_t)stride;
+        for (; d < hi; d += stride)
+            m |= 1ull << (d & 63);
+        msk[w - w_lo] = m;
+    }
+    __syncthreads();
+
+    const int64_t rbase = (int64_t)blockIdx.x * 256 + wave * 64;
+    int dist[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        dist[k] = 0;
+
+    for (int w0 = w_lo; w0 < w_hi; w0 += kHamWin) {
+        // stage 64 rows x 16 words: 16 lanes per row, 4 rows per pass
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            const int r = 4 * p + (lane >> 4), ww = lane & 15;
+            const int64_t row = rbase + r;
+            uint64_t v = 0;
+            if (row < n && w0 + ww < w_hi)
+                v = Q[row * ldq + w0 + ww];
+            qs[wave][r][ww] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int nw = (w_hi - w0) < kHamWin ? (w_hi - w0) : kHamWin;
+        for (int ww = 0; ww < nw; ++ww) {
+            const uint64_t q = qs[wave][lane][ww];
+            const uint64_t m = msk[w0 + ww - w_lo];
+            const uint64_t *cw = C + w0 + ww;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (k < K)
+                    dist[k] += __popcll((q ^ cw[(int64_t)k * ldc]) & m);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    const int64_t row = rbase + lane;
+    if (row >= n)
+        return;
+    int bd = INT_MAX, bk = 0;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (k < K) {
+            if (dist[k] < bd) { bd = dist[k]; bk = k; }
+            if (dists)
+                dists[row * K + k] = dist[k];
+        }
+    argmin[row] = bk;
+    if (min_dist)
+        min_dist[row] = bd;
+}
+
+hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
+                          int start, int end, int stride, int32_t *argmin, int32_t *min_dist,
+                          int32_t *dists, hipStream_t st)
+{
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (K <= 8)
+        hipLaunchKernelGGL(k_hamming<8>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
+    else if (K <= 16)
+        hipLaunchKernelGGL(k_hamming<16>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
+    else if (K <= 32)
+        hipLaunchKernelGGL(k_hamming<32>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
+    else if (K <= 64)
+        hipLaunchKernelGGL(k_hamming<64>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
+    else
+        hipLaunchKernelGGL(k_hamming<128>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Majority bundling.  Pass 1 counts, per (class, dimension), the members
+// whose bit is set, with one workgroup per (word column, row block) and
+// integer atomics (order-free, hence deterministic); pass 2 thresholds.
+// ws holds cnt[K][nbits] then nk[K] (int32), zeroed first.
+// ---------------------------------------------------------------------------
+constexpr int kBundleRows = 2048;
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *__restrict__ p, int64_t count, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_bundle_count(const uint64_t *__restrict__ H, int64_t n, int nbits,
+                                                      int64_t ldh, const int32_t *__restrict__ labels, int K,
+                                                      int W, int32_t *__restrict__ gcnt, int32_t *__restrict__ gnk)
+{
+    __shared__ int lcnt[kMaxK * 64];
+    __shared__ int lnk[kMaxK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int w = blockIdx.x % W;
+    const int64_t r0 = (int64_t)(blockIdx.x / W) * kBundleRows;
+    for (int i = t; i < K * 64; i += 256)
+        lcnt[i] = 0;
+    if (t < K)
+        lnk[t] = 0;
+    __syncthreads();
+    const int64_t r1 = r0 + kBundleRows < n ? r0 + kBundleRows : n;
+    for (int64_t i = r0 + wave; i < r1; i += kWaves) {
+        const int k = labels[i];
+        if (k < 0 || k >= K)
+            continue;
+        const uint64_t x = H[i * ldh + w];
+        if ((x >> lane) & 1ull)
+            atomicAdd(&lcnt[k * 64 + lane], 1);
+        if (w == 0 && lane == 0)
+            atomicAdd(&lnk[k], 1);
+    }
+    __syncthreads();
+    for (int i = t; i < K * 64; i += 256) {
+        const int k = i >> 6, j = i & 63;
+        const int d = w * 64 + j;
+        if (d < nbits && lcnt[i])
+            atomicAdd(&gcnt[(int64_t)k * nbits + d], lcnt[i]);
+    }
+    if (w == 0 && t < K && lnk[t])
+        atomicAdd(&gnk[t], lnk[t]);
+}
+
+__global__ __launch_bounds__(256) void k_bundle_final(const int32_t *__restrict__ gcnt,
+                                                      const int32_t *__restrict__ gnk, int K, int nbits, int W,
+                                                      uint64_t *__restrict__ C, int64_t ldc,
+                                                      int32_t *__restrict__ counts)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)K * W)
+        return;
+    const int k = (int)(idx / W), w = (int)(idx % W);
+    const int nk = gnk[k];
+    uint64_t word = 0;
+    for (int j = 0; j < 64; ++j) {
+        const int d = w * 64 + j;
+        if (d < nbits && 2 * gcnt[(int64_t)k * nbits + d] > nk)
+            word |= 1ull << j;
+    }
+    C[(int64_t)k * ldc + w] = word;
+    if (w == 0 && counts)
+        counts[k] = nk;
+}
+
+hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels, int K,
+                         uint64_t *C, int64_t ldc, int32_t *counts, int32_t *ws, hipStream_t st)
+{
+    const int W = (nbits + 63) / 64;
+    const int64_t cells = (int64_t)K * nbits + K;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((cells + 255) / 256 < 4096 ? (cells + 255) / 256 : 4096)),
+                       dim3(256), 0, st, ws, cells, 0);
+    const int64_t rb = (n + kBundleRows - 1) / kBundleRows;
+    if (rb > 0)
+        hipLaunchKernelGGL(k_bundle_count, dim3((unsigned)(rb * W)), dim3(256), 0, st, H, n, nbits, ldh, labels,
+                           K, W, ws, ws + (int64_t)K * nbits);
+    hipLaunchKernelGGL(k_bundle_final, dim3((unsigned)(((int64_t)K * W + 255) / 256)), dim3(256), 0, st, ws,
+                       ws + (int64_t)K * nbits, K, nbits, W, C, ldc, counts);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Feature conversion diagnostic: the value of each feature as the encoder's
+// X loader converts it (same helpers).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_convert(const void *__restrict__ X, int x_type, int64_t n, int F,
+                                                 int64_t ldx, int compute, float *__restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n * F)
+        return;
+    const int64_t i = idx / F;
+    const int f = (int)(idx % F);
+    float v;
+    if (x_type == X_FP32)
+        v = ((const float *)X)[i * ldx + f];
+    else {
+        const uint32_t b = ((const uint8_t *)X)[i * ldx + f];
+        v = byte_value(b, 0, x_type == X_INT8);
+    }
+    if (compute == C_FP8)
+        v = __builtin_amdgcn_cvt_f32_fp8((int)fp8x4(v, 0.f, 0.f, 0.f), 0);
+    else if (compute == C_BF16)
+        v = __uint_as_float(bf16x2(v, 0.f) << 16);
+    out[idx] = v;
+}
+
+hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute, float *out,
+                          hipStream_t st)
+{
+    const int64_t total = n * F;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, x_type, n, F, ldx,
+                       compute, out);
+    return hipGetLastError();
+}
+
+}  // namespace hdc

@@ -1,0 +1,230 @@
+"""Thin Python binding of libhdc.so (include/hdc.h).
+
+Argument marshalling only: torch supplies device memory and the current
+stream; every step of the hot path runs in the library's HIP kernels.  The
+library is loaded from the package directory; if it is missing this module
+raises at import time, so no call can silently fall back to another
+implementation.
+
+Layout helpers pad features and projections to the leading dimensions the
+kernels require (a multiple of 64 elements); the pad columns are ignored by
+the kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhdc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhdc.so is not built (%s); run __graft_entry__.build() or "
+                      "python paper_2606_26547_amd/build.py" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+INT8, UINT8, BF16, FP8_E4M3, FP32 = 0, 1, 2, 3, 4
+DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32}
+STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
+          4: "HDC_ERR_DEVICE"}
+EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
+           "hdc_bundle", "hdc_hamming_argmin", "hdc_classify_workspace_bytes", "hdc_classify",
+           "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
+           "hdc_convert_features"]
+
+
+class Dims(C.Structure):
+    _fields_ = [("start", C.c_int32), ("end", C.c_int32), ("stride", C.c_int32)]
+
+
+class Config(C.Structure):
+    _fields_ = [("d_trunc", C.c_int32), ("stride", C.c_int32), ("start", C.c_int32), ("dtype", C.c_int32)]
+
+
+class ConfigResult(C.Structure):
+    _fields_ = [("correct", C.c_int32), ("n", C.c_int32), ("ticks", C.c_uint64)]
+
+
+class HDCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s: %s" % (where, _lib.hdc_status_string(code).decode()))
+        self.code = code
+
+
+_p, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_lib.hdc_status_string.restype = C.c_char_p
+_lib.hdc_status_string.argtypes = [C.c_int]
+_lib.hdc_dims_count.restype = _i32
+_lib.hdc_dims_count.argtypes = [Dims]
+_lib.hdc_encode.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i64]
+_lib.hdc_bundle_workspace_bytes.restype = _sz
+_lib.hdc_bundle_workspace_bytes.argtypes = [_i32, _i32]
+_lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
+_lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, _p, _p, _p]
+_lib.hdc_classify_workspace_bytes.restype = _sz
+_lib.hdc_classify_workspace_bytes.argtypes = [_i32, _i32]
+_lib.hdc_classify.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i32,
+                              _i64, _p, _p, _p, _sz]
+_lib.hdc_eval_configs_workspace_bytes.restype = _sz
+_lib.hdc_eval_configs_workspace_bytes.argtypes = [_p, _i32, _i32]
+_lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
+                                  _p, _i32, _p, _p, _sz]
+_lib.hdc_device_clock_hz.restype = C.c_double
+_lib.hdc_device_clock_hz.argtypes = []
+_lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int, _p]
+for _name in EXPORTS:
+    assert hasattr(_lib, _name)
+
+
+def lib():
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise HDCError(code, where)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _xtype(t: torch.Tensor) -> int:
+    return {torch.int8: INT8, torch.uint8: UINT8, torch.float32: FP32}[t.dtype]
+
+
+def dims_count(start: int, end: int, stride: int) -> int:
+    return int(_lib.hdc_dims_count(Dims(start, end, stride)))
+
+
+def words(nbits: int) -> int:
+    return max(1, (nbits + 63) // 64)
+
+
+def pad_cols(a, device="cuda", mult: int = 64) -> torch.Tensor:
+    """Copy a 2-D array into a zero-padded device tensor whose row pitch is a
+    multiple of ``mult`` elements (the layout the kernels read)."""
+    t = torch.as_tensor(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a
+    n, F = t.shape
+    ld = max(mult, (F + mult - 1) // mult * mult)
+    out = torch.zeros((n, ld), dtype=t.dtype, device=device)
+    out[:, :F] = t.to(device)
+    return out
+
+
+class Model:
+    """Device-resident projection (and, once trained, class hypervectors)."""
+
+    def __init__(self, P, K: int, device="cuda"):
+        P = np.asarray(P) if not isinstance(P, torch.Tensor) else P
+        self.D, self.F = int(P.shape[0]), int(P.shape[1])
+        self.K = int(K)
+        self.P = pad_cols(P, device)
+        self.C = None
+        self.counts = None
+
+
+def encode(X: torch.Tensor, F: int, P: torch.Tensor, D: int, compute="int8", start=0, end=None, stride=1,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """hdc_encode: packed sign bits [n][words(|S|)] (uint64 viewed as int64)."""
+    end = D if end is None else end
+    nd = dims_count(start, end, stride)
+    n = X.shape[0]
+    if out is None:
+        out = torch.zeros((n, words(nd)), dtype=torch.int64, device=X.device)
+    _check(_lib.hdc_encode(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
+                           DTYPE[compute], Dims(start, end, stride), _ptr(out), out.shape[1]), "hdc_encode")
+    return out
+
+
+def bundle(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.Tensor | None = None):
+    """hdc_bundle: class hypervectors [K][words(nbits)] and class sizes."""
+    W = words(nbits)
+    Cw = torch.zeros((K, W), dtype=torch.int64, device=H.device)
+    counts = torch.zeros(K, dtype=torch.int32, device=H.device)
+    need = int(_lib.hdc_bundle_workspace_bytes(nbits, K))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=H.device)
+    _check(_lib.hdc_bundle(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(Cw),
+                           Cw.shape[1], _ptr(counts), _ptr(ws), ws.numel()), "hdc_bundle")
+    return Cw, counts
+
+
+def hamming_argmin(Q: torch.Tensor, Cw: torch.Tensor, start: int, end: int, stride: int = 1,
+                   with_min=False, with_dists=False):
+    n, K = Q.shape[0], Cw.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device=Q.device)
+    mn = torch.empty(n, dtype=torch.int32, device=Q.device) if with_min else None
+    dists = torch.empty((n, K), dtype=torch.int32, device=Q.device) if with_dists else None
+    _check(_lib.hdc_hamming_argmin(_stream(), _ptr(Q), n, Q.shape[1], _ptr(Cw), K, Cw.shape[1],
+                                   Dims(start, end, stride), _ptr(lab), _ptr(mn), _ptr(dists)),
+           "hdc_hamming_argmin")
+    return lab, mn, dists
+
+
+def classify_workspace_bytes(n_dims: int, K: int) -> int:
+    return int(_lib.hdc_classify_workspace_bytes(n_dims, K))
+
+
+def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, compute="int8", start=0,
+             d_trunc=None, stride=1, with_dists=False, ws: torch.Tensor | None = None,
+             labels: torch.Tensor | None = None):
+    """hdc_classify: fused encode + Hamming + argmin under one configuration."""
+    d_trunc = D if d_trunc is None else d_trunc
+    n, K = X.shape[0], Cw.shape[0]
+    nd = dims_count(start, d_trunc, stride)
+    need = classify_workspace_bytes(nd, K)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    dists = torch.empty((n, K), dtype=torch.int32, device=X.device) if with_dists else None
+    _check(_lib.hdc_classify(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
+                             DTYPE[compute], Dims(start, d_trunc, stride), _ptr(Cw), K, Cw.shape[1],
+                             _ptr(labels), _ptr(dists), _ptr(ws), ws.numel()), "hdc_classify")
+    return (labels, dists) if with_dists else labels
+
+
+def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:
+    out = torch.empty((X.shape[0], F), dtype=torch.float32, device=X.device)
+    _check(_lib.hdc_convert_features(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1],
+                                     DTYPE[compute], _ptr(out)), "hdc_convert_features")
+    return out
+
+
+def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
+                 cfgs, ws: torch.Tensor | None = None):
+    """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype-name)], one
+    persistent launch; returns (correct[ncfg], ticks[ncfg]) device tensors."""
+    arr = np.array([[d, k, s, DTYPE[t] if isinstance(t, str) else int(t)] for (d, k, s, t) in cfgs],
+                   dtype=np.int32).reshape(-1, 4)
+    host = (Config * len(arr))(*[Config(*map(int, r)) for r in arr])
+    dev = torch.from_numpy(arr).to(X.device)
+    K = Cw.shape[0]
+    need = int(_lib.hdc_eval_configs_workspace_bytes(host, len(arr), K))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
+    out = torch.zeros((len(arr), 4), dtype=torch.int32, device=X.device)   # {correct, n, ticks(u64)}
+    _check(_lib.hdc_eval_configs(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1], _ptr(truth),
+                                 _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], _ptr(dev), len(arr),
+                                 _ptr(out), _ptr(ws), ws.numel()), "hdc_eval_configs")
+    correct = out[:, 0]
+    ticks = out[:, 2:4].contiguous().view(torch.int64).view(-1)
+    return correct, ticks
+
+
+def device_clock_hz() -> float:
+    return float(_lib.hdc_device_clock_hz())
+
+
+def to_u64(t: torch.Tensor) -> np.ndarray:
+    """Device int64 word tensor -> host uint64 numpy array."""
+    return t.cpu().numpy().view(np.uint64)

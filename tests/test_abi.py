@@ -1,0 +1,68 @@
+"""The C ABI library loads and exports every entry point include/hdc.h
+declares; argument validation (which runs before any device work) rejects
+bad calls.  No compute call is made here, so no GPU is needed."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hdc.h")
+LIB = os.path.join(ROOT, "paper_2606_26547_amd", "libhdc.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hdc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2606_26547_amd.build import build
+        build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ["hdc_encode", "hdc_bundle", "hdc_hamming_argmin", "hdc_eval_configs", "hdc_classify"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+class Dims(C.Structure):
+    _fields_ = [("start", C.c_int32), ("end", C.c_int32), ("stride", C.c_int32)]
+
+
+def test_validation_without_device(lib):
+    lib.hdc_status_string.restype = C.c_char_p
+    assert lib.hdc_status_string(0) == b"HDC_OK"
+    lib.hdc_dims_count.argtypes = [Dims]
+    assert lib.hdc_dims_count(Dims(0, 10240, 1)) == 10240
+    assert lib.hdc_dims_count(Dims(3, 100, 7)) == 14
+    assert lib.hdc_dims_count(Dims(5, 5, 1)) == 0
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_encode.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, p, i64]
+    fake = C.c_void_p(1 << 20)       # never dereferenced: validation fails first
+    # negative n, F <= 0, end > D, stride < 1, unsupported pair, unaligned ld
+    assert lib.hdc_encode(None, fake, 0, -1, 8, 64, fake, 64, 64, 0, Dims(0, 64, 1), fake, 1) == 1
+    assert lib.hdc_encode(None, fake, 0, 1, 0, 64, fake, 64, 64, 0, Dims(0, 64, 1), fake, 1) == 1
+    assert lib.hdc_encode(None, fake, 0, 1, 8, 64, fake, 64, 64, 0, Dims(0, 65, 1), fake, 1) == 1
+    assert lib.hdc_encode(None, fake, 0, 1, 8, 64, fake, 64, 64, 0, Dims(0, 64, 0), fake, 1) == 1
+    assert lib.hdc_encode(None, fake, 4, 1, 8, 64, fake, 64, 64, 0, Dims(0, 64, 1), fake, 1) == 2
+    assert lib.hdc_encode(None, fake, 0, 1, 8, 40, fake, 64, 64, 0, Dims(0, 64, 1), fake, 1) == 1
+    assert lib.hdc_encode(None, fake, 0, 1, 2000, 2048, fake, 64, 2048, 0, Dims(0, 64, 1), fake, 1) == 2
+    # n == 0 is a no-op
+    assert lib.hdc_encode(None, None, 0, 0, 8, 64, fake, 64, 64, 0, Dims(0, 64, 1), None, 1) == 0
+    lib.hdc_classify_workspace_bytes.restype = C.c_size_t
+    assert lib.hdc_classify_workspace_bytes(10240, 26) == 320 * 1024 + 512
+    assert lib.hdc_classify_workspace_bytes(10240, 200) == 0
+    lib.hdc_bundle_workspace_bytes.restype = C.c_size_t
+    assert lib.hdc_bundle_workspace_bytes(10240, 26) == 4 * 26 * 10241

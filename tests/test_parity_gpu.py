@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, on
+the same seeded inputs.  Integer results (packed hypervectors, bundles,
+distances, argmins) must match bit for bit; the fp32-feature encodings must
+agree in sign wherever |y| exceeds the floating-point summation band."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2606_26547_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hdc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_26547_amd import hdc as H
+    return H
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def words_np(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def np_dtype(x_type):
+    return {"int8": np.int8, "uint8": np.uint8, "fp32": np.float32}[x_type]
+
+
+ENC_CASES = [
+    # n, F, D, x_type, compute, (start, end, stride)
+    (1, 1, 64, "int8", "int8", None),
+    (63, 63, 96, "int8", "int8", None),
+    (65, 617, 640, "int8", "int8", None),
+    (300, 617, 2048, "int8", "int8", (0, 1000, 1)),
+    (257, 784, 1100, "uint8", "int8", (3, 1100, 7)),
+    (129, 1024, 512, "int8", "int8", (1, 512, 2)),
+    (70, 130, 700, "uint8", "int8", (5, 690, 3)),
+    (200, 617, 1024, "int8", "bf16", None),
+    (97, 784, 512, "uint8", "bf16", (0, 512, 4)),
+    (200, 617, 1024, "int8", "fp8", None),
+    (131, 784, 640, "uint8", "fp8", (2, 640, 2)),
+    (33, 1000, 320, "int8", "fp8", None),
+    (600, 64, 2048, "int8", "int8", None),
+    (64, 512, 64, "uint8", "int8", (0, 64, 8)),
+]
+
+
+@pytest.mark.parametrize("case", ENC_CASES, ids=lambda c: "n%d_F%d_D%d_%s_%s_%s" % (c[0], c[1], c[2], c[3], c[4], c[5]))
+def test_encode_integer_features_bit_exact(hdc, case):
+    n, F, D, xt, ct, dims = case
+    start, end, stride = dims or (0, D, 1)
+    say("encode", case)
+    X, P = dg.random_case(n, F, D, xt, seed=n + F + D)
+    ref = O.encode(X, P, ct, start, end, stride)
+    Xd, Pd = hdc.pad_cols(X), hdc.pad_cols(P)
+    H = hdc.encode(Xd, F, Pd, D, ct, start, end, stride)
+    torch.cuda.synchronize()
+    assert np.array_equal(words_np(H), ref)
+
+
+@pytest.mark.parametrize("ct", ["fp32", "bf16", "fp8"])
+def test_encode_fp32_features_band(hdc, ct):
+    say("encode fp32 features", ct)
+    d = dg.config_c1(1)
+    X, P = d.X_test, d.P
+    Y, absum = O.project(X, P, ct)
+    ref_bits = np.unpackbits(O.encode(X, P, ct).view(np.uint8), axis=1, bitorder="little")[:, :P.shape[0]]
+    H = hdc.encode(hdc.pad_cols(X), X.shape[1], hdc.pad_cols(P), P.shape[0], ct)
+    torch.cuda.synchronize()
+    got = np.unpackbits(words_np(H).view(np.uint8), axis=1, bitorder="little")[:, :P.shape[0]]
+    # fp32 accumulation of F terms: |error| <= gamma_F * sum|x'| (2x slack)
+    F = X.shape[1]
+    gamma = 2 * F * 2.0 ** -24 / (1 - F * 2.0 ** -24)
+    sure = np.abs(Y) > gamma * absum[:, None]
+    assert sure.mean() > 0.999
+    assert np.array_equal(got[sure], ref_bits[sure])
+    flips = (got != ref_bits).mean()
+    assert flips <= 1e-3
+
+
+BUNDLE_CASES = [(1, 64, 1), (100, 100, 3), (6238, 2048, 26), (5000, 1000, 128), (300, 10240, 10)]
+
+
+@pytest.mark.parametrize("case", BUNDLE_CASES, ids=str)
+def test_bundle_bit_exact(hdc, case):
+    n, nbits, K = case
+    say("bundle", case)
+    g = np.random.default_rng(n + nbits)
+    W = (nbits + 63) // 64
+    bits = g.integers(0, 2, size=(n, W * 64), dtype=np.uint8)
+    bits[:, nbits:] = 0
+    H = np.packbits(bits, axis=1, bitorder="little").view(np.uint64).reshape(n, W)
+    y = g.integers(0, K, size=n).astype(np.int32)
+    if K > 2:
+        y[y == 1] = 0                      # class 1 empty
+    Cref, cref = O.bundle(H, y, K, nbits)
+    Cw, counts = hdc.bundle(dev(H.view(np.int64)), nbits, dev(y), K)
+    torch.cuda.synchronize()
+    assert np.array_equal(words_np(Cw), Cref)
+    assert np.array_equal(counts.cpu().numpy(), cref)
+
+
+HAM_CASES = [(1, 64, 1, (0, 64, 1)), (257, 2048, 26, (0, 2048, 1)), (1000, 10240, 26, (0, 4096, 1)),
+             (333, 8192, 10, (0, 8192, 2)), (129, 8192, 10, (3, 8000, 4)), (64, 1000, 100, (1, 999, 3)),
+             (500, 16384, 128, (0, 16384, 8)), (77, 640, 5, (0, 640, 1))]
+
+
+@pytest.mark.parametrize("case", HAM_CASES, ids=str)
+def test_hamming_argmin_bit_exact(hdc, case):
+    n, nbits, K, (s, e, k) = case
+    say("hamming", case)
+    g = np.random.default_rng(n * 7 + K)
+    W = (nbits + 63) // 64
+    Q = g.integers(0, 2 ** 63, size=(n, W), dtype=np.int64).view(np.uint64)
+    Cw = g.integers(0, 2 ** 63, size=(K, W), dtype=np.int64).view(np.uint64)
+    if K >= 3:
+        Cw[2] = Cw[0]                      # duplicate class: ties -> lower index
+    dref = O.hamming(Q, Cw, s, e, k)
+    lref, mref = O.argmin(dref)
+    lab, mn, dists = hdc.hamming_argmin(dev(Q.view(np.int64)), dev(Cw.view(np.int64)), s, e, k, True, True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dists.cpu().numpy(), dref)
+    assert np.array_equal(lab.cpu().numpy(), lref)
+    assert np.array_equal(mn.cpu().numpy(), mref)
+
+
+CLS_CASES = [
+    # n, F, D, K, x_type, compute, (start, d_trunc, stride)
+    (1, 64, 64, 2, "int8", "int8", None),
+    (65, 617, 1024, 26, "int8", "int8", None),
+    (300, 617, 2048, 26, "int8", "int8", (0, 1024, 1)),
+    (200, 784, 2048, 10, "uint8", "int8", (1, 2048, 2)),
+    (100, 1024, 1536, 100, "int8", "int8", (0, 1536, 3)),
+    (130, 256, 1024, 50, "int8", "int8", None),
+    (129, 617, 1024, 26, "int8", "bf16", (0, 1024, 2)),
+    (129, 617, 1024, 26, "int8", "fp8", None),
+    (90, 784, 1024, 10, "uint8", "fp8", (0, 1024, 4)),
+    (90, 784, 1024, 10, "uint8", "bf16", None),
+    (70, 96, 1000, 5, "int8", "int8", (7, 990, 5)),
+]
+
+
+@pytest.mark.parametrize("case", CLS_CASES, ids=str)
+def test_classify_bit_exact(hdc, case):
+    n, F, D, K, xt, ct, dims = case
+    start, d_trunc, stride = dims or (0, D, 1)
+    say("classify", case)
+    X, P = dg.random_case(n, F, D, xt, seed=3 * n + F)
+    g = np.random.default_rng(n + K)
+    Cw = g.integers(0, 2 ** 63, size=(K, (D + 63) // 64), dtype=np.int64).view(np.uint64)
+    if D % 64:
+        Cw[:, -1] &= np.uint64((1 << (D % 64)) - 1)
+    lref, dref = O.classify(X, P, Cw, ct, start, d_trunc, stride, with_dists=True)
+    lab, dists = hdc.classify(hdc.pad_cols(X), F, hdc.pad_cols(P), D, dev(Cw.view(np.int64)), ct, start,
+                              d_trunc, stride, with_dists=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dists.cpu().numpy(), dref)
+    assert np.array_equal(lab.cpu().numpy(), lref)
+
+
+def test_fused_equals_encode_then_hamming(hdc):
+    say("fused vs unfused")
+    X, P = dg.random_case(500, 617, 4096, "int8", seed=99)
+    g = np.random.default_rng(1)
+    Cw = g.integers(0, 2 ** 63, size=(26, 64), dtype=np.int64)
+    Xd, Pd, Cd = hdc.pad_cols(X), hdc.pad_cols(P), dev(Cw)
+    for (s, e, k) in [(0, 4096, 1), (0, 2048, 2), (3, 4000, 4)]:
+        lab_f, d_f = hdc.classify(Xd, 617, Pd, 4096, Cd, "int8", s, e, k, with_dists=True)
+        H = hdc.encode(Xd, 617, Pd, 4096, "int8", s, e, k)
+        idx = np.arange(s, e, k)
+        bits = np.unpackbits(Cw.view(np.uint8), axis=1, bitorder="little")[:, idx]
+        W = (idx.size + 63) // 64
+        pad = np.zeros((26, W * 64), np.uint8)
+        pad[:, :idx.size] = bits
+        Cg = np.packbits(pad, axis=1, bitorder="little").view(np.int64)
+        lab_u, _, d_u = hdc.hamming_argmin(H, dev(Cg), 0, idx.size, 1, with_dists=True)
+        torch.cuda.synchronize()
+        assert torch.equal(lab_f, lab_u) and torch.equal(d_f, d_u)
+
+
+def test_convert_features_canonical_integers(hdc):
+    say("convert 384 integers")
+    i8 = np.arange(-128, 128, dtype=np.int8).reshape(1, -1)
+    u8 = np.arange(0, 256, dtype=np.uint8).reshape(1, -1)
+    for arr in (i8, u8):
+        for ct, fn in (("bf16", O.round_bf16), ("fp8", O.round_e4m3), ("int8", float)):
+            got = hdc.convert_features(hdc.pad_cols(arr), arr.shape[1], ct).cpu().numpy()[0]
+            ref = np.array([fn(float(v)) for v in arr[0]])
+            assert np.array_equal(got, ref), ct
+    f = np.array([[17.0, 19.0, -17.0, 0.001, 447.0, 460.0, 464.0, 470.0, 1e4, -1e4, 1 + 2 ** -8, 3.3e38]],
+                 dtype=np.float32)
+    for ct, fn in (("bf16", O.round_bf16), ("fp8", O.round_e4m3)):
+        got = hdc.convert_features(hdc.pad_cols(f), f.shape[1], ct).cpu().numpy()[0]
+        ref = np.array([fn(float(v)) for v in f[0]], dtype=np.float32)
+        assert np.array_equal(got, ref), (ct, got, ref)
+
+
+def test_empty_and_invalid(hdc):
+    say("edge cases")
+    X = torch.zeros((0, 64), dtype=torch.int8, device="cuda")
+    P = hdc.pad_cols(np.ones((64, 8), np.int8))
+    H = hdc.encode(X, 8, P, 64)
+    assert H.shape == (0, 1)
+    with pytest.raises(hdc.HDCError):
+        hdc.encode(hdc.pad_cols(np.ones((2, 8), np.int8)), 8, P, 64, "int8", 0, 65, 1)   # end > D
+    with pytest.raises(hdc.HDCError):
+        hdc.encode(hdc.pad_cols(np.ones((2, 8), np.int8)), 8, P, 64, "int8", 10, 5, 1)   # empty set
+    with pytest.raises(hdc.HDCError) as e:
+        hdc.encode(hdc.pad_cols(np.ones((2, 8), np.float32)), 8, P, 64, "int8")          # fp32 -> int8
+    assert e.value.code == 2
+    Cw = torch.zeros((200, 1), dtype=torch.int64, device="cuda")
+    with pytest.raises(hdc.HDCError):
+        hdc.hamming_argmin(torch.zeros((3, 1), dtype=torch.int64, device="cuda"), Cw, 0, 64)   # K > 128

@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the HDC classification hot path on one MI355X.
+
+Workload: the speech-feature-shaped configuration (617 int8 features,
+26 classes, D = 10240): class hypervectors are trained on its 6238 training
+vectors (GPU encode + majority bundle), then a batch of fresh queries drawn
+from the same mixture is classified by the fused kernel (encode -> sign ->
+Hamming -> argmin).  One timed step classifies the whole batch with the plain
+(unapproximated) configuration; ``value`` is queries/s of those steps.
+
+The tuned configuration is chosen the way the paper's tuner does it
+(Sec. 3 / 5.2): every candidate of the (D', stride, dtype) grid is evaluated
+on 2000 sweep queries in one persistent launch (hdc_eval_configs), and the
+fastest one whose accuracy is within 1 point of the plain configuration is
+kept; it is then timed on the same batch.  Also reported: per-call latency
+p50/p99 at the configuration's test-set size (1559 queries), the training
+time, the sweep time, a roofline line for the fused kernel (int8 MFMA), and
+the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--batch 262144]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1 << 18)
+    ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); got --gpus %d, WORLD_SIZE %d" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_26547_amd import datagen as dg
+    from paper_2606_26547_amd import hdc, tuner
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    N = args.batch
+
+    # ------------------------------------------------------------ data
+    t0 = time.time()
+    sp = dg.SpeechLike(2)
+    ds = sp.dataset()
+    F, K, D = ds.F, ds.K, ds.D
+    Xq, yq = sp.queries(N, stream=10)
+    Xs, ys = sp.queries(dg.C4["n_queries"], stream=4)          # sweep queries
+    log("data ready in %.1fs: F=%d K=%d D=%d batch=%d" % (time.time() - t0, F, K, D, N))
+
+    Pd = hdc.pad_cols(ds.P, dev)
+    Xtr = hdc.pad_cols(ds.X_train, dev)
+    ytr = torch.as_tensor(ds.y_train).to(dev)
+    Xqd = hdc.pad_cols(Xq, dev)
+    yqd = torch.as_tensor(yq).to(dev)
+    Xsd = hdc.pad_cols(Xs, dev)
+    ysd = torch.as_tensor(ys).to(dev)
+    Xte = hdc.pad_cols(ds.X_test, dev)
+    ws_b = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(D, K), dtype=torch.uint8, device=dev)
+    Htr = torch.zeros((Xtr.shape[0], hdc.words(D)), dtype=torch.int64, device=dev)
+
+    def train():
+        hdc.encode(Xtr, F, Pd, D, "int8", out=Htr)
+        return hdc.bundle(Htr, D, ytr, K, ws_b)
+
+    Cw, _ = train()
+    torch.cuda.synchronize()
+
+    def event_loop(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        durs = [a.elapsed_time(b) for a, b in ev]          # ms, on the launch stream
+        return wall * 1e3 / steps, float(np.mean(durs)), durs
+
+    # ------------------------------------------------------------ plain steps
+    plain = hdc.Prepared(Cw, D, "int8")
+    labels = torch.empty(N, dtype=torch.int32, device=dev)
+    ms_step, ms_kernel, _ = event_loop(lambda: plain(Xqd, F, Pd, labels), args.steps, args.warmup)
+    acc_plain = float((labels == yqd).float().mean().item())
+    qps = N / (ms_step / 1e3)
+    ops = 2.0 * F * D * N                      # algorithmic encode ops per launch (pad not counted)
+    achieved = ops / (ms_kernel / 1e3) / 1e12
+    log("plain: %.3f ms/step (kernel %.3f ms) -> %.3e q/s, %.1f TOP/s, acc %.4f" %
+        (ms_step, ms_kernel, qps, achieved, acc_plain))
+
+    out = {
+        "metric": "queries/s (encode+Hamming argmin) plain vs tuned at <=1% acc loss; p99 ms",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic (seeded c2 Gaussian-mixture generator; ISOLET-shaped, no real dataset)",
+        "config": {"workload": "speech-shaped HDC classify, int8 features F=617, K=26 classes, D=10240, "
+                               "plain config, batch of %d fresh queries; model bundled from 6238 train vectors" % N,
+                   "F": F, "K": K, "D": D, "batch": N, "parallelism": "none (1 GPU)"},
+        "accuracy_plain": acc_plain,
+        "roofline": {"bound": "mfma", "kernel": "k_encode<int8, classify>", "achieved": achieved,
+                     "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
+                     "traffic": None, "ms_per_launch": ms_kernel,
+                     "ops_per_launch": ops},
+    }
+
+    if not args.no_extras:
+        # -------------------------------------------------------- training
+        ms_train, _, _ = event_loop(train, 5, 1)
+        out["train"] = {"ms": ms_train, "n_train": int(Xtr.shape[0]),
+                        "note": "encode of the training set + majority bundle"}
+        # -------------------------------------------------------- sweep + tuned selection
+        grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
+        slots = [(d, k, 0, t) for (d, k, t) in dg.sweep_slots(4)]
+        tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)                  # warm-up launch
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)
+        sweep_ms = (time.perf_counter() - t) * 1e3
+        grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid)
+        best, plain_r = tuner.select_tuned(
+            grid_res, (D, 1, 0, "int8"), 1.0,
+            timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw))
+        out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
+                        "ms": sweep_ms, "one_launch": True}
+        d, k, s, tdt = best.cfg
+        tuned = hdc.Prepared(Cw, D, tdt, s, d, k)
+        tl = torch.empty(N, dtype=torch.int32, device=dev)
+        ms_t, ms_tk, _ = event_loop(lambda: tuned(Xqd, F, Pd, tl), args.steps, args.warmup)
+        acc_t = float((tl == yqd).float().mean().item())
+        out["tuned"] = {"config": {"d_trunc": d, "stride": k, "start": s, "dtype": tdt},
+                        "value": N / (ms_t / 1e3), "ms_per_step": ms_t, "accuracy": acc_t,
+                        "speedup_vs_plain": ms_step / ms_t,
+                        "sweep_accuracy": best.accuracy, "sweep_accuracy_plain": plain_r.accuracy,
+                        "rule": "fastest grid config with sweep accuracy >= plain - 1 pt"}
+        log("tuned %s: %.3f ms/step, acc %.4f, speedup %.2fx" % (best.cfg, ms_t, acc_t, ms_step / ms_t))
+        # -------------------------------------------------------- latency at config size
+        lat = {}
+        nte = int(Xte.shape[0])
+        for name, prep in (("plain", plain), ("tuned", tuned)):
+            lab = torch.empty(nte, dtype=torch.int32, device=dev)
+            for _ in range(10):
+                prep(Xte, F, Pd, lab)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(args.latency_calls):
+                t = time.perf_counter()
+                prep(Xte, F, Pd, lab)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t) * 1e3)
+            lat[name] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),
+                         "queries_per_call": nte}
+        out["latency"] = lat
+        out["p99_ms"] = lat["plain"]["p99_ms"]
+
+    # ------------------------------------------------------------ CPU oracle
+    if not args.no_cpu:
+        from oracle import oracle as O
+        n_cpu = min(args.cpu_sample, N)
+        Cref = Cw.cpu().numpy().view(np.uint64)
+        t = time.perf_counter()
+        lab_cpu = O.classify(Xq[:n_cpu], ds.P, Cref)
+        dt = time.perf_counter() - t
+        agree = float((lab_cpu == labels[:n_cpu].cpu().numpy()).mean())
+        out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "queries/s", "cores": O.threads(), "kind": "oracle",
+                               "sample": "first %d queries of the batch, plain config (exact int encode + "
+                                         "bit-by-bit Hamming + argmin), %.1fs" % (n_cpu, dt),
+                               "labels_agree_with_gpu": agree}
+        log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -167,6 +167,26 @@ hdc_status hdc_classify(void *stream,
                         void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
+ * hdc_classify_prepare / hdc_classify_prepared -- hdc_classify split in
+ * two, for resident models: _prepare gathers the class hypervectors over
+ * S(dims) into the workspace once (the class operand of the fused kernel and
+ * the per-class count of -1 elements); _prepared then classifies any number
+ * of query batches with that workspace, launching only the fused kernel.
+ * The result is identical to hdc_classify.  `ws` must stay untouched
+ * between the two calls and be sized by hdc_classify_workspace_bytes();
+ * K and dims must be the same in both calls.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_classify_prepare(void *stream,
+                                const uint64_t *C, int32_t K, int64_t ldc, hdc_dims dims,
+                                void *ws, size_t ws_bytes);
+hdc_status hdc_classify_prepared(void *stream,
+                                 const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                 const int8_t *P, int32_t D, int64_t ldp,
+                                 hdc_dtype compute, hdc_dims dims, int32_t K,
+                                 int32_t *labels, int32_t *dists,
+                                 const void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
  * hdc_eval_configs -- one persistent launch that evaluates many
  * approximation configurations on the same queries: the inner loop of the
  * paper's tuning system, which runs each candidate configuration and reads
@@ -176,10 +196,14 @@ hdc_status hdc_classify(void *stream,
  *     out[c].correct = #{i : label_i == truth[i]}
  *     out[c].ticks   = sum over c's work items of device wall-clock ticks
  * (ticks / hdc_device_clock_hz() seconds of device time; several items run
- * concurrently, so this is busy time, not elapsed time).
- *   cfgs   HOST array [ncfg]; read before the call returns
- *   out    [ncfg] hdc_config_result, device memory, zeroed by the call
- *   ws     >= hdc_eval_configs_workspace_bytes(...) with the same arguments
+ * concurrently, so this is busy time, not elapsed time).  A configuration
+ * with an unsupported dtype or an empty / out-of-range dimension set does no
+ * work and reports n = 0.  Work is scheduled longest configuration first.
+ *   X      integer features only (HDC_INT8 / HDC_UINT8); F <= 1024
+ *   truth  [n] int32 true labels
+ *   cfgs   [ncfg] hdc_config, device memory; ncfg <= 4096
+ *   out    [ncfg] hdc_config_result, device memory, overwritten
+ *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, D, K), 256-byte aligned
  * ------------------------------------------------------------------- */
 typedef struct {
     int32_t d_trunc, stride, start;
@@ -192,7 +216,7 @@ typedef struct {
     uint64_t ticks;
 } hdc_config_result;
 
-size_t hdc_eval_configs_workspace_bytes(const hdc_config *cfgs, int32_t ncfg, int32_t K);
+size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
 hdc_status hdc_eval_configs(void *stream,
                             const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                             const int32_t *truth,

@@ -199,6 +199,51 @@ size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
     return class_table_bytes(n_dims, K) + 4 * 32 * 4;
 }
 
+hdc_status hdc_classify_prepare(void *stream, const uint64_t *C, int32_t K, int64_t ldc, hdc_dims dims, void *ws,
+                                size_t ws_bytes)
+{
+    if (K <= 0 || dims.stride < 1 || dims.start < 0 || dims.end <= dims.start)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK)
+        return HDC_ERR_UNSUPPORTED;
+    if (!C || ldc < (dims.end + 63) / 64)
+        return HDC_ERR_INVALID;
+    const int32_t nd = dims_count(dims);
+    if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    int8_t *tab = (int8_t *)ws;
+    int32_t *cpop = (int32_t *)((uint8_t *)ws + class_table_bytes(nd, K));
+    return from_hip(launch_class_table(C, K, ldc, dims.start, dims.stride, nd, tab, cpop, (hipStream_t)stream));
+}
+
+hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                 const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
+                                 int32_t K, int32_t *labels, int32_t *dists, const void *ws, size_t ws_bytes)
+{
+    int ct, xt;
+    hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
+    if (s != HDC_OK)
+        return s;
+    if (K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK)
+        return HDC_ERR_UNSUPPORTED;
+    if (n > 0 && !labels)
+        return HDC_ERR_INVALID;
+    const int32_t nd = dims_count(dims);
+    if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
+    a.ctab = (const int8_t *)ws;
+    a.cpop = (const int32_t *)((const uint8_t *)ws + class_table_bytes(nd, K));
+    a.K = K;
+    a.labels = labels;
+    a.dists = dists;
+    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{0}, (hipStream_t)stream));
+}
+
 hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                         const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
                         const uint64_t *C, int32_t K, int64_t ldc, int32_t *labels, int32_t *dists, void *ws,
@@ -210,38 +255,28 @@ hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n
         return s;
     if (K <= 0)
         return HDC_ERR_INVALID;
-    if (K > kMaxK)
-        return HDC_ERR_UNSUPPORTED;
-    if (!C || ldc < (dims.end + 63) / 64)
-        return HDC_ERR_INVALID;
     if (n > 0 && !labels)
         return HDC_ERR_INVALID;
-    const int32_t nd = dims_count(dims);
-    if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K) || !aligned(ws, 16))
-        return HDC_ERR_WORKSPACE;
-    if (n == 0)
+    if (n == 0) {
+        const int32_t nd = dims_count(dims);
+        if (K > kMaxK)
+            return HDC_ERR_UNSUPPORTED;
+        if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K))
+            return HDC_ERR_WORKSPACE;
         return HDC_OK;
-    hipStream_t st = (hipStream_t)stream;
-    int8_t *tab = (int8_t *)ws;
-    int32_t *cpop = (int32_t *)((uint8_t *)ws + class_table_bytes(nd, K));
-    hipError_t e = launch_class_table(C, K, ldc, dims.start, dims.stride, nd, tab, cpop, st);
-    if (e != hipSuccess)
-        return HDC_ERR_DEVICE;
-    EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
-    a.ctab = tab;
-    a.cpop = cpop;
-    a.K = K;
-    a.labels = labels;
-    a.dists = dists;
-    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{0}, st));
+    }
+    s = hdc_classify_prepare(stream, C, K, ldc, dims, ws, ws_bytes);
+    if (s != HDC_OK)
+        return s;
+    return hdc_classify_prepared(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, K, labels, dists, ws,
+                                 ws_bytes);
 }
 
-size_t hdc_eval_configs_workspace_bytes(const hdc_config *cfgs, int32_t ncfg, int32_t K)
+size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
 {
-    (void)cfgs;
-    (void)ncfg;
-    (void)K;
-    return 0;
+    if (ncfg > kMaxConfigs)
+        return 0;
+    return sweep_workspace_bytes(ncfg, D, K);
 }
 
 hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
@@ -249,9 +284,39 @@ hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64
                             int32_t K, int64_t ldc, const hdc_config *cfgs, int32_t ncfg,
                             hdc_config_result *out, void *ws, size_t ws_bytes)
 {
-    (void)stream; (void)X; (void)x_type; (void)n; (void)F; (void)ldx; (void)truth; (void)P; (void)D;
-    (void)ldp; (void)C; (void)K; (void)ldc; (void)cfgs; (void)ncfg; (void)out; (void)ws; (void)ws_bytes;
-    return HDC_ERR_UNSUPPORTED;
+    int ct, xt;
+    hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, HDC_INT8, hdc_dims{0, D, 1}, &ct, &xt);
+    if (s != HDC_OK)
+        return s;
+    if (K <= 0 || ncfg <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK || ncfg > kMaxConfigs)
+        return HDC_ERR_UNSUPPORTED;
+    if (!C || ldc < (D + 63) / 64 || !cfgs || !out || (n > 0 && !truth))
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_eval_configs_workspace_bytes(ncfg, D, K) || !aligned(ws, 256))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    SweepArgs a;
+    a.X = X;
+    a.x_type = xt;
+    a.n = n;
+    a.F = F;
+    a.ldx = ldx;
+    a.truth = truth;
+    a.P = P;
+    a.ldp = ldp;
+    a.D = D;
+    a.C = C;
+    a.K = K;
+    a.ldc = ldc;
+    a.cfgs = cfgs;
+    a.ncfg = ncfg;
+    a.out = out;
+    a.ws = (uint8_t *)ws;
+    a.ws_bytes = ws_bytes;
+    return from_hip(launch_sweep(a, (hipStream_t)stream));
 }
 
 double hdc_device_clock_hz(void)

@@ -49,6 +49,7 @@ constexpr int kWaves = 4;           // waves per workgroup of the encoder
 constexpr int kMaxF = 1024;
 constexpr int kMaxFFloat = 256;
 constexpr int kMaxK = 128;
+constexpr int kMaxConfigs = 4096;
 
 inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
 inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }

@@ -33,6 +33,7 @@ STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_E
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
            "hdc_bundle", "hdc_hamming_argmin", "hdc_classify_workspace_bytes", "hdc_classify",
+           "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
            "hdc_convert_features"]
 
@@ -69,8 +70,11 @@ _lib.hdc_classify_workspace_bytes.restype = _sz
 _lib.hdc_classify_workspace_bytes.argtypes = [_i32, _i32]
 _lib.hdc_classify.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i32,
                               _i64, _p, _p, _p, _sz]
+_lib.hdc_classify_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
+_lib.hdc_classify_prepared.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _i32,
+                                       _p, _p, _p, _sz]
 _lib.hdc_eval_configs_workspace_bytes.restype = _sz
-_lib.hdc_eval_configs_workspace_bytes.argtypes = [_p, _i32, _i32]
+_lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32]
 _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
                                   _p, _i32, _p, _p, _sz]
 _lib.hdc_device_clock_hz.restype = C.c_double
@@ -193,6 +197,36 @@ def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor,
     return (labels, dists) if with_dists else labels
 
 
+class Prepared:
+    """Class operand of one (model, configuration) kept on the device, so that
+    repeated classification launches only the fused kernel."""
+
+    def __init__(self, Cw: torch.Tensor, D: int, compute="int8", start=0, d_trunc=None, stride=1):
+        self.D, self.K = D, Cw.shape[0]
+        self.compute, self.start = compute, start
+        self.d_trunc = D if d_trunc is None else d_trunc
+        self.stride = stride
+        self.nd = dims_count(start, self.d_trunc, stride)
+        need = classify_workspace_bytes(self.nd, self.K)
+        self.ws = torch.empty(max(need, 16), dtype=torch.uint8, device=Cw.device)
+        _check(_lib.hdc_classify_prepare(_stream(), _ptr(Cw), self.K, Cw.shape[1],
+                                         Dims(start, self.d_trunc, stride), _ptr(self.ws), self.ws.numel()),
+               "hdc_classify_prepare")
+
+    def __call__(self, X: torch.Tensor, F: int, P: torch.Tensor, labels: torch.Tensor | None = None,
+                 with_dists=False):
+        n = X.shape[0]
+        if labels is None:
+            labels = torch.empty(n, dtype=torch.int32, device=X.device)
+        dists = torch.empty((n, self.K), dtype=torch.int32, device=X.device) if with_dists else None
+        _check(_lib.hdc_classify_prepared(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), self.D,
+                                          P.shape[1], DTYPE[self.compute],
+                                          Dims(self.start, self.d_trunc, self.stride), self.K, _ptr(labels),
+                                          _ptr(dists), _ptr(self.ws), self.ws.numel()),
+               "hdc_classify_prepared")
+        return (labels, dists) if with_dists else labels
+
+
 def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:
     out = torch.empty((X.shape[0], F), dtype=torch.float32, device=X.device)
     _check(_lib.hdc_convert_features(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1],
@@ -206,10 +240,9 @@ def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, 
     persistent launch; returns (correct[ncfg], ticks[ncfg]) device tensors."""
     arr = np.array([[d, k, s, DTYPE[t] if isinstance(t, str) else int(t)] for (d, k, s, t) in cfgs],
                    dtype=np.int32).reshape(-1, 4)
-    host = (Config * len(arr))(*[Config(*map(int, r)) for r in arr])
     dev = torch.from_numpy(arr).to(X.device)
     K = Cw.shape[0]
-    need = int(_lib.hdc_eval_configs_workspace_bytes(host, len(arr), K))
+    need = int(_lib.hdc_eval_configs_workspace_bytes(len(arr), D, K))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
     out = torch.zeros((len(arr), 4), dtype=torch.int32, device=X.device)   # {correct, n, ticks(u64)}

@@ -16,6 +16,19 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// LDS (address space 3) pointer types: keeping the address space explicit
+// makes the compiler emit ds_read / ds_write instead of flat accesses.
+#define HDC_LDS __attribute__((address_space(3)))
+typedef HDC_LDS uint8_t lds_u8;
+typedef HDC_LDS int32_t lds_i32;
+typedef HDC_LDS uint4 lds_uint4;
+typedef HDC_LDS v4i lds_v4i;
+
+__device__ __forceinline__ void lds_st16(lds_u8 *p, uint4 v)
+{
+    *(lds_v4i *)p = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+}
+
 // ---------------------------------------------------------------------------
 // Operand traits.  Every compute type uses a 32x32 MFMA (rows = dimensions,
 // columns = queries).  KSTEP features are consumed per instruction; each

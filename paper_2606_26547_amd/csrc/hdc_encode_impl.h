@@ -39,7 +39,7 @@ static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
 
 // Largest QT whose query registers fit comfortably beside the accumulators.
 template <int CT, int KS> struct QtMax {
-    static constexpr int value = (KS * Tr<CT>::DW <= 80 && CT != C_BF16) ? 2 : 1;
+    static constexpr int value = ((CT == C_I8 && KS <= 16) || (CT == C_F32 && KS <= 64)) ? 2 : 1;
 };
 
 template <int CT, int XF, int KS>

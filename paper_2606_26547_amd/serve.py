@@ -1,0 +1,359 @@
+"""Continuous-batching serving loop over resident HDC models.
+
+Requests are either inference (classify n query vectors with one model under
+its plain or tuned configuration) or configuration-evaluation jobs (run a
+list of approximation configurations on labelled queries in one persistent
+launch: the tuner's inner loop, Sec. 3 / 4.1 of the paper).
+
+Structure
+---------
+* ``Scheduler``: admission and batching only (no device code), so it can be
+  tested on the CPU with a fake executor.  A request is admitted when its
+  device bytes fit in the HBM budget left after the resident models; admitted
+  inference requests for the same (model, configuration) are packed into a
+  batch of at most ``max_batch`` queries the next time that lane is free —
+  requests that arrive while earlier batches run join the next batch
+  (continuous batching, not a queue of whole requests).  Bytes are released
+  when the batch completes.
+* ``GpuExecutor``: one HIP stream per model plus one for configuration jobs;
+  a batch is an async H2D copy from pinned staging, one fused-classifier
+  launch (``hdc_classify_prepared``) and an async D2H copy of the labels,
+  closed by an event.  Batches of different models overlap on the device.
+* ``Server``: the scheduler thread that drives both and completes futures
+  with per-request latency (arrival -> labels on the host).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- requests
+@dataclasses.dataclass
+class Request:
+    model: int
+    X: np.ndarray                      # [n][F] int8 queries
+    tuned: bool = False
+    kind: str = "infer"                # "infer" | "configs"
+    cfgs: list | None = None           # configs job: [(d_trunc, stride, start, dtype)]
+    truth: np.ndarray | None = None    # configs job: labels
+    t_arrival: float = 0.0
+    future: Future = dataclasses.field(default_factory=Future)
+    rid: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+
+@dataclasses.dataclass
+class Batch:
+    key: tuple                          # (model, tuned) or ("configs", rid)
+    requests: list
+    offsets: list
+    n: int
+    nbytes: int
+    handle: object = None
+
+
+class AdmissionError(ValueError):
+    pass
+
+
+class Scheduler:
+    """Admission by device-memory budget and continuous batching per lane.
+
+    ``bytes_of(request)`` gives the device bytes a request holds while it is
+    in flight; ``budget`` is what is left of the HBM budget after the
+    resident models.  A lane is (model, tuned) for inference and a private
+    lane per configuration job; each lane has at most ``depth`` batches in
+    flight."""
+
+    def __init__(self, budget: int, bytes_of, max_batch: int = 16384, depth: int = 2):
+        self.budget = int(budget)
+        self.bytes_of = bytes_of
+        self.max_batch = int(max_batch)
+        self.depth = int(depth)
+        self.used = 0
+        self.waiting = collections.deque()          # arrived, not yet admitted (FIFO)
+        self.admitted = collections.defaultdict(collections.deque)   # lane -> requests
+        self.inflight = collections.defaultdict(int)                  # lane -> batches in flight
+        self.peak_used = 0
+
+    def lane(self, r: Request):
+        return ("configs", r.rid) if r.kind == "configs" else (r.model, bool(r.tuned))
+
+    def submit(self, r: Request):
+        need = self.bytes_of(r)
+        if need > self.budget:
+            raise AdmissionError("request needs %d device bytes, budget is %d" % (need, self.budget))
+        self.waiting.append(r)
+
+    def admit(self):
+        """Admit waiting requests in arrival order while they fit."""
+        while self.waiting:
+            r = self.waiting[0]
+            need = self.bytes_of(r)
+            if self.used + need > self.budget:
+                break
+            self.waiting.popleft()
+            self.used += need
+            self.peak_used = max(self.peak_used, self.used)
+            self.admitted[self.lane(r)].append(r)
+
+    def next_batches(self) -> list[Batch]:
+        """Form one batch for every lane that has admitted work and a free slot."""
+        self.admit()
+        out = []
+        for lane, q in self.admitted.items():
+            if not q or self.inflight[lane] >= self.depth:
+                continue
+            reqs, offs, n, nb = [], [], 0, 0
+            while q and (not reqs or n + q[0].n <= self.max_batch) and q[0].kind == "infer":
+                r = q.popleft()
+                reqs.append(r)
+                offs.append(n)
+                n += r.n
+                nb += self.bytes_of(r)
+            if not reqs:                                    # a configuration job runs alone
+                r = q.popleft()
+                reqs, offs, n, nb = [r], [0], r.n, self.bytes_of(r)
+            self.inflight[lane] += 1
+            out.append(Batch(lane, reqs, offs, n, nb))
+        return out
+
+    def done(self, b: Batch):
+        self.inflight[b.key] -= 1
+        self.used -= b.nbytes
+
+    def idle(self) -> bool:
+        return not self.waiting and not any(self.admitted.values()) and not any(self.inflight.values())
+
+
+# ---------------------------------------------------------------- executor
+class GpuExecutor:
+    """Resident models and per-model streams; runs batches asynchronously."""
+
+    def __init__(self, models, device="cuda", max_batch: int = 16384):
+        import torch
+
+        from . import hdc
+        self.torch, self.hdc = torch, hdc
+        self.dev = device
+        self.max_batch = max_batch
+        self.models = []
+        self.streams = []
+        for m in models:
+            self.models.append(m)
+            self.streams.append(torch.cuda.Stream(device=device))
+        self.cfg_stream = torch.cuda.Stream(device=device)
+        self.resident_bytes = sum(m.resident_bytes for m in models)
+
+    @staticmethod
+    def request_bytes(r: Request, F: int) -> int:
+        ld = max(64, (F + 63) // 64 * 64)
+        return r.n * (ld + 4) + (1 << 12)
+
+    def launch(self, b: Batch):
+        torch, hdc = self.torch, self.hdc
+        r0 = b.requests[0]
+        m = self.models[r0.model]
+        stream = self.cfg_stream if r0.kind == "configs" else self.streams[r0.model]
+        ld = m.P.shape[1]
+        host = torch.empty((b.n, ld), dtype=torch.int8, pin_memory=True)
+        hv = host.numpy()
+        hv[:, m.F:] = 0
+        for r, off in zip(b.requests, b.offsets):
+            hv[off:off + r.n, :m.F] = r.X
+        with torch.cuda.stream(stream):
+            X = host.to(self.dev, non_blocking=True)
+            if r0.kind == "configs":
+                truth = torch.as_tensor(r0.truth, dtype=torch.int32).pin_memory().to(self.dev, non_blocking=True)
+                correct, ticks = hdc.eval_configs(X, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws)
+                out = torch.empty(len(r0.cfgs), dtype=torch.int32, pin_memory=True)
+                out.copy_(correct, non_blocking=True)
+            else:
+                prep = m.tuned if r0.tuned else m.plain
+                labels = prep(X, m.F, m.P)
+                out = torch.empty(b.n, dtype=torch.int32, pin_memory=True)
+                out.copy_(labels, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        b.handle = (ev, out, host, X)
+
+    def ready(self, b: Batch) -> bool:
+        return b.handle[0].query()
+
+    def results(self, b: Batch):
+        ev, out, _, _ = b.handle
+        ev.synchronize()
+        res = out.numpy()
+        if b.requests[0].kind == "configs":
+            return [res.copy()]
+        return [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
+
+
+class ResidentModel:
+    """A model kept on the device: projection, class hypervectors and the
+    prepared class operands of its plain and tuned configurations."""
+
+    def __init__(self, P: np.ndarray, X_train: np.ndarray, y_train: np.ndarray, K: int,
+                 tuned_cfg=None, device="cuda"):
+        import torch
+
+        from . import hdc
+        self.D, self.F, self.K = int(P.shape[0]), int(P.shape[1]), int(K)
+        self.P = hdc.pad_cols(P, device)
+        Xtr = hdc.pad_cols(X_train, device)
+        H = hdc.encode(Xtr, self.F, self.P, self.D)
+        self.C, _ = hdc.bundle(H, self.D, torch.as_tensor(y_train, dtype=torch.int32).to(device), self.K)
+        del H, Xtr
+        self.plain = hdc.Prepared(self.C, self.D, "int8")
+        self.tuned_cfg = tuned_cfg or (self.D, 1, 0, "int8")
+        d, k, s, t = self.tuned_cfg
+        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
+        self.sweep_ws = None
+        self.resident_bytes = (self.P.numel() + self.C.numel() * 8 + self.plain.ws.numel()
+                               + self.tuned.ws.numel())
+
+    def set_tuned(self, cfg):
+        from . import hdc
+        d, k, s, t = cfg
+        self.tuned_cfg = cfg
+        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
+
+
+# ---------------------------------------------------------------- server
+class Server:
+    """Scheduler thread: admits, batches, launches and completes requests."""
+
+    def __init__(self, executor, budget: int, max_batch: int = 16384, depth: int = 2,
+                 bytes_of=None, poll_s: float = 2e-4):
+        self.ex = executor
+        if bytes_of is None:
+            bytes_of = lambda r: GpuExecutor.request_bytes(r, executor.models[r.model].F)  # noqa: E731
+        self.sched = Scheduler(budget, bytes_of, max_batch, depth)
+        self.lock = threading.Lock()
+        self.running = []
+        self.stop_flag = False
+        self.poll_s = poll_s
+        self.next_id = 0
+        self.completed = []                 # (rid, kind, model, n, latency_s)
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.thread.start()
+
+    def submit(self, r: Request) -> Future:
+        with self.lock:
+            r.t_arrival = r.t_arrival or time.perf_counter()
+            r.rid = self.next_id
+            self.next_id += 1
+            try:
+                self.sched.submit(r)
+            except AdmissionError as e:
+                r.future.set_exception(e)
+        return r.future
+
+    def _loop(self):
+        while True:
+            with self.lock:
+                batches = self.sched.next_batches()
+                stopping = self.stop_flag and self.sched.idle() and not self.running
+            if stopping:
+                return
+            for b in batches:
+                try:
+                    self.ex.launch(b)
+                    self.running.append(b)
+                except Exception as e:   # a malformed request fails alone
+                    for r in b.requests:
+                        r.future.set_exception(e)
+                    with self.lock:
+                        self.sched.done(b)
+            still = []
+            for b in self.running:
+                if self.ex.ready(b):
+                    res = self.ex.results(b)
+                    now = time.perf_counter()
+                    with self.lock:
+                        self.sched.done(b)
+                    for r, v in zip(b.requests, res):
+                        self.completed.append((r.rid, r.kind, r.model, r.n, now - r.t_arrival))
+                        r.future.set_result(v)
+                else:
+                    still.append(b)
+            self.running = still
+            if not batches and still:
+                time.sleep(self.poll_s)
+            elif not batches and not still:
+                time.sleep(self.poll_s)
+
+    def close(self, timeout: float = 60.0):
+        self.stop_flag = True
+        self.thread.join(timeout)
+
+    def latency_report(self, kind="infer"):
+        lat = np.array([c[4] for c in self.completed if c[1] == kind])
+        if lat.size == 0:
+            return {}
+        return {"requests": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+                "queries": int(sum(c[3] for c in self.completed if c[1] == kind))}
+
+
+def open_loop(server: Server, sources, rate: float, duration: float, seed: int, tuned: bool,
+              job_frac: float = 0.05, job_cfgs=None, job_queries: int = 512, max_n: int = 4096):
+    """Drive ``server`` with an open-loop Poisson stream: arrivals are
+    submitted at their scheduled times regardless of completions (so queueing
+    shows up in the latency instead of being hidden).  ``sources[m]`` has
+    ``queries(n, stream) -> (X, y)``.  Returns the futures with their requests."""
+    from .datagen import rng
+    t_arr = poisson_arrivals(rate, duration, seed)
+    sizes = request_sizes(t_arr.size, seed, max_n)
+    g = rng(seed, 13)
+    models = g.integers(0, len(sources), size=t_arr.size)
+    is_job = g.random(t_arr.size) < job_frac
+    pool = {}
+    for m, src in enumerate(sources):                   # pre-drawn query pools per model
+        pool[m] = src.queries(max_n, 100 + m)
+    out = []
+    t0 = time.perf_counter()
+    for i, ta in enumerate(t_arr):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        m = int(models[i])
+        X, y = pool[m]
+        if is_job[i]:
+            n = min(job_queries, X.shape[0])
+            r = Request(model=m, X=X[:n], kind="configs", cfgs=job_cfgs(m), truth=y[:n])
+        else:
+            n = int(sizes[i])
+            off = int(g.integers(0, X.shape[0] - n + 1))
+            r = Request(model=m, X=X[off:off + n], tuned=tuned)
+        r.t_arrival = t0 + ta
+        out.append((r, server.submit(r)))
+    return out
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Open-loop arrival times (seconds) of a Poisson process."""
+    from .datagen import rng
+    g = rng(seed, 11)
+    t, out = 0.0, []
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= duration:
+            return np.array(out)
+        out.append(t)
+
+
+def request_sizes(count: int, seed: int, max_n: int = 4096) -> np.ndarray:
+    """Log-uniform request sizes in [1, max_n]."""
+    from .datagen import rng
+    g = rng(seed, 12)
+    return np.floor(np.exp(g.uniform(0, np.log(max_n + 1), size=count))).astype(int).clip(1, max_n)

@@ -1,0 +1,141 @@
+"""Serving loop on the CPU: admission by device-memory budget, continuous
+batching and result routing, driven by a fake executor with scripted
+latencies (no GPU)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_26547_amd.serve import AdmissionError, Request, Scheduler, Server, poisson_arrivals, request_sizes
+
+
+class FakeExecutor:
+    """Completes a batch `latency(batch)` seconds after launch; the 'labels'
+    of a query are a deterministic function of its features."""
+
+    def __init__(self, latency=lambda b: 0.002, fail_model=None):
+        self.latency = latency
+        self.launched = []
+        self.fail_model = fail_model
+        self.lock = threading.Lock()
+        self.concurrent = 0
+        self.max_concurrent = 0
+
+    def launch(self, b):
+        if self.fail_model is not None and b.requests[0].model == self.fail_model:
+            raise ValueError("bad model")
+        with self.lock:
+            self.launched.append(b)
+            self.concurrent += 1
+            self.max_concurrent = max(self.max_concurrent, self.concurrent)
+        b.handle = time.perf_counter() + self.latency(b)
+
+    def ready(self, b):
+        return time.perf_counter() >= b.handle
+
+    def results(self, b):
+        with self.lock:
+            self.concurrent -= 1
+        if b.requests[0].kind == "configs":
+            return [np.array([len(b.requests[0].cfgs)])]
+        return [r.X.astype(np.int64).sum(1) % 7 for r in b.requests]
+
+
+def req(model, n, seed=0, **kw):
+    X = np.random.default_rng(seed).integers(-127, 128, size=(n, 16)).astype(np.int8)
+    return Request(model=model, X=X, **kw)
+
+
+def test_scheduler_admission_respects_budget_and_fifo():
+    s = Scheduler(budget=1000, bytes_of=lambda r: r.n * 10, max_batch=1000)
+    rs = [req(0, 30, i) for i in range(5)]            # 300 bytes each
+    for r in rs:
+        s.submit(r)
+    b = s.next_batches()
+    assert len(b) == 1 and [r.n for r in b[0].requests] == [30, 30, 30]   # 900 of 1000 admitted
+    assert s.used == 900 and len(s.waiting) == 2
+    s.done(b[0])
+    b2 = s.next_batches()
+    assert [r for r in b2[0].requests] == rs[3:]
+    with pytest.raises(AdmissionError):
+        s.submit(req(0, 200))                           # 2000 bytes > budget
+
+
+def test_scheduler_batches_per_lane_with_depth_and_max_batch():
+    s = Scheduler(budget=10 ** 9, bytes_of=lambda r: r.n, max_batch=100, depth=2)
+    for i in range(6):
+        s.submit(req(i % 2, 40, i))
+    s.submit(req(0, 40, 99, tuned=True))
+    bs = s.next_batches()
+    keys = sorted(b.key for b in bs)
+    assert keys == [(0, False), (0, True), (1, False)]
+    for b in bs:
+        assert b.n <= 100
+    bs2 = s.next_batches()                              # depth 2: one more batch per busy lane
+    assert sorted(b.key for b in bs2) == [(0, False), (1, False)]
+    assert s.next_batches() == []                       # both lanes at depth, nothing admitted left
+    assert all(s.inflight[k] <= 2 for k in s.inflight)
+
+
+def test_continuous_batching_joins_running_lane():
+    ex = FakeExecutor(latency=lambda b: 0.05)
+    srv = Server(ex, budget=10 ** 9, max_batch=10 ** 6, depth=1, bytes_of=lambda r: r.n)
+    f0 = srv.submit(req(0, 10, 0))
+    time.sleep(0.01)                                    # batch 0 is running
+    later = [srv.submit(req(0, 5, i + 1)) for i in range(4)]
+    for f in [f0] + later:
+        f.result(timeout=5)
+    srv.close()
+    sizes = [b.n for b in ex.launched]
+    assert sizes[0] == 10 and sizes[1] == 20            # the four late requests ran as one batch
+
+
+def test_results_routed_to_their_requests_and_latency_reported():
+    ex = FakeExecutor(latency=lambda b: 0.001 * (1 + b.n / 1000))
+    srv = Server(ex, budget=5000, max_batch=300, bytes_of=lambda r: r.n)
+    sizes = request_sizes(60, seed=3, max_n=200)
+    futs, reqs = [], []
+    for i, n in enumerate(sizes):
+        r = req(i % 3, int(n), seed=i)
+        reqs.append(r)
+        futs.append(srv.submit(r))
+    for r, f in zip(reqs, futs):
+        assert np.array_equal(f.result(timeout=10), r.X.astype(np.int64).sum(1) % 7)
+    srv.close()
+    rep = srv.latency_report()
+    assert rep["requests"] == 60 and rep["queries"] == int(sizes.sum())
+    assert rep["p99_ms"] >= rep["p50_ms"] > 0
+    assert srv.sched.peak_used <= 5000 and srv.sched.used == 0
+
+
+def test_config_jobs_run_alone_and_failures_are_isolated():
+    ex = FakeExecutor(fail_model=2)
+    srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n)
+    good = srv.submit(req(0, 8))
+    bad = srv.submit(req(2, 8))
+    job = srv.submit(req(1, 50, kind="configs", cfgs=[(1024, 1, 0, "int8")] * 3, truth=np.zeros(50)))
+    assert good.result(timeout=5).shape == (8,)
+    assert job.result(timeout=5)[0] == 3
+    with pytest.raises(ValueError):
+        bad.result(timeout=5)
+    srv.close()
+    assert all(len(b.requests) == 1 for b in ex.launched if b.requests[0].kind == "configs")
+
+
+def test_tight_budget_still_completes_everything():
+    ex = FakeExecutor(latency=lambda b: 0.002)
+    srv = Server(ex, budget=100, max_batch=1000, bytes_of=lambda r: r.n)
+    futs = [srv.submit(req(i % 2, 40, i)) for i in range(20)]
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+    assert srv.sched.peak_used <= 100
+
+
+def test_arrival_process_and_sizes():
+    t = poisson_arrivals(2000.0, 1.0, seed=1)
+    assert 1800 < t.size < 2200 and np.all(np.diff(t) > 0)
+    n = request_sizes(10000, seed=2)
+    assert n.min() >= 1 and n.max() <= 4096
+    assert 300 < n.mean() < 700                          # log-uniform on [1, 4096]: mean ~ 492

@@ -1,0 +1,82 @@
+"""Serving on the GPU: resident models of different shapes, requests served
+alone and in a concurrent mix must give identical labels (the int8 path is
+exact, so bit for bit), equal to the oracle's; configuration jobs in the mix
+equal a standalone sweep; a tight HBM budget still completes everything."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2606_26547_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    assert torch.cuda.is_available()
+    from paper_2606_26547_amd import serve
+    shapes = [(64, 2, 1024), (256, 26, 4096), (617, 26, 10240), (1024, 100, 16384)]
+    srcs = [dg.ClusterModelData(F, K, D, seed=20 + i) for i, (F, K, D) in enumerate(shapes)]
+    models = [serve.ResidentModel(s.P, s.X_train, s.y_train, s.K, tuned_cfg=(s.D // 2, 2, 0, "int8"))
+              for s in srcs]
+    torch.cuda.synchronize()
+    return serve, srcs, models
+
+
+def run_alone(serve, models, reqs):
+    ex = serve.GpuExecutor(models)
+    srv = serve.Server(ex, budget=1 << 34)
+    out = []
+    for r in reqs:
+        out.append(srv.submit(r).result(timeout=60))     # one at a time
+    srv.close()
+    return out
+
+
+def test_alone_equals_mix_and_oracle(setup):
+    serve, srcs, models = setup
+    print("[case] serving alone vs mix", flush=True)
+    g = np.random.default_rng(0)
+    reqs = []
+    for i in range(24):
+        m = i % len(models)
+        n = int(g.integers(1, 700))
+        X, _ = srcs[m].queries(n, 300 + i)
+        reqs.append((m, X, bool(i % 3 == 0)))
+    mk = lambda: [serve.Request(model=m, X=X, tuned=t) for (m, X, t) in reqs]   # noqa: E731
+    alone = run_alone(serve, models, mk())
+    ex = serve.GpuExecutor(models)
+    srv = serve.Server(ex, budget=1 << 34, max_batch=2048)
+    futs = [srv.submit(r) for r in mk()]                 # all at once: batched and overlapped
+    mix = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for a, b in zip(alone, mix):
+        assert np.array_equal(a, b)
+    # labels equal the oracle's for a sample of requests
+    for idx in (0, 5, 10):
+        m, X, t = reqs[idx]
+        C = models[m].C.cpu().numpy().view(np.uint64)
+        d, k, s, dt = models[m].tuned_cfg if t else (models[m].D, 1, 0, "int8")
+        ref = O.classify(X, srcs[m].P, C, dt, s, d, k)
+        assert np.array_equal(mix[idx], ref)
+
+
+def test_config_jobs_in_mix_and_tight_budget(setup):
+    serve, srcs, models = setup
+    print("[case] serving configs + tight budget", flush=True)
+    cfgs = [(models[2].D, 1, 0, "int8"), (4096, 2, 0, "fp8"), (2048, 1, 0, "bf16")]
+    X, y = srcs[2].queries(512, 77)
+    ex = serve.GpuExecutor(models)
+    srv = serve.Server(ex, budget=3 * 1024 * 1024, max_batch=4096)      # a few requests at a time
+    job = srv.submit(serve.Request(model=2, X=X, kind="configs", cfgs=cfgs, truth=y))
+    infer = [srv.submit(serve.Request(model=i % 4, X=srcs[i % 4].queries(1000, 500 + i)[0]))
+             for i in range(12)]
+    got = job.result(timeout=120)
+    for f in infer:
+        f.result(timeout=120)
+    srv.close()
+    assert srv.sched.peak_used <= 3 * 1024 * 1024
+    C = models[2].C.cpu().numpy().view(np.uint64)
+    ref = O.eval_configs(X, y, srcs[2].P, C, cfgs)
+    assert np.array_equal(got, ref)

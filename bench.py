@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     return ap.parse_args()
 
 
@@ -194,8 +195,42 @@ def main():
                          "queries_per_call": nte}
         out["latency"] = lat
         out["p99_ms"] = lat["plain"]["p99_ms"]
+        # -------------------------------------------------------- unfused Hamming search
+        # packed query hypervectors (2^20 rows) against resident class bits:
+        # bytes = the queries read once (class words are cached), HBM-bound.
+        # "mfma": prepared classes on the matrix cores; "popcount": the
+        # workspace-free search.
+        ham = {}
+        for name, (Kh, nbits) in (("speech K=26 D=10240", (26, 10240)), ("image K=10 D=8192", (10, 8192)),
+                                  ("K=100 D=10240", (100, 10240))):
+            nq = 1 << 20
+            W = nbits // 64
+            Q = torch.randint(-(1 << 62), 1 << 62, (nq, W), dtype=torch.int64, device=dev)
+            Ch = torch.randint(-(1 << 62), 1 << 62, (Kh, W), dtype=torch.int64, device=dev)
+            lab_h = torch.empty(nq, dtype=torch.int32, device=dev)
+            lab_p = torch.empty(nq, dtype=torch.int32, device=dev)
+            hp = hdc.HammingPrepared(Ch, 0, nbits, 1)
+            row = {"queries": nq}
+            for kind, fn in (("mfma", lambda: hp(Q, out=lab_h)),
+                             ("popcount", lambda: hdc.lib().hdc_hamming_argmin(
+                                 hdc._stream(), hdc._ptr(Q), nq, W, hdc._ptr(Ch), Kh, W, hdc.Dims(0, nbits, 1),
+                                 hdc._ptr(lab_p), None, None))):
+                _, ms_hk, _ = event_loop(fn, 10, 2)
+                gbs = nq * W * 8 / (ms_hk / 1e3) / 1e9
+                row[kind] = {"ms": ms_hk, "GB_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                             "queries_per_s": nq / (ms_hk / 1e3)}
+            row["agree"] = bool(torch.equal(lab_h, lab_p))
+            ham[name] = row
+            del Q, Ch, hp
+        out["hamming_unfused"] = ham
+        log("hamming GB/s: %s" % {k: (round(v["mfma"]["GB_s"], 1), round(v["popcount"]["GB_s"], 1), v["agree"])
+                                  for k, v in ham.items()})
+        # -------------------------------------------------------- serving
+        if args.serve_seconds > 0:
+            out["serving"] = serving(args, dev, dg, hdc, tuner, torch)
 
     # ------------------------------------------------------------ CPU oracle
+
     if not args.no_cpu:
         from oracle import oracle as O
         n_cpu = min(args.cpu_sample, N)
@@ -211,6 +246,53 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
 
     print(json.dumps(out), flush=True)
+
+
+def serving(args, dev, dg, hdc, tuner, torch):
+    """Open-loop Poisson stream over the 8 resident serving models: 95%
+    inference requests of 1..4096 queries (log-uniform), 5% configuration
+    jobs (16 configurations x 512 labelled queries); HBM budget 16 GiB.
+    Reported per mode (plain / tuned): p50 / p99 latency from arrival to
+    labels on the host, and completed queries per second."""
+    from paper_2606_26547_amd import serve
+
+    srcs = dg.serving_models(5)
+    models = [serve.ResidentModel(s.P, s.X_train, s.y_train, s.K) for s in srcs]
+    tuned_cfgs = []
+    for s, m in zip(srcs, models):
+        Xv, yv = s.queries(2048, 900)
+        grid = [(d, k, 0, "int8") for d in sorted({m.D, m.D // 2, m.D // 4, m.D // 8}) for k in (1, 2)]
+        res = tuner.sweep(hdc.pad_cols(Xv, dev), m.F, torch.as_tensor(yv).to(dev), m.P, m.D, m.C, grid)
+        best, plain = tuner.select_tuned(res, (m.D, 1, 0, "int8"), 1.0)
+        m.set_tuned(best.cfg)
+        tuned_cfgs.append({"F": m.F, "K": m.K, "D": m.D, "tuned": list(best.cfg),
+                           "acc_plain": plain.accuracy, "acc_tuned": best.accuracy})
+    torch.cuda.synchronize()
+
+    def job_cfgs(mi):
+        D = models[mi].D
+        return [(d, k, 0, t) for d in (D, D // 2, D // 4, D // 8) for k in (1, 2) for t in ("int8", "fp8")]
+
+    report = {"models": tuned_cfgs, "rate_req_s": 2000.0, "seconds": args.serve_seconds,
+              "budget_bytes": 16 << 30}
+    for mode in ("plain", "tuned"):
+        ex = serve.GpuExecutor(models)
+        srv = serve.Server(ex, budget=16 << 30)
+        t0 = time.perf_counter()
+        futs = serve.open_loop(srv, srcs, 2000.0, args.serve_seconds, seed=7, tuned=(mode == "tuned"),
+                               job_cfgs=job_cfgs)
+        for _, f in futs:
+            f.result(timeout=300)
+        wall = time.perf_counter() - t0
+        srv.close()
+        rep = srv.latency_report("infer")
+        rep["configs_jobs"] = srv.latency_report("configs")
+        rep["queries_per_s"] = rep.get("queries", 0) / wall
+        rep["peak_admitted_bytes"] = srv.sched.peak_used
+        report[mode] = rep
+        log("serving %s: p50 %.3f ms p99 %.3f ms, %d requests" % (mode, rep.get("p50_ms", -1), rep.get("p99_ms", -1),
+                                                                rep.get("requests", 0)))
+    return report
 
 
 if __name__ == "__main__":

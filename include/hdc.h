@@ -146,6 +146,28 @@ hdc_status hdc_hamming_argmin(void *stream,
                               int32_t *argmin, int32_t *min_dist, int32_t *dists);
 
 /* ---------------------------------------------------------------------
+ * hdc_hamming_prepare / hdc_hamming_argmin_prepared -- the same search as
+ * hdc_hamming_argmin, split in two for resident class hypervectors (Sec. 2.2
+ * Listing 1: hamming_distance, red_perf, arg_min; Sec. 4.2): _prepare turns
+ * the classes and the perforation set S(perf) into a matrix-core operand
+ * in the workspace once; _prepared then searches any number of query
+ * batches against it.  Outputs are identical to hdc_hamming_argmin with the
+ * same arguments.  `ws` must stay untouched between the calls; K and perf
+ * must be the same in both.
+ *   ws       >= hdc_hamming_workspace_bytes(perf, K) bytes, 16-byte aligned
+ * Supports K <= 128, perf.end <= 65536.
+ * ------------------------------------------------------------------- */
+size_t hdc_hamming_workspace_bytes(hdc_dims perf, int32_t K);
+hdc_status hdc_hamming_prepare(void *stream,
+                               const uint64_t *C, int32_t K, int64_t ldc,
+                               hdc_dims perf, void *ws, size_t ws_bytes);
+hdc_status hdc_hamming_argmin_prepared(void *stream,
+                                       const uint64_t *Q, int64_t n, int64_t ldq,
+                                       int32_t K, hdc_dims perf,
+                                       int32_t *argmin, int32_t *min_dist, int32_t *dists,
+                                       const void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
  * hdc_classify -- the fused inference path: encode each query over the
  * dimensions S(dims) under `compute`, compare bit j of the query with bit
  * S_j of each (full-D) class hypervector, argmin.  Equal, bit for bit, to

@@ -192,6 +192,55 @@ hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_
                                    dists, (hipStream_t)stream));
 }
 
+static hdc_status check_perf(hdc_dims perf, int32_t K)
+{
+    if (K <= 0 || perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK || perf.end > 65536)
+        return HDC_ERR_UNSUPPORTED;
+    return HDC_OK;
+}
+
+size_t hdc_hamming_workspace_bytes(hdc_dims perf, int32_t K)
+{
+    if (check_perf(perf, K) != HDC_OK)
+        return 0;
+    return ham_workspace_bytes(perf.start, perf.end, K);
+}
+
+hdc_status hdc_hamming_prepare(void *stream, const uint64_t *C, int32_t K, int64_t ldc, hdc_dims perf, void *ws,
+                               size_t ws_bytes)
+{
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (!C || ldc < (perf.end + 63) / 64)
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_hamming_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    return from_hip(launch_ham_prepare(C, K, ldc, perf.start, perf.end, perf.stride, (uint8_t *)ws,
+                                       (hipStream_t)stream));
+}
+
+hdc_status hdc_hamming_argmin_prepared(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, int32_t K,
+                                       hdc_dims perf, int32_t *argmin, int32_t *min_dist, int32_t *dists,
+                                       const void *ws, size_t ws_bytes)
+{
+    if (n < 0)
+        return HDC_ERR_INVALID;
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (!ws || ws_bytes < hdc_hamming_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    if (!Q || ldq < (perf.end + 63) / 64 || !argmin)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_ham_prepared(Q, n, ldq, K, perf.start, perf.end, (const uint8_t *)ws, argmin,
+                                        min_dist, dists, (hipStream_t)stream));
+}
+
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
 {
     if (n_dims <= 0 || K <= 0 || K > kMaxK)

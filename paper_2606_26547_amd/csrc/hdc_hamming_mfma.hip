@@ -1,0 +1,229 @@
+// Hamming distance + argmin over packed hypervectors on the matrix cores.
+//
+// With q'_d in {0,1} the query bit (1 = element -1) and c_d = +1 / -1 the
+// class element, the Hamming distance over S is
+//     dist = popc_S(c) + sum_{d in S} q'_d * c_d.
+// The sum runs as an int8 MFMA (rows = classes, columns = queries, K = 32
+// dimensions per instruction).  The query operand is built from the packed
+// words with one shift and four ANDs per dword: lanes of the first half
+// take bit planes 0-3 of every byte, lanes of the second half planes 4-7
+// (the dword shifted down by 4), so byte i of plane register pl is 2^pl
+// when its bit is set.  The class operand holds c_d * 2^(6-pl), so every
+// set query bit contributes exactly 64 * c_d and the accumulator is
+// 64 * sum q' c.  Dimensions outside S (perforated, or past the end) have
+// class byte 0, so query bits there contribute nothing and the queries need
+// no masking.  This costs ~0.2 VALU ops per dimension instead of the
+// popcount form's 2 per dimension per class, so large class counts stay
+// HBM-bound.
+//
+// Class operand table (built once per (classes, perforation) by
+// k_ham_table): for word w (relative to the first word of S), half h (low /
+// high dword) and class tile kt, 64 lanes x 16 bytes where lane l, byte
+// b = 4*pl + i holds class kt*32 + l%32 at dimension 64w + 32h + 8i + p with
+// plane p = 4*(l/32) + pl.
+#include <limits.h>
+
+#include "hdc_device.h"
+
+namespace hdc {
+
+// Shape per class-tile count: query tiles (32 queries) per wave, and words
+// per staged window (the class operand of a window takes WIN * 2 * KT KiB
+// of LDS beside the workgroup's query rows of WIN + 1 words).
+template <int KT> struct HmShape {
+    static constexpr int QT = KT == 4 ? 1 : 2;
+    static constexpr int WIN = KT == 4 ? 4 : 8;
+    static constexpr int ROWS = kWaves * QT * 32;   // queries per workgroup
+};
+
+struct HamLayout {
+    int w_lo, w_hi, KT;
+    size_t off_popc, total;
+    HamLayout(int start, int end, int K)
+    {
+        w_lo = start >> 6;
+        w_hi = (end + 63) >> 6;
+        KT = class_tiles(K);
+        const size_t tab = (size_t)(w_hi - w_lo) * 2 * KT * 1024;
+        off_popc = tab;
+        total = off_popc + 128 * 4;
+    }
+};
+
+size_t ham_workspace_bytes(int start, int end, int K) { return HamLayout(start, end, K).total; }
+
+__global__ __launch_bounds__(256) void k_ham_table(const uint64_t *__restrict__ C, int K, int64_t ldc, int start,
+                                                   int end, int stride, int w_lo, int KT, int64_t total,
+                                                   int8_t *__restrict__ tab)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total)
+        return;
+    const int lane = (int)(idx & 63);
+    const int kt = (int)((idx >> 6) % KT);
+    const int64_t wh = (idx >> 6) / KT;   // word * 2 + half
+    const int64_t w = w_lo + (wh >> 1);
+    const int h = (int)(wh & 1);
+    const int k = kt * 32 + (lane & 31), g = lane >> 5;
+    uint32_t o[4] = {0, 0, 0, 0};
+    if (k < K) {
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const int pl = b >> 2, i = b & 3, p = 4 * g + pl;
+            const int64_t d = w * 64 + 32 * h + 8 * i + p;
+            if (d >= start && d < end && (d - start) % stride == 0) {
+                const int bit = (int)((C[k * ldc + (d >> 6)] >> (d & 63)) & 1u);
+                const int c = bit ? -1 : 1;
+                const int v = c * (1 << (6 - pl));
+                o[pl] |= ((uint32_t)v & 0xffu) << (8 * i);
+            }
+        }
+    }
+    *(uint4 *)(tab + idx * 16) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// Bit planes of one query dword as the B operand of one MFMA; sh is 0 for
+// lanes of the first half and 4 for the second.
+__device__ __forceinline__ v4i planes(uint32_t d, uint32_t sh)
+{
+    const uint32_t e = d >> sh;
+    v4i b;
+    b[0] = (int)(e & 0x01010101u);
+    b[1] = (int)(e & 0x02020202u);
+    b[2] = (int)(e & 0x04040404u);
+    b[3] = (int)(e & 0x08080808u);
+    return b;
+}
+
+template <int KT>
+__global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq, int K,
+                                                      int w_lo, int w_hi, const int8_t *__restrict__ tab,
+                                                      const int32_t *__restrict__ popc, int32_t *__restrict__ argmin,
+                                                      int32_t *__restrict__ min_dist, int32_t *__restrict__ dists)
+{
+    constexpr int kHmQT = HmShape<KT>::QT, kHmWin = HmShape<KT>::WIN, ROWS = HmShape<KT>::ROWS;
+    __shared__ uint64_t qs[ROWS][kHmWin + 1];                 // odd row pitch: conflict-free column reads
+    __shared__ __align__(16) uint8_t ct[kHmWin * 2 * KT * 1024];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
+    const uint32_t sh = 4u * (uint32_t)g;
+    const int64_t rbase = (int64_t)blockIdx.x * ROWS;
+
+    v16i acc[KT][kHmQT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int qt = 0; qt < kHmQT; ++qt)
+            acc[kt][qt] = v16i{};
+
+    for (int w0 = w_lo; w0 < w_hi; w0 += kHmWin) {
+        const int nw = (w_hi - w0) < kHmWin ? (w_hi - w0) : kHmWin;
+        __syncthreads();   // previous window consumed
+        // queries: kHmWin lanes per row, consecutive words (coalesced rows)
+#pragma unroll
+        for (int p = 0; p < ROWS * kHmWin / 256; ++p) {
+            const int r = p * (256 / kHmWin) + t / kHmWin, ww = t % kHmWin;
+            const int64_t row = rbase + r;
+            uint64_t v = 0;
+            if (row < n && ww < nw)
+                v = Q[row * ldq + w0 + ww];
+            qs[r][ww] = v;
+        }
+        // class operand of the window, 16 bytes per thread per pass
+        {
+            const int64_t base = (int64_t)(w0 - w_lo) * 2 * KT * 1024;
+            const int bytes = nw * 2 * KT * 1024;
+            for (int o = t * 16; o < kHmWin * 2 * KT * 1024; o += 256 * 16) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (o < bytes)
+                    v = *(const uint4 *)(tab + base + o);
+                *(uint4 *)(ct + o) = v;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll 2
+        for (int ww = 0; ww < kHmWin; ++ww) {
+            uint64_t q[kHmQT];
+#pragma unroll
+            for (int qt = 0; qt < kHmQT; ++qt)
+                q[qt] = qs[(wave * kHmQT + qt) * 32 + (lane & 31)][ww];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                v4i af[KT];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    af[kt] = *(const v4i *)(ct + (((ww * 2 + h) * KT + kt) * 64 + lane) * 16);
+#pragma unroll
+                for (int qt = 0; qt < kHmQT; ++qt) {
+                    const v4i bf = planes(h ? (uint32_t)(q[qt] >> 32) : (uint32_t)q[qt], sh);
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt)
+                        acc[kt][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[kt], bf, acc[kt][qt], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    // argmin: lane holds query l%32 of each tile and classes 8(v/4)+4g+v%4
+#pragma unroll
+    for (int qt = 0; qt < kHmQT; ++qt) {
+        const int64_t q = rbase + (wave * kHmQT + qt) * 32 + (lane & 31);
+        int bd = INT_MAX, bk = 0;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int k = kt * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+                if (k < K) {
+                    const int d = popc[k] + (acc[kt][qt][v] >> 6);
+                    if (d < bd) { bd = d; bk = k; }
+                    if (dists && q < n)
+                        dists[q * K + k] = d;
+                }
+            }
+        const int od = __shfl_xor(bd, 32), ok = __shfl_xor(bk, 32);
+        if (od < bd || (od == bd && ok < bk)) { bd = od; bk = ok; }
+        if (g == 0 && q < n) {
+            argmin[q] = bk;
+            if (min_dist)
+                min_dist[q] = bd;
+        }
+    }
+}
+
+hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, int end, int stride, uint8_t *ws,
+                              hipStream_t st)
+{
+    const HamLayout L(start, end, K);
+    const int64_t total = (int64_t)(L.w_hi - L.w_lo) * 2 * L.KT * 64;
+    hipLaunchKernelGGL(k_ham_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc, start, end,
+                       stride, L.w_lo, L.KT, total, (int8_t *)ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int nd = (end - start + stride - 1) / stride;
+    return launch_class_popc(C, K, ldc, start, stride, nd, L.KT, (int32_t *)(ws + L.off_popc), st);
+}
+
+hipError_t launch_ham_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K, int start, int end,
+                               const uint8_t *ws, int32_t *argmin, int32_t *min_dist, int32_t *dists,
+                               hipStream_t st)
+{
+    const HamLayout L(start, end, K);
+    const int8_t *tab = (const int8_t *)ws;
+    const int32_t *popc = (const int32_t *)(ws + L.off_popc);
+#define HDC_HM_CASE(KT_)                                                                                       \
+    if (L.KT == KT_) {                                                                                         \
+        constexpr int R = HmShape<KT_>::ROWS;                                                                  \
+        hipLaunchKernelGGL(k_hamming_mfma<KT_>, dim3((unsigned)((n + R - 1) / R)), dim3(256), 0, st, Q, n, ldq, \
+                           K, L.w_lo, L.w_hi, tab, popc, argmin, min_dist, dists);                             \
+        return hipGetLastError();                                                                              \
+    }
+    HDC_HM_CASE(1)
+    HDC_HM_CASE(2)
+    HDC_HM_CASE(4)
+#undef HDC_HM_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hdc

@@ -58,6 +58,14 @@ inline size_t class_table_bytes(int nd, int K) { return (size_t)chunks(nd) * cla
 hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st);
 hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,
                               int8_t *tab, int32_t *cpop, hipStream_t st);
+hipError_t launch_class_popc(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd, int KT,
+                             int32_t *cpop, hipStream_t st);
+size_t ham_workspace_bytes(int start, int end, int K);
+hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, int end, int stride, uint8_t *ws,
+                              hipStream_t st);
+hipError_t launch_ham_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K, int start, int end,
+                               const uint8_t *ws, int32_t *argmin, int32_t *min_dist, int32_t *dists,
+                               hipStream_t st);
 hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K,
                           int64_t ldc, int start, int end, int stride, int32_t *argmin,
                           int32_t *min_dist, int32_t *dists, hipStream_t st);

@@ -63,6 +63,13 @@ __global__ __launch_bounds__(256) void k_class_popc(const uint64_t *__restrict__
         popc[k] = part[0];
 }
 
+hipError_t launch_class_popc(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd, int KT,
+                             int32_t *cpop, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_class_popc, dim3(KT * 32), dim3(256), 0, st, C, K, ldc, s0, stride, nd, cpop);
+    return hipGetLastError();
+}
+
 hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,
                               int8_t *tab, int32_t *cpop, hipStream_t st)
 {
@@ -76,10 +83,13 @@ hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int
 
 // ---------------------------------------------------------------------------
 // Hamming distance + argmin over packed hypervectors (unfused path).  One
-// query per lane; the wave's 64 query rows are staged through LDS a window
-// of 16 words at a time with coalesced loads; the class words are uniform
-// across the wave; the perforation mask of every word is precomputed per
-// workgroup.  Distances accumulate in KB registers per lane.
+// query per lane.  Per window of 16 words the workgroup stages (a) each
+// wave's 64 query rows with coalesced 16-byte loads and (b) the 16 words of
+// every class, already ANDed with the perforation mask, into LDS; the inner
+// loop is branch-free: the query word is masked once, every class word is an
+// LDS broadcast read, and each (class, word) costs 2 xor + 2 popcount-
+// accumulate.  Classes are compiled in buckets of KB (rows K..KB-1 are zero
+// and their distances are ignored); words past the end are zero.
 // ---------------------------------------------------------------------------
 constexpr int kHamWin = 16;
 constexpr int kHamMaxWords = 1024;   // hypervectors up to 65536 bits
@@ -91,6 +101,7 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q,
                                                  int32_t *__restrict__ min_dist, int32_t *__restrict__ dists)
 {
     __shared__ uint64_t qs[kWaves][64][kHamWin + 1];
+    __shared__ uint64_t cls[KB][kHamWin];
     __shared__ uint64_t msk[kHamMaxWords];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int w_lo = start >> 6, w_hi = (end + 63) >> 6;
@@ -103,7 +114,6 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q,
             m |= 1ull << (d & 63);
         msk[w - w_lo] = m;
     }
-    __syncthreads();
 
     const int64_t rbase = (int64_t)blockIdx.x * 256 + wave * 64;
     int dist[KB];
@@ -112,7 +122,8 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q,
         dist[k] = 0;
 
     for (int w0 = w_lo; w0 < w_hi; w0 += kHamWin) {
-        // stage 64 rows x 16 words: 16 lanes per row, 4 rows per pass
+        __syncthreads();   // masks ready / previous window consumed
+        // query tile: 64 rows x 16 words, 16 lanes per row, 4 rows per pass
 #pragma unroll
         for (int p = 0; p < 16; ++p) {
             const int r = 4 * p + (lane >> 4), ww = lane & 15;
@@ -122,18 +133,26 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q,
                 v = Q[row * ldq + w0 + ww];
             qs[wave][r][ww] = v;
         }
-        __builtin_amdgcn_wave_barrier();
-        const int nw = (w_hi - w0) < kHamWin ? (w_hi - w0) : kHamWin;
-        for (int ww = 0; ww < nw; ++ww) {
-            const uint64_t q = qs[wave][lane][ww];
-            const uint64_t m = msk[w0 + ww - w_lo];
-            const uint64_t *cw = C + w0 + ww;
-#pragma unroll
-            for (int k = 0; k < KB; ++k)
-                if (k < K)
-                    dist[k] += __popcll((q ^ cw[(int64_t)k * ldc]) & m);
+        // class window, masked by S
+        for (int i = t; i < KB * kHamWin; i += 256) {
+            const int k = i / kHamWin, ww = i % kHamWin;
+            uint64_t v = 0;
+            if (k < K && w0 + ww < w_hi)
+                v = C[(int64_t)k * ldc + w0 + ww] & msk[w0 + ww - w_lo];
+            cls[k][ww] = v;
         }
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+#pragma unroll 2
+        for (int ww = 0; ww < kHamWin; ++ww) {
+            const uint64_t m = (w0 + ww < w_hi) ? msk[w0 + ww - w_lo] : 0ull;
+            const uint64_t q = qs[wave][lane][ww] & m;
+            const uint32_t ql = (uint32_t)q, qh = (uint32_t)(q >> 32);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const uint64_t c = cls[k][ww];
+                dist[k] += __popc(ql ^ (uint32_t)c) + __popc(qh ^ (uint32_t)(c >> 32));
+            }
+        }
     }
 
     const int64_t row = rbase + lane;
@@ -152,22 +171,31 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t *__restrict__ Q,
         min_dist[row] = bd;
 }
 
+#define HDC_HAM_CASE(KB_)                                                                                      \
+    if (K <= KB_) {                                                                                            \
+        hipLaunchKernelGGL(k_hamming<KB_>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, \
+                           min_dist, dists);                                                                   \
+        return hipGetLastError();                                                                              \
+    }
+
 hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
                           int start, int end, int stride, int32_t *argmin, int32_t *min_dist,
                           int32_t *dists, hipStream_t st)
 {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    if (K <= 8)
-        hipLaunchKernelGGL(k_hamming<8>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
-    else if (K <= 16)
-        hipLaunchKernelGGL(k_hamming<16>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
-    else if (K <= 32)
-        hipLaunchKernelGGL(k_hamming<32>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
-    else if (K <= 64)
-        hipLaunchKernelGGL(k_hamming<64>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
-    else
-        hipLaunchKernelGGL(k_hamming<128>, grid, block, 0, st, Q, n, ldq, C, K, ldc, start, end, stride, argmin, min_dist, dists);
-    return hipGetLastError();
+    HDC_HAM_CASE(4)
+    HDC_HAM_CASE(8)
+    HDC_HAM_CASE(12)
+    HDC_HAM_CASE(16)
+    HDC_HAM_CASE(20)
+    HDC_HAM_CASE(24)
+    HDC_HAM_CASE(28)
+    HDC_HAM_CASE(32)
+    HDC_HAM_CASE(48)
+    HDC_HAM_CASE(64)
+    HDC_HAM_CASE(100)
+    HDC_HAM_CASE(128)
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

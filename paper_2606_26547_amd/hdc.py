@@ -32,7 +32,8 @@ DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP
 STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
-           "hdc_bundle", "hdc_hamming_argmin", "hdc_classify_workspace_bytes", "hdc_classify",
+           "hdc_bundle", "hdc_hamming_argmin", "hdc_hamming_workspace_bytes", "hdc_hamming_prepare",
+           "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
            "hdc_convert_features"]
@@ -66,6 +67,10 @@ _lib.hdc_bundle_workspace_bytes.restype = _sz
 _lib.hdc_bundle_workspace_bytes.argtypes = [_i32, _i32]
 _lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
 _lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, _p, _p, _p]
+_lib.hdc_hamming_workspace_bytes.restype = _sz
+_lib.hdc_hamming_workspace_bytes.argtypes = [Dims, _i32]
+_lib.hdc_hamming_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
+_lib.hdc_hamming_argmin_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, _p, _p, _p, _p, _sz]
 _lib.hdc_classify_workspace_bytes.restype = _sz
 _lib.hdc_classify_workspace_bytes.argtypes = [_i32, _i32]
 _lib.hdc_classify.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i32,
@@ -172,6 +177,33 @@ def hamming_argmin(Q: torch.Tensor, Cw: torch.Tensor, start: int, end: int, stri
                                    Dims(start, end, stride), _ptr(lab), _ptr(mn), _ptr(dists)),
            "hdc_hamming_argmin")
     return lab, mn, dists
+
+
+def hamming_workspace_bytes(start: int, end: int, stride: int, K: int) -> int:
+    return int(_lib.hdc_hamming_workspace_bytes(Dims(start, end, stride), K))
+
+
+class HammingPrepared:
+    """Class hypervectors of one (classes, perforation) turned into the
+    matrix-core operand once; each call searches a batch of query
+    hypervectors against them (hdc_hamming_argmin_prepared)."""
+
+    def __init__(self, Cw: torch.Tensor, start: int, end: int, stride: int = 1):
+        self.K, self.perf = Cw.shape[0], Dims(start, end, stride)
+        need = hamming_workspace_bytes(start, end, stride, self.K)
+        self.ws = torch.empty(max(need, 16), dtype=torch.uint8, device=Cw.device)
+        _check(_lib.hdc_hamming_prepare(_stream(), _ptr(Cw), self.K, Cw.shape[1], self.perf, _ptr(self.ws),
+                                        self.ws.numel()), "hdc_hamming_prepare")
+
+    def __call__(self, Q: torch.Tensor, with_min=False, with_dists=False, out: torch.Tensor | None = None):
+        n = Q.shape[0]
+        lab = out if out is not None else torch.empty(n, dtype=torch.int32, device=Q.device)
+        mn = torch.empty(n, dtype=torch.int32, device=Q.device) if with_min else None
+        dists = torch.empty((n, self.K), dtype=torch.int32, device=Q.device) if with_dists else None
+        _check(_lib.hdc_hamming_argmin_prepared(_stream(), _ptr(Q), n, Q.shape[1], self.K, self.perf, _ptr(lab),
+                                                _ptr(mn), _ptr(dists), _ptr(self.ws), self.ws.numel()),
+               "hdc_hamming_argmin_prepared")
+        return lab, mn, dists
 
 
 def classify_workspace_bytes(n_dims: int, K: int) -> int:

@@ -133,6 +133,51 @@ def test_hamming_argmin_bit_exact(hdc, case):
     assert np.array_equal(mn.cpu().numpy(), mref)
 
 
+@pytest.mark.parametrize("case", HAM_CASES + [(40, 65536, 128, (0, 65536, 1)), (300, 10240, 64, (64, 9000, 1))],
+                         ids=str)
+def test_hamming_prepared_bit_exact(hdc, case):
+    """Matrix-core search against prepared classes: equal to the oracle and
+    reusable across batches."""
+    n, nbits, K, (s, e, k) = case
+    say("hamming_prepared", case)
+    g = np.random.default_rng(n * 11 + K)
+    W = (nbits + 63) // 64
+    Q = g.integers(0, 2 ** 63, size=(n, W), dtype=np.int64).view(np.uint64)
+    Cw = g.integers(0, 2 ** 63, size=(K, W), dtype=np.int64).view(np.uint64)
+    if K >= 3:
+        Cw[2] = Cw[0]
+    dref = O.hamming(Q, Cw, s, e, k)
+    lref, mref = O.argmin(dref)
+    prep = hdc.HammingPrepared(dev(Cw.view(np.int64)), s, e, k)
+    for rows in (slice(0, n), slice(n // 3, n)):
+        lab, mn, dists = prep(dev(Q[rows].view(np.int64)), True, True)
+        torch.cuda.synchronize()
+        assert np.array_equal(dists.cpu().numpy(), dref[rows])
+        assert np.array_equal(lab.cpu().numpy(), lref[rows])
+        assert np.array_equal(mn.cpu().numpy(), mref[rows])
+
+
+def test_hamming_prepared_full_size(hdc):
+    """2^18 speech-shaped queries (D = 10240, 26 classes) and a perforated
+    search: both search kernels agree everywhere, the oracle on a sample."""
+    n, D, K = 1 << 18, 10240, 26
+    say("hamming_prepared_full", n, D, K)
+    g = torch.Generator(device="cuda").manual_seed(17)
+    Qd = torch.randint(-2 ** 63, 2 ** 63 - 1, (n, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    Cd = torch.randint(-2 ** 63, 2 ** 63 - 1, (K, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    for (s, e, k) in [(0, D, 1), (0, 4096, 2)]:
+        prep = hdc.HammingPrepared(Cd, s, e, k)
+        lab, mn, _ = prep(Qd, True)
+        lab2, mn2, _ = hdc.hamming_argmin(Qd, Cd, s, e, k, True)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, lab2) and torch.equal(mn, mn2)
+        idx = torch.arange(0, n, 997, device="cuda")
+        Qs = Qd[idx].cpu().numpy().view(np.uint64)
+        lref, mref = O.argmin(O.hamming(Qs, Cd.cpu().numpy().view(np.uint64), s, e, k))
+        assert np.array_equal(lab[idx].cpu().numpy(), lref)
+        assert np.array_equal(mn[idx].cpu().numpy(), mref)
+
+
 CLS_CASES = [
     # n, F, D, K, x_type, compute, (start, d_trunc, stride)
     (1, 64, 64, 2, "int8", "int8", None),

@@ -8,7 +8,9 @@
 namespace hdc {
 
 template <int CT, int XF, int QT, int KS, int KT, int MODE>
-__global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(Encoder<CT, XF, QT, KS, KT, MODE>::WAVES)))
+void k_encode(EncodeArgs a)
 {
     typedef Encoder<CT, XF, QT, KS, KT, MODE> E;
     __shared__ __align__(16) uint8_t smem[E::LDS];

@@ -6,7 +6,7 @@
 // and written to one half of a double-buffered LDS area while the current
 // chunk is multiplied on the matrix cores (rows = dimensions, columns =
 // queries).  The 32x32 accumulator of each query tile then goes through one
-// of two epilogues:
+// of two epilogues, which run between the MFMAs of the following chunk:
 //   M_ENCODE   sign -> packed bits, one uint32 half-word per query per chunk
 //   M_CLASSIFY sign -> {0,-1} bytes laid out as the B operand of a second
 //              int8 MFMA against the +-1 class bytes of the same 32
@@ -21,7 +21,7 @@
 
 namespace hdc {
 
-template <int CT, int XF, int QT, int KS, int KT, int MODE, bool PIPE = false>
+template <int CT, int XF, int QT, int KS, int KT, int MODE, int WV = 0>
 struct Encoder {
     typedef Tr<CT> T;
     typedef typename T::frag frag;
@@ -31,13 +31,18 @@ struct Encoder {
     static constexpr int RSB = KS * KB + 16;               // LDS row stride (16 B skew)
     static constexpr int PIECES = (KS * KSTEP + 15) / 16;  // 16-byte int8 pieces per row (max)
     static constexpr int MP = (PIECES + 7) / 8;            // pieces per thread (8 threads / row)
-    // Three LDS stages (software-pipelined loop) when they fit beside a second
-    // workgroup's worth of headroom, else two (plain double buffering).
-    static constexpr int NBUF = PIPE ? 3 : 2;
+    static constexpr int NBUF = 2;                         // double-buffered LDS stage
     static constexpr int OFF_C = NBUF * kDimChunk * RSB;
     static constexpr int OFF_CS = OFF_C + (MODE == M_CLASSIFY ? NBUF * KT * 1024 : 0);
     static constexpr int LDS = OFF_CS + NBUF * kDimChunk * 4;
     static constexpr int QPW = QT * 32;                    // queries per wave
+    // Waves per SIMD the kernel is compiled for (WV, or by default two where
+    // the resident query operand leaves room, so that one wave's stalls are
+    // covered by the other's MFMAs, else one).
+    static constexpr int WAVES = WV ? WV
+                                    : ((QT == 1 && KT == 1 &&
+                                        ((CT == C_I8 && KS <= 20) || (CT == C_BF16 && KS <= 16) ||
+                                         (CT == C_F32 && KS <= 64))) ? 2 : 1);
     static constexpr int QPB = QPW * kWaves;               // queries per workgroup
 
     // ---------------------------------------------------------------- X
@@ -242,49 +247,58 @@ struct Encoder {
     }
 
     // ------------------------------------------------------------ compute
-    // Fixed-length, branch-free K loop over the chunk in LDS with the next
-    // projection fragment read while the current one is multiplied (steps
-    // past the feature count read zero-filled LDS against zero features).
+    // A dependent MFMA chain issues at half rate on gfx950 (the result
+    // latency is twice the issue interval).  Two waves per SIMD hide that
+    // for each other; a single-tile wave compiled for one wave per SIMD
+    // alternates its K steps between KC = 2 accumulators instead, added in
+    // the epilogue: exact for int32, and order-free for the float rungs on
+    // integer-valued features (sums below 2^24).
+    static constexpr int KC = (QT == 1 && WAVES == 1 && KS >= 2) ? 2 : 1;
+    typedef acc_t Parts[QT][KC];
+    static constexpr int kPhases = 4 * QT;   // epilogue phases (see Epilogue)
+
     struct NoHook {
         __device__ __forceinline__ void operator()(int) const {}
     };
-    static constexpr int kMaxPhases = 8;   // epilogue phases a hook may run
 
-    static __device__ __forceinline__ void chunk_mma(acc_t (&acc)[QT], const frag (&xr)[QT][KS],
-                                                     const lds_u8 *lp, int lane)
-    {
-        chunk_mma(acc, xr, lp, lane, NoHook{});
-    }
-
-    // hook(p) runs phase p of another chunk's epilogue right after the
-    // MFMAs of step p, so its VALU work issues while the matrix core is busy;
+    // Fixed-length, branch-free K loop over the chunk in LDS with PD
+    // projection fragments in flight (steps past the feature count read
+    // zero-filled LDS against zero features).  Chain 0 of every tile starts
+    // from the uint8 correction 128 * sum_i p_i of its rows (0 otherwise).
+    // hook(p) runs phase p of the previous chunk's epilogue after the MFMAs
+    // of step p * SP, so its VALU work issues while the matrix core is busy;
     // phases past the last step run after the loop.
     template <class Hook>
-    static __device__ __forceinline__ void chunk_mma(acc_t (&acc)[QT], const frag (&xr)[QT][KS],
-                                                     const lds_u8 *lp, int lane, const Hook &hook)
+    static __device__ __forceinline__ void chunk_mma(Parts &part, const frag (&xr)[QT][KS], const lds_u8 *lp,
+                                                     const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
     {
         const int g = lane >> 5, row = lane & 31;
-        // A dependent MFMA chain issues at half rate on gfx950 (the result
-        // latency is twice the issue interval), so with one query tile the
-        // K steps alternate between two accumulators (KC chains) that are
-        // added at the end: exact for int32, and order-free for the float
-        // rungs on integer-valued features (sums below 2^24).
-        constexpr int KC = (QT == 1 && KS >= 2) ? 2 : 1;
-        acc_t part[QT][KC];
+        const lds_u8 *base = lp + row * RSB + g * (KB / 2);
+        constexpr int PDW = (CT == C_I8 && QT == 1 && WAVES == 1) ? 4 : (CT == C_F32 ? 4 : 2);
+        constexpr int PD = KS < PDW ? KS : PDW;
+        constexpr int SP = KS >= 2 * kPhases ? 2 : 1;
+        frag f[PD];
+#pragma unroll
+        for (int s = 0; s < PD; ++s)
+            f[s] = *(const HDC_LDS frag *)(base + s * KB);
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
             for (int k = 0; k < KC; ++k)
                 part[qt][k] = acc_t{};
-        const lds_u8 *base = lp + row * RSB + g * (KB / 2);
-        // PD fragments in flight; the scheduling barriers keep each read
-        // PD steps ahead of its use instead of next to it.
-        constexpr int PDW = (CT == C_I8 && QT == 1) ? 4 : (CT == C_F32 ? 4 : 2);
-        constexpr int PD = KS < PDW ? KS : PDW;
-        frag f[PD];
+        if constexpr (CT == C_I8) {
+            if (colsum) {
 #pragma unroll
-        for (int s = 0; s < PD; ++s)
-            f[s] = *(const HDC_LDS frag *)(base + s * KB);
+                for (int j = 0; j < 4; ++j) {
+                    const v4i cs = *(const lds_v4i *)(lcs + 8 * j + 4 * g);
+#pragma unroll
+                    for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            part[qt][0][4 * j + i] = 128 * cs[i];
+                }
+            }
+        }
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const frag cur = f[s % PD];
@@ -293,130 +307,77 @@ struct Encoder {
 #pragma unroll
             for (int qt = 0; qt < QT; ++qt)
                 mma(part[qt][s % KC], cur, xr[qt][s]);
-            hook(s);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (CT == C_FP8) {
-            // The 16-pass E4M3 MFMA's last accumulator register was observed
-            // to be read one wait state too early by the compiler-inserted
-            // hazard padding (a wrong sign in register 15 right after the
-            // loop); sleeping ~64 clocks keeps every read past the window.
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_sleep(1);
+            if (s % SP == 0 && s / SP < kPhases)
+                hook(s / SP);
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int qt = 0; qt < QT; ++qt) {
-            acc[qt] = part[qt][0];
-            if constexpr (KC == 2)
-                acc[qt] += part[qt][1];
-        }
-#pragma unroll
-        for (int p = KS; p < kMaxPhases; ++p)
+        for (int p = (KS + SP - 1) / SP; p < kPhases; ++p)
             hook(p);
     }
 
-    // Sign words of one tile, with the uint8 column-sum correction.
-    static __device__ __forceinline__ void signs(uint32_t (&w)[16], const acc_t &acc, const lds_i32 *lcs,
-                                                 bool colsum, int g)
-    {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            if constexpr (CT == C_I8) {
-                int y = acc[v];
-                if (colsum)
-                    y += 128 * lcs[8 * (v >> 2) + 4 * g + (v & 3)];
-                w[v] = sign_word(y);
-            } else {
-                w[v] = sign_word(acc[v]);
-            }
-        }
-    }
-
-    // ------------------------------------------------------------ body
-    // Runs the whole dimension loop for the queries of this workgroup.
-    // Returns the class accumulators (classify mode) through dacc.
-    static __device__ __forceinline__ void run(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
-                                               v16i (&dacc)[KT][QT])
-    {
-        if constexpr (NBUF == 3)
-            run_pipe(a, smem, qblock, dacc);
-        else
-            run_db(a, smem, qblock, dacc);
-    }
-
-    // Epilogue of one chunk split into phases (see chunk_mma's hook).
-    //   classify: phase 0 reads the class fragments; per query tile qt,
-    //             phases 1+3qt and 2+3qt turn the signs into {0,-1} bytes
-    //             and phase 3+3qt runs the Hamming MFMAs.
-    //   encode:   per query tile, phase 3qt packs the first 8 signs, 1+3qt
-    //             the rest (and joins the lane halves), 2+3qt stores.
+    // Epilogue of one chunk split into phases; per query tile qt:
+    //   4qt     adds the KC partial accumulators
+    //   classify: 4qt+1, 4qt+2 turn the signs into {0,-1} bytes (the B
+    //             operand), 4qt+3 runs the Hamming MFMAs against the class
+    //             fragments of the chunk
+    //   encode:   4qt+1, 4qt+2 pack the 16 signs of the lane and join the
+    //             two lane halves, 4qt+3 stores the 32-bit word
     struct Epilogue {
         const EncodeArgs &a;
-        const acc_t (&acc)[QT];
+        Parts &part;
         v16i (&dacc)[KT][QT];
-        const lds_u8 *lc;
-        const lds_i32 *lcs;
+        const v4i (&cf)[KT];
         int c, lane, g;
         int64_t qbase;
-        bool colsum;
-        mutable v4i cf[KT];
         mutable v4i mb[QT];
         mutable uint32_t bits[QT];
 
-        __device__ __forceinline__ uint32_t sw(int qt, int v) const
-        {
-            if constexpr (CT == C_I8) {
-                int y = acc[qt][v];
-                if (colsum)
-                    y += 128 * lcs[8 * (v >> 2) + 4 * g + (v & 3)];
-                return sign_word(y);
-            } else {
-                return sign_word(acc[qt][v]);
-            }
-        }
-
         __device__ __forceinline__ void operator()(int p) const
         {
-            if constexpr (MODE == M_CLASSIFY) {
-                if (p == 0) {
 #pragma unroll
-                    for (int kt = 0; kt < KT; ++kt)
-                        cf[kt] = *(const lds_v4i *)(lc + (kt * 64 + lane) * 16);
-                    return;
-                }
+            for (int qt = 0; qt < QT; ++qt) {
+                const int ph = p - 4 * qt;
+                const acc_t &y = part[qt][0];
+                if (ph == 0) {
+                    if constexpr (CT == C_FP8) {
+                        // The 16-pass E4M3 MFMA's accumulator was observed to
+                        // be read one wait state early by the compiler-inserted
+                        // hazard padding; extra wait states keep the read clear.
+                        __builtin_amdgcn_sched_barrier(0);
+                        asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if constexpr (KC == 2)
+                        part[qt][0] += part[qt][1];
+                } else if (ph == 1 || ph == 2) {
+                    if constexpr (MODE == M_CLASSIFY) {
 #pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    const int ph = p - 1 - 3 * qt;
-                    if (ph == 0 || ph == 1) {
-#pragma unroll
-                        for (int e = 2 * ph; e < 2 * ph + 2; ++e) {
+                        for (int e = 2 * (ph - 1); e < 2 * ph; ++e) {
                             // bytes: 0xFF where the projection is negative, else 0
-                            uint32_t t0 = __builtin_amdgcn_perm(sw(qt, 4 * e + 1), sw(qt, 4 * e), 0x0C0C0B09u);
-                            uint32_t t1 = __builtin_amdgcn_perm(sw(qt, 4 * e + 3), sw(qt, 4 * e + 2), 0x0B090C0Cu);
+                            const uint32_t t0 = __builtin_amdgcn_perm(sign_word(y[4 * e + 1]),
+                                                                      sign_word(y[4 * e]), 0x0C0C0B09u);
+                            const uint32_t t1 = __builtin_amdgcn_perm(sign_word(y[4 * e + 3]),
+                                                                      sign_word(y[4 * e + 2]), 0x0B090C0Cu);
                             mb[qt][e] = (int)(t0 | t1);
                         }
-                    } else if (ph == 2) {
+                    } else {
+                        uint32_t b = ph == 1 ? 0u : bits[qt];
 #pragma unroll
-                        for (int kt = 0; kt < KT; ++kt)
-                            mma(dacc[kt][qt], cf[kt], mb[qt]);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    const int ph = p - 3 * qt;
-                    if (ph == 0 || ph == 1) {
-                        uint32_t b = ph == 0 ? 0u : bits[qt];
-#pragma unroll
-                        for (int v = 8 * ph; v < 8 * ph + 8; ++v)
-                            b |= (sw(qt, v) >> 31) << (8 * (v >> 2) + (v & 3));
-                        if (ph == 1) {
+                        for (int v = 8 * (ph - 1); v < 8 * ph; ++v)
+                            b |= (sign_word(y[v]) >> 31) << (8 * (v >> 2) + (v & 3));
+                        if (ph == 2) {
                             b <<= 4 * g;
                             b |= (uint32_t)__shfl_xor((int)b, 32);
                         }
                         bits[qt] = b;
-                    } else if (ph == 2) {
+                    }
+                } else if (ph == 3) {
+                    if constexpr (MODE == M_CLASSIFY) {
+#pragma unroll
+                        for (int kt = 0; kt < KT; ++kt)
+                            mma(dacc[kt][qt], cf[kt], mb[qt]);
+                    } else {
                         const int64_t q = qbase + qt * 32 + (lane & 31);
                         if (g == 0 && q < a.n)
                             a.H32[q * a.ldh32 + c] = bits[qt];
@@ -426,110 +387,16 @@ struct Encoder {
         }
     };
 
-    // Software-pipelined loop over a ring of three LDS stages: iteration c
-    // prefetches chunk c+2 into registers, multiplies chunk c+1 while chunk
-    // c's epilogue runs between its MFMAs, stores chunk c+2 into the stage
-    // that chunk c-1 used, and synchronises once.  The two accumulator sets
-    // alternate, so the loop is unrolled by two.
-    static __device__ __forceinline__ void run_pipe(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
-                                                    v16i (&dacc)[KT][QT])
-    {
-        const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
-        const int64_t qbase = qblock + (int64_t)wave * QPW;
-        const int ks_used = (a.F + KSTEP - 1) / KSTEP;
-        const int npc = (ks_used * KSTEP + 15) / 16;
-        const int NC = (a.nd + kDimChunk - 1) / kDimChunk;
-        const bool colsum = CT == C_I8 && XF == 0 && a.x_type == X_UINT8;
-
-        frag xr[QT][KS];
-        load_x(xr, a, qbase, lane, ks_used);
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int qt = 0; qt < QT; ++qt)
-                dacc[kt][qt] = v16i{};
-
-        lds_u8 *L = (lds_u8 *)smem;
-        auto lp = [&](int i) { return L + i * (kDimChunk * RSB); };
-        auto lc = [&](int i) { return L + OFF_C + i * (KT * 1024); };
-        auto lcs = [&](int i) { return (lds_i32 *)(L + OFF_CS) + i * kDimChunk; };
-
-        uint4 pr[MP];
-        uint4 cr = make_uint4(0, 0, 0, 0);
-        zero_tails(lp(0), lp(1), t, npc);
-        zero_tails(lp(2), lp(2), t, npc);
-        stage_load(pr, a, 0, t, npc);
-        if constexpr (MODE == M_CLASSIFY)
-            cr = class_load(a, 0, t);
-        stage_store(lp(0), lcs(0), pr, a, 0, t, npc, colsum);
-        if constexpr (MODE == M_CLASSIFY)
-            class_store(lc(0), cr, t);
-        stage_load(pr, a, 1, t, npc);
-        if constexpr (MODE == M_CLASSIFY)
-            cr = class_load(a, NC > 1 ? 1 : 0, t);
-        if (NC > 1) {
-            stage_store(lp(1), lcs(1), pr, a, 1, t, npc, colsum);
-            if constexpr (MODE == M_CLASSIFY)
-                class_store(lc(1), cr, t);
-        }
-        __syncthreads();
-
-        acc_t A[QT], B[QT];
-        chunk_mma(A, xr, lp(0), lane);
-
-        // one pipelined iteration: epilogue of chunk c (accumulators cur,
-        // stage bc) interleaved with the MFMAs of chunk c+1 into nxt
-        auto body = [&](int c, int bc, const acc_t (&cur)[QT], acc_t (&nxt)[QT]) {
-            const int b1 = bc == 2 ? 0 : bc + 1, b2 = b1 == 2 ? 0 : b1 + 1;
-            stage_load(pr, a, c + 2, t, npc);
-            if constexpr (MODE == M_CLASSIFY)
-                cr = class_load(a, c + 2 < NC ? c + 2 : NC - 1, t);
-            Epilogue epi{a, cur, dacc, lc(bc), lcs(bc), c, lane, g, qbase, colsum};
-            chunk_mma(nxt, xr, lp(b1), lane, epi);
-            if (c + 2 < NC) {
-                stage_store(lp(b2), lcs(b2), pr, a, c + 2, t, npc, colsum);
-                if constexpr (MODE == M_CLASSIFY)
-                    class_store(lc(b2), cr, t);
-            }
-            __syncthreads();
-        };
-        auto last = [&](int c, int bc, const acc_t (&cur)[QT]) {
-            Epilogue epi{a, cur, dacc, lc(bc), lcs(bc), c, lane, g, qbase, colsum};
-#pragma unroll
-            for (int p = 0; p < kMaxPhases; ++p)
-                epi(p);
-        };
-
-        int bc = 0;
-        for (int c = 0;; c += 2) {
-            if (c + 1 >= NC) {
-                last(c, bc, A);
-                break;
-            }
-            body(c, bc, A, B);
-            bc = bc == 2 ? 0 : bc + 1;
-            if (c + 2 >= NC) {
-                last(c + 1, bc, B);
-                break;
-            }
-            body(c + 1, bc, B, A);
-            bc = bc == 2 ? 0 : bc + 1;
-        }
-        if constexpr (MODE == M_ENCODE) {
-            if (NC & 1) {   // high half of the last word holds no dimension
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    const int64_t q = qbase + qt * 32 + (lane & 31);
-                    if (g == 0 && q < a.n)
-                        a.H32[q * a.ldh32 + NC] = 0u;
-                }
-            }
-        }
-    }
-
-    // Plain double-buffered loop (used when three stages do not fit).
-    static __device__ __forceinline__ void run_db(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
-                                                  v16i (&dacc)[KT][QT])
+    // ------------------------------------------------------------ body
+    // Runs the whole dimension loop for the queries of this workgroup over a
+    // double-buffered LDS stage: step c prefetches chunk c+1 into registers,
+    // multiplies chunk c while chunk c-1's epilogue runs between its MFMAs,
+    // reads chunk c's class fragments into registers, stores chunk c+1 into
+    // the other buffer and synchronises once.  The two accumulator sets
+    // alternate, so the loop is unrolled by two.  Returns the class
+    // accumulators (classify mode) through dacc.
+    static __device__ __forceinline__ void run(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
+                                               v16i (&dacc)[KT][QT])
     {
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
         const int64_t qbase = qblock + (int64_t)wave * QPW;
@@ -562,52 +429,19 @@ struct Encoder {
             class_store(lc[0], cr, t);
         __syncthreads();
 
-        for (int c = 0; c < NC; ++c) {
-            const int b = c & 1;
+        v4i cf[KT];
+        auto step = [&](int c, int b, Parts &cur, const auto &hook) {
             const bool more = c + 1 < NC;
-            // prefetch the next chunk (the last iteration re-reads in-bounds
-            // data and discards it, keeping the loop free of branches)
+            // prefetch the next chunk (the last step re-reads in-bounds data
+            // and discards it, keeping the loop free of branches)
             stage_load(pr, a, c + 1, t, npc);
             if constexpr (MODE == M_CLASSIFY)
                 cr = class_load(a, more ? c + 1 : c, t);
-            acc_t acc[QT];
-            chunk_mma(acc, xr, lp[b], lane);
-            if constexpr (MODE == M_ENCODE) {
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    uint32_t w[16];
-                    signs(w, acc[qt], lcs[b], colsum, g);
-                    uint32_t bits = 0;
-#pragma unroll
-                    for (int v = 0; v < 16; ++v)
-                        bits |= (w[v] >> 31) << (8 * (v >> 2) + (v & 3));
-                    bits <<= 4 * g;
-                    bits |= (uint32_t)__shfl_xor((int)bits, 32);
-                    const int64_t q = qbase + qt * 32 + (lane & 31);
-                    if (g == 0 && q < a.n)
-                        a.H32[q * a.ldh32 + c] = bits;
-                }
-            } else {
-                v4i cf[KT];
+            chunk_mma(cur, xr, lp[b], lcs[b], colsum, lane, hook);
+            if constexpr (MODE == M_CLASSIFY) {
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt)
                     cf[kt] = *(const lds_v4i *)(lc[b] + (kt * 64 + lane) * 16);
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    uint32_t w[16];
-                    signs(w, acc[qt], lcs[b], colsum, g);
-                    v4i mb;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        // bytes: 0xFF where the projection is negative, else 0
-                        uint32_t t0 = __builtin_amdgcn_perm(w[4 * e + 1], w[4 * e], 0x0C0C0B09u);
-                        uint32_t t1 = __builtin_amdgcn_perm(w[4 * e + 3], w[4 * e + 2], 0x0B090C0Cu);
-                        mb[e] = (int)(t0 | t1);
-                    }
-#pragma unroll
-                    for (int kt = 0; kt < KT; ++kt)
-                        mma(dacc[kt][qt], cf[kt], mb);
-                }
             }
             if (more) {
                 stage_store(lp[b ^ 1], lcs[b ^ 1], pr, a, c + 1, t, npc, colsum);
@@ -615,6 +449,27 @@ struct Encoder {
                     class_store(lc[b ^ 1], cr, t);
             }
             __syncthreads();
+        };
+        auto last = [&](int c, Parts &prev) {
+            Epilogue epi{a, prev, dacc, cf, c, lane, g, qbase};
+#pragma unroll
+            for (int p = 0; p < kPhases; ++p)
+                epi(p);
+        };
+
+        Parts P0, P1;
+        step(0, 0, P0, NoHook{});
+        for (int c = 1;; c += 2) {
+            if (c >= NC) {
+                last(c - 1, P0);
+                break;
+            }
+            step(c, 1, P1, Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
+            if (c + 1 >= NC) {
+                last(c, P1);
+                break;
+            }
+            step(c + 1, 0, P0, Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
         }
         if constexpr (MODE == M_ENCODE) {
             if (NC & 1) {   // high half of the last word holds no dimension
@@ -627,7 +482,6 @@ struct Encoder {
             }
         }
     }
-
     // Argmin over the class accumulators; returns the label of this lane's
     // query (valid in lanes 0..31 of each tile) and optionally writes dists.
     static __device__ __forceinline__ void finish(const EncodeArgs &a, int64_t qblock,

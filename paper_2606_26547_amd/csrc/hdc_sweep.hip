@@ -148,7 +148,7 @@ template <int CT, int KS, int KT>
 __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
                                            hdc_config_result *res)
 {
-    typedef Encoder<CT, 0, kSweepQT, KS, KT, M_CLASSIFY> E;
+    typedef Encoder<CT, 0, kSweepQT, KS, KT, M_CLASSIFY, 1> E;
     v16i dacc[KT][kSweepQT];
     E::run(a, smem, qblock, dacc);
     int32_t lab[kSweepQT];
@@ -166,9 +166,9 @@ __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *sme
 
 template <int FB, int KT>
 struct SweepLds {
-    static constexpr int a = Encoder<C_I8, 0, kSweepQT, FB / 32, KT, M_CLASSIFY>::LDS;
-    static constexpr int b = Encoder<C_FP8, 0, kSweepQT, FB / 64, KT, M_CLASSIFY>::LDS;
-    static constexpr int c = Encoder<C_BF16, 0, kSweepQT, FB / 16, KT, M_CLASSIFY>::LDS;
+    static constexpr int a = Encoder<C_I8, 0, kSweepQT, FB / 32, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int b = Encoder<C_FP8, 0, kSweepQT, FB / 64, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int c = Encoder<C_BF16, 0, kSweepQT, FB / 16, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int ab = a > b ? a : b;
     static constexpr int value = ab > c ? ab : c;
 };

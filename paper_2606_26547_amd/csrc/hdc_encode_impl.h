@@ -7,12 +7,12 @@
 
 namespace hdc {
 
-template <int CT, int XF, int QT, int KS, int KT, int MODE>
+template <int CT, int XF, int QT, int KS, int KT, int MODE, bool DMA, int RT>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(Encoder<CT, XF, QT, KS, KT, MODE>::WAVES)))
+__attribute__((amdgpu_waves_per_eu(Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT>::WAVES)))
 void k_encode(EncodeArgs a)
 {
-    typedef Encoder<CT, XF, QT, KS, KT, MODE> E;
+    typedef Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT> E;
     __shared__ __align__(16) uint8_t smem[E::LDS];
     const int64_t qblock = (int64_t)blockIdx.x * E::QPB;
     v16i dacc[KT][QT];
@@ -30,13 +30,31 @@ void k_encode(EncodeArgs a)
     }
 }
 
-template <int CT, int XF, int QT, int KS, int KT, int MODE>
+template <int CT, int XF, int QT, int KS, int KT, int MODE, bool DMA = false, int RT = 1>
 static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
 {
-    typedef Encoder<CT, XF, QT, KS, KT, MODE> E;
+    typedef Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT> E;
     const int64_t blocks = (a.n + E::QPB - 1) / E::QPB;
-    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE, DMA, RT>), dim3((unsigned)blocks), dim3(256), 0, st,
+                       a);
     return hipGetLastError();
+}
+
+// int8 features on the int8 path stage the projection straight into LDS.
+// Where the registers allow, each wave (one per SIMD) multiplies two query
+// tiles by two row tiles per chunk: four independent accumulator chains,
+// each projection fragment read from LDS feeds two MFMAs, and a barrier
+// every 80 MFMAs.  Otherwise one tile of each, two waves per SIMD.
+template <int KS, int KT> struct BigTile {
+    static constexpr bool value = KS <= 20 && KT <= 2;
+};
+template <int KS, int KT, int MODE>
+static hipError_t launch_dma(const EncodeArgs &a, hipStream_t st)
+{
+    if constexpr (BigTile<KS, KT>::value)
+        return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 2>(a, st);
+    else
+        return launch_one<C_I8, 0, 1, KS, KT, MODE, true, 1>(a, st);
 }
 
 // Largest QT whose query registers fit comfortably beside the accumulators.
@@ -47,6 +65,18 @@ template <int CT, int KS> struct QtMax {
 template <int CT, int XF, int KS>
 static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStream_t st)
 {
+    if constexpr (CT == C_I8 && XF == 0) {
+        if (a.x_type == X_INT8) {
+            if (mode == M_ENCODE)
+                return launch_dma<KS, 1, M_ENCODE>(a, st);
+            const int kt = class_tiles(a.K);
+            if (kt == 1)
+                return launch_dma<KS, 1, M_CLASSIFY>(a, st);
+            if (kt == 2)
+                return launch_dma<KS, 2, M_CLASSIFY>(a, st);
+            return launch_dma<KS, 4, M_CLASSIFY>(a, st);
+        }
+    }
     constexpr int QM = QtMax<CT, KS>::value;
     const int qt = (tile.qt == 1 || QM == 1) ? 1 : 2;
     if (mode == M_ENCODE) {

@@ -21,7 +21,7 @@
 
 namespace hdc {
 
-template <int CT, int XF, int QT, int KS, int KT, int MODE, int WV = 0>
+template <int CT, int XF, int QT, int KS, int KT, int MODE, int WV = 0, bool DMA = false, int RT = 1>
 struct Encoder {
     typedef Tr<CT> T;
     typedef typename T::frag frag;
@@ -31,16 +31,31 @@ struct Encoder {
     static constexpr int RSB = KS * KB + 16;               // LDS row stride (16 B skew)
     static constexpr int PIECES = (KS * KSTEP + 15) / 16;  // 16-byte int8 pieces per row (max)
     static constexpr int MP = (PIECES + 7) / 8;            // pieces per thread (8 threads / row)
-    static constexpr int NBUF = 2;                         // double-buffered LDS stage
-    static constexpr int OFF_C = NBUF * kDimChunk * RSB;
-    static constexpr int OFF_CS = OFF_C + (MODE == M_CLASSIFY ? NBUF * KT * 1024 : 0);
-    static constexpr int LDS = OFF_CS + NBUF * kDimChunk * 4;
+    // DMA: int8 projection rows and class fragments go from global memory
+    // straight into LDS (global_load_lds, 16 bytes per lane; int8 features
+    // only, which need no column sums), three stages deep.  Each load fills
+    // 1 KiB of LDS contiguously, so a stage is NIW loads per wave and the
+    // units past the 32 rows land in the stage's slack.
+    // A chunk is RT row tiles of 32 dimensions (RT > 1 with DMA staging
+    // only); its class operand is RT * KT KiB.
+    static_assert(!DMA || (CT == C_I8 && XF == 0), "direct LDS staging is for int8 features on int8 MFMA");
+    static_assert(RT == 1 || DMA, "several row tiles per chunk need direct LDS staging");
+    static constexpr int CH = kDimChunk * RT;              // dimensions per chunk
+    static constexpr int UPR = RSB / 16;                   // 16-byte units per LDS row
+    static constexpr int NIW = (CH * UPR + 64 * kWaves - 1) / (64 * kWaves);
+    static constexpr int NCT = RT * KT;                    // class tiles per chunk
+    static constexpr int NCW = (NCT + kWaves - 1) / kWaves;   // class-tile loads per wave
+    static constexpr int NBUF = DMA ? 3 : 2;               // LDS stages
+    static constexpr int SSZ = DMA ? NIW * kWaves * 1024 : CH * RSB;   // bytes per stage
+    static constexpr int OFF_C = NBUF * SSZ;
+    static constexpr int OFF_CS = OFF_C + (MODE == M_CLASSIFY ? NBUF * NCT * 1024 : 0);
+    static constexpr int LDS = OFF_CS + (DMA ? 0 : NBUF * kDimChunk * 4);
     static constexpr int QPW = QT * 32;                    // queries per wave
     // Waves per SIMD the kernel is compiled for (WV, or by default two where
     // the resident query operand leaves room, so that one wave's stalls are
     // covered by the other's MFMAs, else one).
     static constexpr int WAVES = WV ? WV
-                                    : ((QT == 1 && KT == 1 &&
+                                    : ((QT == 1 && RT == 1 && KT == 1 &&
                                         ((CT == C_I8 && KS <= 20) || (CT == C_BF16 && KS <= 16) ||
                                          (CT == C_F32 && KS <= 64))) ? 2 : 1);
     static constexpr int QPB = QPW * kWaves;               // queries per workgroup
@@ -248,33 +263,35 @@ struct Encoder {
 
     // ------------------------------------------------------------ compute
     // A dependent MFMA chain issues at half rate on gfx950 (the result
-    // latency is twice the issue interval).  Two waves per SIMD hide that
-    // for each other; a single-tile wave compiled for one wave per SIMD
-    // alternates its K steps between KC = 2 accumulators instead, added in
-    // the epilogue: exact for int32, and order-free for the float rungs on
-    // integer-valued features (sums below 2^24).
-    static constexpr int KC = (QT == 1 && WAVES == 1 && KS >= 2) ? 2 : 1;
-    typedef acc_t Parts[QT][KC];
+    // latency is twice the issue interval), so a single-tile wave alternates
+    // its K steps between KC = 2 accumulators, added in the epilogue: exact
+    // for int32, and order-free for the float rungs on integer-valued
+    // features (sums below 2^24).  Register-staged kernels compiled for two
+    // waves per SIMD have no room for the second set and rely on the other
+    // wave instead; two query tiles are two chains already.
+    static constexpr int KC = (QT == 1 && (WAVES == 1 || DMA) && KS >= 2) ? 2 : 1;
+    typedef acc_t Parts[QT][KC];             // accumulators of one row tile
     static constexpr int kPhases = 4 * QT;   // epilogue phases (see Epilogue)
 
     struct NoHook {
         __device__ __forceinline__ void operator()(int) const {}
     };
 
-    // Fixed-length, branch-free K loop over the chunk in LDS with PD
-    // projection fragments in flight (steps past the feature count read
-    // zero-filled LDS against zero features).  Chain 0 of every tile starts
-    // from the uint8 correction 128 * sum_i p_i of its rows (0 otherwise).
-    // hook(p) runs phase p of the previous chunk's epilogue after the MFMAs
-    // of step p * SP, so its VALU work issues while the matrix core is busy;
-    // phases past the last step run after the loop.
+    // One pass over a row tile (32 dimensions) in LDS: a fixed-length,
+    // branch-free K loop with PD projection fragments in flight (steps past
+    // the feature count read zero-filled or finite LDS against zero
+    // features).  Chain 0 of every query tile starts from the uint8
+    // correction 128 * sum_i p_i of its rows (0 otherwise).  hook(p) runs
+    // phase p of the previous row tile's epilogue after the MFMAs of step
+    // p * SP, so its VALU work issues while the matrix core is busy; phases
+    // past the last step run after the loop.
     template <class Hook>
-    static __device__ __forceinline__ void chunk_mma(Parts &part, const frag (&xr)[QT][KS], const lds_u8 *lp,
-                                                     const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
+    static __device__ __forceinline__ void tile_mma(Parts &part, const frag (&xr)[QT][KS], const lds_u8 *lp,
+                                                    const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
     {
         const int g = lane >> 5, row = lane & 31;
         const lds_u8 *base = lp + row * RSB + g * (KB / 2);
-        constexpr int PDW = (CT == C_I8 && QT == 1 && WAVES == 1) ? 4 : (CT == C_F32 ? 4 : 2);
+        constexpr int PDW = (CT == C_I8 && (WAVES == 1 || DMA)) ? 4 : (CT == C_F32 ? 4 : 2);
         constexpr int PD = KS < PDW ? KS : PDW;
         constexpr int SP = KS >= 2 * kPhases ? 2 : 1;
         frag f[PD];
@@ -316,19 +333,21 @@ struct Encoder {
             hook(p);
     }
 
-    // Epilogue of one chunk split into phases; per query tile qt:
+    // Epilogue of row tile w (dimensions S_{32w .. 32w+31}) split into
+    // phases; per query tile qt:
     //   4qt     adds the KC partial accumulators
     //   classify: 4qt+1, 4qt+2 turn the signs into {0,-1} bytes (the B
     //             operand), 4qt+3 runs the Hamming MFMAs against the class
-    //             fragments of the chunk
-    //   encode:   4qt+1, 4qt+2 pack the 16 signs of the lane and join the
-    //             two lane halves, 4qt+3 stores the 32-bit word
+    //             fragments of the tile
+    //   encode:   4qt+1, 4qt+2 pack the 16 signs of the lane, join the two
+    //             lane halves and clear dimensions past the end, 4qt+3
+    //             stores the 32-bit word
     struct Epilogue {
         const EncodeArgs &a;
         Parts &part;
         v16i (&dacc)[KT][QT];
         const v4i (&cf)[KT];
-        int c, lane, g;
+        int w, lane, g;
         int64_t qbase;
         mutable v4i mb[QT];
         mutable uint32_t bits[QT];
@@ -369,6 +388,9 @@ struct Encoder {
                         if (ph == 2) {
                             b <<= 4 * g;
                             b |= (uint32_t)__shfl_xor((int)b, 32);
+                            const int nv = a.nd - w * kDimChunk;   // dimensions of this tile
+                            if (nv < 32)
+                                b &= nv > 0 ? (1u << nv) - 1u : 0u;
                         }
                         bits[qt] = b;
                     }
@@ -380,23 +402,40 @@ struct Encoder {
                     } else {
                         const int64_t q = qbase + qt * 32 + (lane & 31);
                         if (g == 0 && q < a.n)
-                            a.H32[q * a.ldh32 + c] = bits[qt];
+                            a.H32[q * a.ldh32 + w] = bits[qt];
                     }
                 }
             }
         }
     };
 
+    static __device__ __forceinline__ void run_epilogue(const Epilogue &epi)
+    {
+#pragma unroll
+        for (int p = 0; p < kPhases; ++p)
+            epi(p);
+    }
+
     // ------------------------------------------------------------ body
-    // Runs the whole dimension loop for the queries of this workgroup over a
-    // double-buffered LDS stage: step c prefetches chunk c+1 into registers,
-    // multiplies chunk c while chunk c-1's epilogue runs between its MFMAs,
-    // reads chunk c's class fragments into registers, stores chunk c+1 into
-    // the other buffer and synchronises once.  The two accumulator sets
-    // alternate, so the loop is unrolled by two.  Returns the class
-    // accumulators (classify mode) through dacc.
+    // Runs the whole dimension loop for the queries of this workgroup.
+    // Returns the class accumulators (classify mode) through dacc.
     static __device__ __forceinline__ void run(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
                                                v16i (&dacc)[KT][QT])
+    {
+        if constexpr (DMA)
+            run_dma(a, smem, qblock, dacc);
+        else
+            run_db(a, smem, qblock, dacc);
+    }
+
+    // Register-staged loop over a double-buffered LDS stage: step c
+    // prefetches chunk c+1 into registers, multiplies chunk c while chunk
+    // c-1's epilogue runs between its MFMAs, reads chunk c's class fragments
+    // into registers, stores chunk c+1 into the other buffer and
+    // synchronises once.  The two accumulator sets alternate, so the loop is
+    // unrolled by two.
+    static __device__ __forceinline__ void run_db(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
+                                                  v16i (&dacc)[KT][QT])
     {
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
         const int64_t qbase = qblock + (int64_t)wave * QPW;
@@ -437,7 +476,7 @@ struct Encoder {
             stage_load(pr, a, c + 1, t, npc);
             if constexpr (MODE == M_CLASSIFY)
                 cr = class_load(a, more ? c + 1 : c, t);
-            chunk_mma(cur, xr, lp[b], lcs[b], colsum, lane, hook);
+            tile_mma(cur, xr, lp[b], lcs[b], colsum, lane, hook);
             if constexpr (MODE == M_CLASSIFY) {
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt)
@@ -450,23 +489,17 @@ struct Encoder {
             }
             __syncthreads();
         };
-        auto last = [&](int c, Parts &prev) {
-            Epilogue epi{a, prev, dacc, cf, c, lane, g, qbase};
-#pragma unroll
-            for (int p = 0; p < kPhases; ++p)
-                epi(p);
-        };
 
         Parts P0, P1;
         step(0, 0, P0, NoHook{});
         for (int c = 1;; c += 2) {
             if (c >= NC) {
-                last(c - 1, P0);
+                run_epilogue(Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
                 break;
             }
             step(c, 1, P1, Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
             if (c + 1 >= NC) {
-                last(c, P1);
+                run_epilogue(Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
                 break;
             }
             step(c + 1, 0, P0, Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
@@ -482,6 +515,176 @@ struct Encoder {
             }
         }
     }
+
+    // ------------------------------------------------------------ DMA
+    // Source of each of this lane's NIW loads: LDS unit u = (i * 4 + wave) *
+    // 64 + lane of a stage is row u / UPR, piece u % UPR; the skew unit,
+    // pieces past the features and rows past the chunk re-read piece 0 of an
+    // in-bounds row (finite int8 against zero features, or slack).
+    struct DmaSrc {
+        int row[NIW];
+        int pb[NIW];
+    };
+    static __device__ __forceinline__ void dma_setup(DmaSrc &d, int wave, int lane, int npc)
+    {
+#pragma unroll
+        for (int i = 0; i < NIW; ++i) {
+            const int u = (i * kWaves + wave) * 64 + lane;
+            int r = u / UPR, p = u % UPR;
+            if (r >= CH) {
+                r = CH - 1;
+                p = 0;
+            }
+            d.row[i] = r;
+            d.pb[i] = 16 * (p < npc ? p : 0);
+        }
+    }
+    // Loads chunk c (clamped to the last chunk) into a stage and its class
+    // fragments (wave w loads class tiles (w + 4j) % NCT; duplicate tiles
+    // write the same bytes).  Every wave issues exactly NIW (+ NCW) loads.
+    // The class table holds a whole number of chunks (zero rows past nd).
+    static __device__ __forceinline__ void dma_issue(const EncodeArgs &a, const DmaSrc &d, int c, int NC,
+                                                     lds_u8 *stage, lds_u8 *lcls, int wave, int lane)
+    {
+        // byte offsets fit 32 bits: the projection holds at most 65536 rows
+        // of at most 1024 + padding bytes
+        const int cc = c < NC ? c : NC - 1;
+        const uint32_t rstep = (uint32_t)a.stride * (uint32_t)a.ldp;
+        const uint32_t base = (uint32_t)a.s0 * (uint32_t)a.ldp;
+        const int last = a.nd - 1 - cc * CH;   // rows past it re-read the last one
+#pragma unroll
+        for (int i = 0; i < NIW; ++i) {
+            const int r = d.row[i] < last ? d.row[i] : last;
+            const uint32_t off = base + (uint32_t)(cc * CH + r) * rstep + (uint32_t)d.pb[i];
+            __builtin_amdgcn_global_load_lds((const void *)(a.P + off),
+                                             (HDC_LDS void *)(stage + (i * kWaves + wave) * 1024), 16, 0, 0);
+        }
+        if constexpr (MODE == M_CLASSIFY) {
+#pragma unroll
+            for (int j = 0; j < NCW; ++j) {
+                const int tile = (wave + kWaves * j) % NCT;   // rt * KT + kt
+                const int8_t *src = a.ctab + ((int64_t)cc * NCT + tile) * 1024 + lane * 16;
+                __builtin_amdgcn_global_load_lds((const void *)src, (HDC_LDS void *)(lcls + tile * 1024), 16, 0, 0);
+            }
+        }
+    }
+    // Wait until at most G of this wave's vector memory operations are in
+    // flight (they complete in issue order, so everything older is done),
+    // drain LDS operations, and meet the other waves.
+    template <int G>
+    static __device__ __forceinline__ void dma_barrier()
+    {
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(G) : "memory");
+    }
+
+    // Three-stage loop: step c issues the loads of chunk c+2, multiplies the
+    // RT row tiles of chunk c one after the other (each with the previous row
+    // tile's epilogue between its MFMAs, the class fragments of each tile
+    // read into registers right after its pass), waits for chunk c+1's loads
+    // and synchronises once.  Row tile passes alternate between two
+    // accumulator sets: with RT = 2 that is fixed within a step, with RT = 1
+    // the loop is unrolled by two.
+    static __device__ __forceinline__ void run_dma(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
+                                                   v16i (&dacc)[KT][QT])
+    {
+        static_assert(RT == 1 || RT == 2, "one or two row tiles per chunk");
+        const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
+        const int64_t qbase = qblock + (int64_t)wave * QPW;
+        const int ks_used = (a.F + KSTEP - 1) / KSTEP;
+        const int npc = (ks_used * KSTEP + 15) / 16;
+        const int NC = (a.nd + CH - 1) / CH;
+        // loads issued per step after those of the chunk waited for (stores
+        // of the encode epilogue are not counted: waiting for more is safe)
+        constexpr int G = NIW + (MODE == M_CLASSIFY ? NCW : 0);
+
+        frag xr[QT][KS];
+        load_x(xr, a, qbase, lane, ks_used);
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt)
+                dacc[kt][qt] = v16i{};
+
+        lds_u8 *L = (lds_u8 *)smem;
+        auto lp = [&](int i) { return L + i * SSZ; };
+        auto lc = [&](int i) { return L + OFF_C + i * (NCT * 1024); };
+        DmaSrc ds;
+        dma_setup(ds, wave, lane, npc);
+        dma_issue(a, ds, 0, NC, lp(0), lc(0), wave, lane);
+        dma_issue(a, ds, 1, NC, lp(1), lc(1), wave, lane);
+        dma_barrier<G>();
+
+        v4i cf[KT];
+        int b = 0;   // stage of the chunk being multiplied
+        auto read_cf = [&](int rt) {
+            if constexpr (MODE == M_CLASSIFY) {
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    cf[kt] = *(const lds_v4i *)(lc(b) + ((rt * KT + kt) * 64 + lane) * 16);
+            }
+        };
+        // one row-tile pass of chunk c into cur, with hook between its MFMAs
+        auto pass = [&](int rt, Parts &cur, const auto &hook) {
+            tile_mma(cur, xr, lp(b) + rt * kDimChunk * RSB, nullptr, false, lane, hook);
+            read_cf(rt);
+        };
+        auto issue_next = [&](int c) {
+            const int b2 = b == 0 ? 2 : b - 1;   // (b + 2) % 3
+            dma_issue(a, ds, c + 2, NC, lp(b2), lc(b2), wave, lane);
+        };
+        auto finish_step = [&]() {
+            dma_barrier<G>();
+            b = b == 2 ? 0 : b + 1;
+        };
+
+        Parts P0, P1;
+        if constexpr (RT == 2) {
+            issue_next(0);
+            pass(0, P0, NoHook{});
+            pass(1, P1, Epilogue{a, P0, dacc, cf, 0, lane, g, qbase});
+            finish_step();
+            for (int c = 1; c < NC; ++c) {
+                issue_next(c);
+                pass(0, P0, Epilogue{a, P1, dacc, cf, 2 * c - 1, lane, g, qbase});
+                pass(1, P1, Epilogue{a, P0, dacc, cf, 2 * c, lane, g, qbase});
+                finish_step();
+            }
+            run_epilogue(Epilogue{a, P1, dacc, cf, 2 * NC - 1, lane, g, qbase});
+        } else {
+            issue_next(0);
+            pass(0, P0, NoHook{});
+            finish_step();
+            for (int c = 1;; c += 2) {
+                if (c >= NC) {
+                    run_epilogue(Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
+                    break;
+                }
+                issue_next(c);
+                pass(0, P1, Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
+                finish_step();
+                if (c + 1 >= NC) {
+                    run_epilogue(Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
+                    break;
+                }
+                issue_next(c + 1);
+                pass(0, P0, Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
+                finish_step();
+            }
+        }
+        // no load may still be writing this workgroup's LDS when it exits
+        __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (MODE == M_ENCODE && RT == 1) {
+            if (NC & 1) {   // high half of the last word holds no dimension
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt) {
+                    const int64_t q = qbase + qt * 32 + (lane & 31);
+                    if (g == 0 && q < a.n)
+                        a.H32[q * a.ldh32 + NC] = 0u;
+                }
+            }
+        }
+    }
+
     // Argmin over the class accumulators; returns the label of this lane's
     // query (valid in lanes 0..31 of each tile) and optionally writes dists.
     static __device__ __forceinline__ void finish(const EncodeArgs &a, int64_t qblock,

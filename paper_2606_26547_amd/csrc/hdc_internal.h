@@ -53,7 +53,11 @@ constexpr int kMaxConfigs = 4096;
 
 inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
 inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
-inline size_t class_table_bytes(int nd, int K) { return (size_t)chunks(nd) * class_tiles(K) * 1024; }
+// The fused classifier's class operand covers a whole number of its widest
+// dimension chunks (kMaxRT tiles of 32); rows past the dimension count are 0.
+constexpr int kMaxRT = 2;
+inline int64_t table_chunks(int nd) { return (chunks(nd) + kMaxRT - 1) / kMaxRT * kMaxRT; }
+inline size_t class_table_bytes(int nd, int K) { return (size_t)table_chunks(nd) * class_tiles(K) * 1024; }
 
 hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st);
 hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,

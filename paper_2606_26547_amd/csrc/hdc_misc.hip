@@ -74,7 +74,7 @@ hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int
                               int8_t *tab, int32_t *cpop, hipStream_t st)
 {
     const int KT = class_tiles(K);
-    const int64_t total = chunks(nd) * KT * 64;
+    const int64_t total = table_chunks(nd) * KT * 64;
     hipLaunchKernelGGL(k_class_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc,
                        s0, stride, nd, KT, total, tab);
     hipLaunchKernelGGL(k_class_popc, dim3(KT * 32), dim3(256), 0, st, C, K, ldc, s0, stride, nd, cpop);

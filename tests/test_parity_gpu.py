@@ -51,6 +51,8 @@ ENC_CASES = [
     (33, 1000, 320, "int8", "fp8", None),
     (600, 64, 2048, "int8", "int8", None),
     (64, 512, 64, "uint8", "int8", (0, 64, 8)),
+    (520, 617, 10240, "int8", "int8", (0, 4000, 3)),
+    (257, 300, 2000, "int8", "int8", (5, 1995, 1)),
 ]
 
 

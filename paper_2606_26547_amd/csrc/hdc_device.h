@@ -29,6 +29,18 @@ __device__ __forceinline__ void lds_st16(lds_u8 *p, uint4 v)
     *(lds_v4i *)p = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
 }
 
+// Direct global -> LDS load of 16 bytes per lane: lane l's bytes at
+// base + voff land at LDS address dst + 16 * l (dst is wave-uniform).
+// Issued as inline assembly: the compiler then keeps counting only its own
+// LDS reads (it would otherwise drain every LDS read before each MFMA), and
+// the caller waits for these loads explicitly (vmcnt).
+__device__ __forceinline__ void lds_dma16(const void *base, uint32_t voff, const lds_u8 *dst)
+{
+    const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(m), "v"(voff), "s"(base)
+                 : "memory", "m0");
+}
+
 // ---------------------------------------------------------------------------
 // Operand traits.  Every compute type uses a 32x32 MFMA (rows = dimensions,
 // columns = queries).  KSTEP features are consumed per instruction; each

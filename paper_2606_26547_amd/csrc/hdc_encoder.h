@@ -556,15 +556,13 @@ struct Encoder {
         for (int i = 0; i < NIW; ++i) {
             const int r = d.row[i] < last ? d.row[i] : last;
             const uint32_t off = base + (uint32_t)(cc * CH + r) * rstep + (uint32_t)d.pb[i];
-            __builtin_amdgcn_global_load_lds((const void *)(a.P + off),
-                                             (HDC_LDS void *)(stage + (i * kWaves + wave) * 1024), 16, 0, 0);
+            lds_dma16(a.P, off, stage + (i * kWaves + wave) * 1024);
         }
         if constexpr (MODE == M_CLASSIFY) {
 #pragma unroll
             for (int j = 0; j < NCW; ++j) {
                 const int tile = (wave + kWaves * j) % NCT;   // rt * KT + kt
-                const int8_t *src = a.ctab + ((int64_t)cc * NCT + tile) * 1024 + lane * 16;
-                __builtin_amdgcn_global_load_lds((const void *)src, (HDC_LDS void *)(lcls + tile * 1024), 16, 0, 0);
+                lds_dma16(a.ctab, (uint32_t)((cc * NCT + tile) * 1024 + lane * 16), lcls + tile * 1024);
             }
         }
     }

@@ -273,18 +273,20 @@ struct Encoder {
     typedef acc_t Parts[QT][KC];             // accumulators of one row tile
     static constexpr int kPhases = 4 * QT;   // epilogue phases (see Epilogue)
 
+    // Work interleaved with a pass: at(s) runs after the MFMAs of K step s,
+    // tail() after the loop.
     struct NoHook {
-        __device__ __forceinline__ void operator()(int) const {}
+        __device__ __forceinline__ void at(int) const {}
+        __device__ __forceinline__ void tail() const {}
     };
 
     // One pass over a row tile (32 dimensions) in LDS: a fixed-length,
     // branch-free K loop with PD projection fragments in flight (steps past
     // the feature count read zero-filled or finite LDS against zero
     // features).  Chain 0 of every query tile starts from the uint8
-    // correction 128 * sum_i p_i of its rows (0 otherwise).  hook(p) runs
-    // phase p of the previous row tile's epilogue after the MFMAs of step
-    // p * SP, so its VALU work issues while the matrix core is busy; phases
-    // past the last step run after the loop.
+    // correction 128 * sum_i p_i of its rows (0 otherwise).  The hook's work
+    // (the previous row tile's epilogue, the next chunk's loads) issues
+    // between the MFMAs, while the matrix core is busy.
     template <class Hook>
     static __device__ __forceinline__ void tile_mma(Parts &part, const frag (&xr)[QT][KS], const lds_u8 *lp,
                                                     const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
@@ -293,7 +295,6 @@ struct Encoder {
         const lds_u8 *base = lp + row * RSB + g * (KB / 2);
         constexpr int PDW = (CT == C_I8 && (WAVES == 1 || DMA)) ? 4 : (CT == C_F32 ? 4 : 2);
         constexpr int PD = KS < PDW ? KS : PDW;
-        constexpr int SP = KS >= 2 * kPhases ? 2 : 1;
         frag f[PD];
 #pragma unroll
         for (int s = 0; s < PD; ++s)
@@ -324,13 +325,10 @@ struct Encoder {
 #pragma unroll
             for (int qt = 0; qt < QT; ++qt)
                 mma(part[qt][s % KC], cur, xr[qt][s]);
-            if (s % SP == 0 && s / SP < kPhases)
-                hook(s / SP);
+            hook.at(s);
             __builtin_amdgcn_sched_barrier(0);
         }
-#pragma unroll
-        for (int p = (KS + SP - 1) / SP; p < kPhases; ++p)
-            hook(p);
+        hook.tail();
     }
 
     // Epilogue of row tile w (dimensions S_{32w .. 32w+31}) split into
@@ -416,6 +414,38 @@ struct Encoder {
             epi(p);
     }
 
+    // The epilogue as a pass hook: phase p after K step p * SP.
+    static constexpr int SP = KS >= 2 * kPhases ? 2 : 1;
+    struct EpiHook {
+        Epilogue epi;
+        __device__ __forceinline__ void at(int s) const
+        {
+            if (s % SP == 0 && s / SP < kPhases)
+                epi(s / SP);
+        }
+        __device__ __forceinline__ void tail() const
+        {
+#pragma unroll
+            for (int p = (KS + SP - 1) / SP; p < kPhases; ++p)
+                epi(p);
+        }
+    };
+    template <class H1, class H2>
+    struct Both {
+        H1 h1;
+        H2 h2;
+        __device__ __forceinline__ void at(int s) const
+        {
+            h1.at(s);
+            h2.at(s);
+        }
+        __device__ __forceinline__ void tail() const
+        {
+            h1.tail();
+            h2.tail();
+        }
+    };
+
     // ------------------------------------------------------------ body
     // Runs the whole dimension loop for the queries of this workgroup.
     // Returns the class accumulators (classify mode) through dacc.
@@ -497,12 +527,12 @@ struct Encoder {
                 run_epilogue(Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
                 break;
             }
-            step(c, 1, P1, Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
+            step(c, 1, P1, EpiHook{Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase}});
             if (c + 1 >= NC) {
                 run_epilogue(Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
                 break;
             }
-            step(c + 1, 0, P0, Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
+            step(c + 1, 0, P0, EpiHook{Epilogue{a, P1, dacc, cf, c, lane, g, qbase}});
         }
         if constexpr (MODE == M_ENCODE) {
             if (NC & 1) {   // high half of the last word holds no dimension
@@ -520,52 +550,79 @@ struct Encoder {
     // Source of each of this lane's NIW loads: LDS unit u = (i * 4 + wave) *
     // 64 + lane of a stage is row u / UPR, piece u % UPR; the skew unit,
     // pieces past the features and rows past the chunk re-read piece 0 of an
-    // in-bounds row (finite int8 against zero features, or slack).
-    struct DmaSrc {
-        int row[NIW];
-        int pb[NIW];
-    };
-    static __device__ __forceinline__ void dma_setup(DmaSrc &d, int wave, int lane, int npc)
-    {
+    // in-bounds row (finite int8 against zero features, or slack).  Row r of
+    // chunk c is dimension S_{c*CH + r}.  Byte offsets fit 32 bits: the
+    // projection holds at most 65536 rows of at most 1024 + padding bytes.
+    struct Loader {
+        const EncodeArgs &a;
+        uint32_t off0[NIW];   // offset of load i in chunk 0
+        int rp[NIW];          // row | piece byte offset << 8
+        uint32_t rstep, base, cbytes;
+        int NC, lane, wave;
+
+        __device__ __forceinline__ Loader(const EncodeArgs &a_, int NC_, int npc, int wave_, int lane_)
+            : a(a_), NC(NC_), lane(lane_), wave(wave_)
+        {
+            rstep = (uint32_t)a.stride * (uint32_t)a.ldp;
+            base = (uint32_t)a.s0 * (uint32_t)a.ldp;
+            cbytes = (uint32_t)CH * rstep;
 #pragma unroll
-        for (int i = 0; i < NIW; ++i) {
-            const int u = (i * kWaves + wave) * 64 + lane;
-            int r = u / UPR, p = u % UPR;
-            if (r >= CH) {
-                r = CH - 1;
-                p = 0;
+            for (int i = 0; i < NIW; ++i) {
+                const int u = (i * kWaves + wave) * 64 + lane;
+                int r = u / UPR, p = u % UPR;
+                if (r >= CH) {
+                    r = CH - 1;
+                    p = 0;
+                }
+                const int pb = 16 * (p < npc ? p : 0);
+                off0[i] = base + (uint32_t)r * rstep + (uint32_t)pb;
+                rp[i] = r | (pb << 8);
             }
-            d.row[i] = r;
-            d.pb[i] = 16 * (p < npc ? p : 0);
         }
-    }
-    // Loads chunk c (clamped to the last chunk) into a stage and its class
-    // fragments (wave w loads class tiles (w + 4j) % NCT; duplicate tiles
-    // write the same bytes).  Every wave issues exactly NIW (+ NCW) loads.
-    // The class table holds a whole number of chunks (zero rows past nd).
-    static __device__ __forceinline__ void dma_issue(const EncodeArgs &a, const DmaSrc &d, int c, int NC,
-                                                     lds_u8 *stage, lds_u8 *lcls, int wave, int lane)
-    {
-        // byte offsets fit 32 bits: the projection holds at most 65536 rows
-        // of at most 1024 + padding bytes
-        const int cc = c < NC ? c : NC - 1;
-        const uint32_t rstep = (uint32_t)a.stride * (uint32_t)a.ldp;
-        const uint32_t base = (uint32_t)a.s0 * (uint32_t)a.ldp;
-        const int last = a.nd - 1 - cc * CH;   // rows past it re-read the last one
-#pragma unroll
-        for (int i = 0; i < NIW; ++i) {
-            const int r = d.row[i] < last ? d.row[i] : last;
-            const uint32_t off = base + (uint32_t)(cc * CH + r) * rstep + (uint32_t)d.pb[i];
-            lds_dma16(a.P, off, stage + (i * kWaves + wave) * 1024);
-        }
-        if constexpr (MODE == M_CLASSIFY) {
-#pragma unroll
-            for (int j = 0; j < NCW; ++j) {
-                const int tile = (wave + kWaves * j) % NCT;   // rt * KT + kt
+        // Load i (< NIW + NCW) of chunk c, clamped to the last chunk: the
+        // projection rows, then the class fragments (wave w loads class tiles
+        // (w + 4j) % NCT; duplicate tiles write the same bytes).  In the
+        // chunk holding the last dimension, rows past it re-read that row.
+        // The class table holds a whole number of chunks (zero rows past nd).
+        __device__ __forceinline__ void issue(int i, int c, lds_u8 *stage, lds_u8 *lcls) const
+        {
+            const int cc = c < NC ? c : NC - 1;
+            if (i < NIW) {
+                uint32_t off;
+                if ((cc + 1) * CH <= a.nd) {
+                    off = off0[i] + (uint32_t)cc * cbytes;
+                } else {
+                    const int last = a.nd - 1 - cc * CH;
+                    const int r = (rp[i] & 255) < last ? (rp[i] & 255) : last;
+                    off = base + (uint32_t)(cc * CH + r) * rstep + (uint32_t)(rp[i] >> 8);
+                }
+                lds_dma16(a.P, off, stage + (i * kWaves + wave) * 1024);
+            } else if constexpr (MODE == M_CLASSIFY) {
+                const int tile = (wave + kWaves * (i - NIW)) % NCT;   // rt * KT + kt
                 lds_dma16(a.ctab, (uint32_t)((cc * NCT + tile) * 1024 + lane * 16), lcls + tile * 1024);
             }
         }
-    }
+    };
+    static constexpr int NLOADS = NIW + (MODE == M_CLASSIFY ? NCW : 0);   // loads per wave per chunk
+
+    // The loads of one chunk as a pass hook: load s after K step s.
+    struct LoadHook {
+        const Loader &ld;
+        int c;
+        lds_u8 *stage, *lcls;
+        __device__ __forceinline__ void at(int s) const
+        {
+            if (s < NLOADS)
+                ld.issue(s, c, stage, lcls);
+        }
+        __device__ __forceinline__ void tail() const
+        {
+#pragma unroll
+            for (int s = KS; s < NLOADS; ++s)
+                ld.issue(s, c, stage, lcls);
+        }
+    };
+
     // Wait until at most G of this wave's vector memory operations are in
     // flight (they complete in issue order, so everything older is done),
     // drain LDS operations, and meet the other waves.
@@ -575,13 +632,13 @@ struct Encoder {
         asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(G) : "memory");
     }
 
-    // Three-stage loop: step c issues the loads of chunk c+2, multiplies the
-    // RT row tiles of chunk c one after the other (each with the previous row
-    // tile's epilogue between its MFMAs, the class fragments of each tile
-    // read into registers right after its pass), waits for chunk c+1's loads
-    // and synchronises once.  Row tile passes alternate between two
-    // accumulator sets: with RT = 2 that is fixed within a step, with RT = 1
-    // the loop is unrolled by two.
+    // Three-stage loop: step c multiplies the RT row tiles of chunk c one
+    // after the other, each with the previous row tile's epilogue between
+    // its MFMAs (the first pass also issues the loads of chunk c+2 there),
+    // reads each tile's class fragments into registers right after its
+    // pass, waits for chunk c+1's loads and synchronises once.  Row tile
+    // passes alternate between two accumulator sets: with RT = 2 that is
+    // fixed within a step, with RT = 1 the loop is unrolled by two.
     static __device__ __forceinline__ void run_dma(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
                                                    v16i (&dacc)[KT][QT])
     {
@@ -593,7 +650,7 @@ struct Encoder {
         const int NC = (a.nd + CH - 1) / CH;
         // loads issued per step after those of the chunk waited for (stores
         // of the encode epilogue are not counted: waiting for more is safe)
-        constexpr int G = NIW + (MODE == M_CLASSIFY ? NCW : 0);
+        constexpr int G = NLOADS;
 
         frag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
@@ -606,10 +663,12 @@ struct Encoder {
         lds_u8 *L = (lds_u8 *)smem;
         auto lp = [&](int i) { return L + i * SSZ; };
         auto lc = [&](int i) { return L + OFF_C + i * (NCT * 1024); };
-        DmaSrc ds;
-        dma_setup(ds, wave, lane, npc);
-        dma_issue(a, ds, 0, NC, lp(0), lc(0), wave, lane);
-        dma_issue(a, ds, 1, NC, lp(1), lc(1), wave, lane);
+        const Loader ld(a, NC, npc, wave, lane);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < NLOADS; ++i)
+                ld.issue(i, c, lp(c), lc(c));
         dma_barrier<G>();
 
         v4i cf[KT];
@@ -621,15 +680,18 @@ struct Encoder {
                     cf[kt] = *(const lds_v4i *)(lc(b) + ((rt * KT + kt) * 64 + lane) * 16);
             }
         };
-        // one row-tile pass of chunk c into cur, with hook between its MFMAs
+        // one row-tile pass of the current chunk into cur
         auto pass = [&](int rt, Parts &cur, const auto &hook) {
             tile_mma(cur, xr, lp(b) + rt * kDimChunk * RSB, nullptr, false, lane, hook);
             read_cf(rt);
         };
-        auto issue_next = [&](int c) {
+        auto loads = [&](int c) {   // loads of chunk c + 2 into the free stage
             const int b2 = b == 0 ? 2 : b - 1;   // (b + 2) % 3
-            dma_issue(a, ds, c + 2, NC, lp(b2), lc(b2), wave, lane);
+            return LoadHook{ld, c + 2, lp(b2), lc(b2)};
         };
+        auto epi = [&](Parts &prev, int w) { return EpiHook{Epilogue{a, prev, dacc, cf, w, lane, g, qbase}}; };
+        typedef Both<EpiHook, LoadHook> EpiLoad;
+        typedef Both<NoHook, LoadHook> JustLoad;
         auto finish_step = [&]() {
             dma_barrier<G>();
             b = b == 2 ? 0 : b + 1;
@@ -637,35 +699,30 @@ struct Encoder {
 
         Parts P0, P1;
         if constexpr (RT == 2) {
-            issue_next(0);
-            pass(0, P0, NoHook{});
-            pass(1, P1, Epilogue{a, P0, dacc, cf, 0, lane, g, qbase});
+            pass(0, P0, JustLoad{NoHook{}, loads(0)});
+            pass(1, P1, epi(P0, 0));
             finish_step();
             for (int c = 1; c < NC; ++c) {
-                issue_next(c);
-                pass(0, P0, Epilogue{a, P1, dacc, cf, 2 * c - 1, lane, g, qbase});
-                pass(1, P1, Epilogue{a, P0, dacc, cf, 2 * c, lane, g, qbase});
+                pass(0, P0, EpiLoad{epi(P1, 2 * c - 1), loads(c)});
+                pass(1, P1, epi(P0, 2 * c));
                 finish_step();
             }
             run_epilogue(Epilogue{a, P1, dacc, cf, 2 * NC - 1, lane, g, qbase});
         } else {
-            issue_next(0);
-            pass(0, P0, NoHook{});
+            pass(0, P0, JustLoad{NoHook{}, loads(0)});
             finish_step();
             for (int c = 1;; c += 2) {
                 if (c >= NC) {
                     run_epilogue(Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
                     break;
                 }
-                issue_next(c);
-                pass(0, P1, Epilogue{a, P0, dacc, cf, c - 1, lane, g, qbase});
+                pass(0, P1, EpiLoad{epi(P0, c - 1), loads(c)});
                 finish_step();
                 if (c + 1 >= NC) {
                     run_epilogue(Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
                     break;
                 }
-                issue_next(c + 1);
-                pass(0, P0, Epilogue{a, P1, dacc, cf, c, lane, g, qbase});
+                pass(0, P0, EpiLoad{epi(P1, c), loads(c + 1)});
                 finish_step();
             }
         }

@@ -226,6 +226,10 @@ hdc_status hdc_classify_prepared(void *stream,
  *   cfgs   [ncfg] hdc_config, device memory; ncfg <= 4096
  *   out    [ncfg] hdc_config_result, device memory, overwritten
  *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, D, K), 256-byte aligned
+ *   max_workgroups  0: as many workgroups as fit on the device at once;
+ *          otherwise at most this many (a configuration job that shares
+ *          the device with latency-bound inference leaves it room; the
+ *          work queue finishes every item whatever the count)
  * ------------------------------------------------------------------- */
 typedef struct {
     int32_t d_trunc, stride, start;
@@ -246,7 +250,7 @@ hdc_status hdc_eval_configs(void *stream,
                             const uint64_t *C, int32_t K, int64_t ldc,
                             const hdc_config *cfgs, int32_t ncfg,
                             hdc_config_result *out,
-                            void *ws, size_t ws_bytes);
+                            void *ws, size_t ws_bytes, int32_t max_workgroups);
 
 /* Frequency in Hz of the device wall clock that hdc_eval_configs reads. */
 double hdc_device_clock_hz(void);

@@ -331,13 +331,13 @@ size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
 hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                             const int32_t *truth, const int8_t *P, int32_t D, int64_t ldp, const uint64_t *C,
                             int32_t K, int64_t ldc, const hdc_config *cfgs, int32_t ncfg,
-                            hdc_config_result *out, void *ws, size_t ws_bytes)
+                            hdc_config_result *out, void *ws, size_t ws_bytes, int32_t max_workgroups)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, HDC_INT8, hdc_dims{0, D, 1}, &ct, &xt);
     if (s != HDC_OK)
         return s;
-    if (K <= 0 || ncfg <= 0)
+    if (K <= 0 || ncfg <= 0 || max_workgroups < 0)
         return HDC_ERR_INVALID;
     if (K > kMaxK || ncfg > kMaxConfigs)
         return HDC_ERR_UNSUPPORTED;
@@ -365,6 +365,7 @@ hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64
     a.out = out;
     a.ws = (uint8_t *)ws;
     a.ws_bytes = ws_bytes;
+    a.max_wg = max_workgroups;
     return from_hip(launch_sweep(a, (hipStream_t)stream));
 }
 

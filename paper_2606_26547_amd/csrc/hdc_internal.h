@@ -98,6 +98,7 @@ struct SweepArgs {
     hdc_config_result *out;   // device
     uint8_t *ws;
     size_t ws_bytes;
+    int32_t max_wg;           // 0: fill the device
 };
 size_t sweep_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);

@@ -226,7 +226,9 @@ static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a
     int per_cu = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<FB, KT>, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int grid = cus * per_cu;
+    int grid = cus * per_cu;
+    if (a.max_wg > 0 && a.max_wg < grid)
+        grid = a.max_wg;
     hipLaunchKernelGGL((k_sweep<FB, KT>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, a.out, L.off_desc,
                        L.off_order, L.off_regions, L.region, table_bytes, a.ncfg, tiles);
     return hipGetLastError();

@@ -81,7 +81,7 @@ _lib.hdc_classify_prepared.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i
 _lib.hdc_eval_configs_workspace_bytes.restype = _sz
 _lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32]
 _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
-                                  _p, _i32, _p, _p, _sz]
+                                  _p, _i32, _p, _p, _sz, _i32]
 _lib.hdc_device_clock_hz.restype = C.c_double
 _lib.hdc_device_clock_hz.argtypes = []
 _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int, _p]
@@ -267,12 +267,14 @@ def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:
 
 
 def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
-                 cfgs, ws: torch.Tensor | None = None):
+                 cfgs, ws: torch.Tensor | None = None, max_workgroups: int = 0):
     """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype-name)], one
-    persistent launch; returns (correct[ncfg], ticks[ncfg]) device tensors."""
+    persistent launch; returns (correct[ncfg], ticks[ncfg]) device tensors.
+    Nothing here waits for the device: the configurations go up through
+    pinned memory on the current stream."""
     arr = np.array([[d, k, s, DTYPE[t] if isinstance(t, str) else int(t)] for (d, k, s, t) in cfgs],
                    dtype=np.int32).reshape(-1, 4)
-    dev = torch.from_numpy(arr).to(X.device)
+    dev = torch.from_numpy(arr).pin_memory().to(X.device, non_blocking=True)
     K = Cw.shape[0]
     need = int(_lib.hdc_eval_configs_workspace_bytes(len(arr), D, K))
     if ws is None or ws.numel() < need:
@@ -280,7 +282,7 @@ def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, 
     out = torch.zeros((len(arr), 4), dtype=torch.int32, device=X.device)   # {correct, n, ticks(u64)}
     _check(_lib.hdc_eval_configs(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1], _ptr(truth),
                                  _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], _ptr(dev), len(arr),
-                                 _ptr(out), _ptr(ws), ws.numel()), "hdc_eval_configs")
+                                 _ptr(out), _ptr(ws), ws.numel(), int(max_workgroups)), "hdc_eval_configs")
     correct = out[:, 0]
     ticks = out[:, 2:4].contiguous().view(torch.int64).view(-1)
     return correct, ticks

@@ -18,7 +18,8 @@ Structure
 * ``GpuExecutor``: one HIP stream per model plus one for configuration jobs;
   a batch is an async H2D copy from pinned staging, one fused-classifier
   launch (``hdc_classify_prepared``) and an async D2H copy of the labels,
-  closed by an event.  Batches of different models overlap on the device.
+  closed by an event.  Batches of different models overlap on the device;
+  configuration jobs run on a capped number of workgroups beside them.
 * ``Server``: the scheduler thread that drives both and completes futures
   with per-request latency (arrival -> labels on the host).
 """
@@ -26,6 +27,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import threading
 import time
 from concurrent.futures import Future
@@ -137,15 +139,27 @@ class Scheduler:
 
 # ---------------------------------------------------------------- executor
 class GpuExecutor:
-    """Resident models and per-model streams; runs batches asynchronously."""
+    """Resident models and per-model streams; runs batches asynchronously.
 
-    def __init__(self, models, device="cuda", max_batch: int = 16384):
+    Inference batches use a pool of staging slots (pinned host + device
+    buffers for the queries and the labels, sized for ``max_batch`` queries
+    of the widest model), reused once allocated: the pool grows only to the
+    largest number of batches in flight, so a steady-state launch allocates
+    nothing.  The queries are copied into the slot's pinned buffer, then one
+    H2D copy, one fused-classifier launch and one D2H copy are queued on the
+    model's stream and closed by the slot's event."""
+
+    def __init__(self, models, device="cuda", max_batch: int = 16384, job_workgroups: int = 64,
+                 slots: int = 4):
         import torch
 
         from . import hdc
         self.torch, self.hdc = torch, hdc
         self.dev = device
         self.max_batch = max_batch
+        # configuration jobs run persistent kernels: cap their workgroups so
+        # that inference batches on the other streams still find free units
+        self.job_workgroups = job_workgroups
         self.models = []
         self.streams = []
         for m in models:
@@ -153,6 +167,36 @@ class GpuExecutor:
             self.streams.append(torch.cuda.Stream(device=device))
         self.cfg_stream = torch.cuda.Stream(device=device)
         self.resident_bytes = sum(m.resident_bytes for m in models)
+        self.ld_max = max(m.P.shape[1] for m in models)
+        self.free = collections.deque()
+        self.nslots = 0
+        for _ in range(slots):
+            self.free.append(self._new_slot())
+
+    def warm(self, job_cfgs=None):
+        """Run every kernel the server will use once (each model's plain and
+        tuned classifier, and its configuration sweep when ``job_cfgs(m)``
+        is given), so that first-launch costs stay out of request latency."""
+        torch, hdc = self.torch, self.hdc
+        for i, m in enumerate(self.models):
+            X = torch.zeros((64, m.P.shape[1]), dtype=torch.int8, device=self.dev)
+            m.plain(X, m.F, m.P)
+            m.tuned(X, m.F, m.P)
+            if job_cfgs is not None:
+                y = torch.zeros(64, dtype=torch.int32, device=self.dev)
+                hdc.eval_configs(X, m.F, y, m.P, m.D, m.C, job_cfgs(i), ws=m.sweep_ws,
+                                 max_workgroups=self.job_workgroups)
+        torch.cuda.synchronize()
+
+    def _new_slot(self):
+        torch = self.torch
+        self.nslots += 1
+        n, ld = self.max_batch, self.ld_max
+        return {"hx": torch.empty(n * ld, dtype=torch.int8, pin_memory=True),
+                "dx": torch.empty(n * ld, dtype=torch.int8, device=self.dev),
+                "hl": torch.empty(n, dtype=torch.int32, pin_memory=True),
+                "dl": torch.empty(n, dtype=torch.int32, device=self.dev),
+                "ev": torch.cuda.Event()}
 
     @staticmethod
     def request_bytes(r: Request, F: int) -> int:
@@ -163,39 +207,57 @@ class GpuExecutor:
         torch, hdc = self.torch, self.hdc
         r0 = b.requests[0]
         m = self.models[r0.model]
-        stream = self.cfg_stream if r0.kind == "configs" else self.streams[r0.model]
-        ld = m.P.shape[1]
-        host = torch.empty((b.n, ld), dtype=torch.int8, pin_memory=True)
-        hv = host.numpy()
-        hv[:, m.F:] = 0
-        for r, off in zip(b.requests, b.offsets):
-            hv[off:off + r.n, :m.F] = r.X
-        with torch.cuda.stream(stream):
-            X = host.to(self.dev, non_blocking=True)
-            if r0.kind == "configs":
+        if r0.kind == "configs":
+            stream = self.cfg_stream
+            ld = m.P.shape[1]
+            host = torch.zeros((b.n, ld), dtype=torch.int8, pin_memory=True)
+            host.numpy()[:, :m.F] = r0.X
+            with torch.cuda.stream(stream):
+                X = host.to(self.dev, non_blocking=True)
                 truth = torch.as_tensor(r0.truth, dtype=torch.int32).pin_memory().to(self.dev, non_blocking=True)
-                correct, ticks = hdc.eval_configs(X, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws)
+                correct, _ = hdc.eval_configs(X, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws,
+                                              max_workgroups=self.job_workgroups)
                 out = torch.empty(len(r0.cfgs), dtype=torch.int32, pin_memory=True)
                 out.copy_(correct, non_blocking=True)
-            else:
-                prep = m.tuned if r0.tuned else m.plain
-                labels = prep(X, m.F, m.P)
-                out = torch.empty(b.n, dtype=torch.int32, pin_memory=True)
-                out.copy_(labels, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        b.handle = (ev, out, host, X)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            b.handle = ("configs", ev, out, host, X, truth)
+            return
+        if b.n > self.max_batch:
+            raise ValueError("batch of %d queries exceeds max_batch %d" % (b.n, self.max_batch))
+        slot = self.free.popleft() if self.free else self._new_slot()
+        stream = self.streams[r0.model]
+        ld = m.P.shape[1]
+        hxt = slot["hx"][:b.n * ld].view(b.n, ld)
+        hx = hxt.numpy()
+        for r, off in zip(b.requests, b.offsets):
+            hx[off:off + r.n, :m.F] = r.X
+        if ld > m.F:
+            hx[:, m.F:] = 0
+        with torch.cuda.stream(stream):
+            dx = slot["dx"][:b.n * ld].view(b.n, ld)
+            dx.copy_(hxt, non_blocking=True)
+            prep = m.tuned if r0.tuned else m.plain
+            prep(dx, m.F, m.P, slot["dl"][:b.n])
+            slot["hl"][:b.n].copy_(slot["dl"][:b.n], non_blocking=True)
+            slot["ev"].record(stream)
+        b.handle = ("infer", slot)
 
     def ready(self, b: Batch) -> bool:
-        return b.handle[0].query()
+        h = b.handle
+        return (h[1] if h[0] == "configs" else h[1]["ev"]).query()
 
     def results(self, b: Batch):
-        ev, out, _, _ = b.handle
-        ev.synchronize()
-        res = out.numpy()
-        if b.requests[0].kind == "configs":
-            return [res.copy()]
-        return [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
+        h = b.handle
+        if h[0] == "configs":
+            h[1].synchronize()
+            return [h[2].numpy().copy()]
+        slot = h[1]
+        slot["ev"].synchronize()
+        res = slot["hl"].numpy()
+        out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
+        self.free.append(slot)
+        return out
 
 
 class ResidentModel:
@@ -203,7 +265,7 @@ class ResidentModel:
     prepared class operands of its plain and tuned configurations."""
 
     def __init__(self, P: np.ndarray, X_train: np.ndarray, y_train: np.ndarray, K: int,
-                 tuned_cfg=None, device="cuda"):
+                 tuned_cfg=None, device="cuda", max_job_cfgs: int = 64):
         import torch
 
         from . import hdc
@@ -217,9 +279,11 @@ class ResidentModel:
         self.tuned_cfg = tuned_cfg or (self.D, 1, 0, "int8")
         d, k, s, t = self.tuned_cfg
         self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
-        self.sweep_ws = None
+        # workspace of configuration jobs (up to max_job_cfgs configurations)
+        need = int(hdc.lib().hdc_eval_configs_workspace_bytes(max_job_cfgs, self.D, self.K))
+        self.sweep_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
         self.resident_bytes = (self.P.numel() + self.C.numel() * 8 + self.plain.ws.numel()
-                               + self.tuned.ws.numel())
+                               + self.tuned.ws.numel() + self.sweep_ws.numel())
 
     def set_tuned(self, cfg):
         from . import hdc
@@ -244,6 +308,12 @@ class Server:
         self.poll_s = poll_s
         self.next_id = 0
         self.completed = []                 # (rid, kind, model, n, latency_s)
+        # Everything allocated so far (models, pools, staging) lives as long
+        # as the server: move it out of the cyclic collector's view, so that
+        # a full collection during serving does not stall the loop for tens
+        # of milliseconds.
+        gc.collect()
+        gc.freeze()
         self.thread = threading.Thread(target=self._loop, daemon=True)
         self.thread.start()
 

@@ -44,9 +44,11 @@ def test_sweep_256_slots_consistent(env):
     Pd, Cd = hdc.pad_cols(ds.P), torch.as_tensor(env["C"].view(np.int64)).cuda()
     correct, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)
     correct2, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)
+    correct3, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots, max_workgroups=7)   # few workers
     torch.cuda.synchronize()
     c = correct.cpu().numpy()
     assert np.array_equal(c, correct2.cpu().numpy())
+    assert np.array_equal(c, correct3.cpu().numpy())
     first = {}
     for s, v in zip(slots, c):
         assert first.setdefault(s, v) == v            # duplicates agree

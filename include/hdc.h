@@ -154,6 +154,8 @@ hdc_status hdc_hamming_argmin(void *stream,
  * batches against it.  Outputs are identical to hdc_hamming_argmin with the
  * same arguments.  `ws` must stay untouched between the calls; K and perf
  * must be the same in both.
+ *   Q        16-byte aligned with an even row pitch ldq (the prepared
+ *            search streams query words 16 bytes at a time)
  *   ws       >= hdc_hamming_workspace_bytes(perf, K) bytes, 16-byte aligned
  * Supports K <= 128, perf.end <= 65536.
  * ------------------------------------------------------------------- */

@@ -235,7 +235,7 @@ hdc_status hdc_hamming_argmin_prepared(void *stream, const uint64_t *Q, int64_t 
         return HDC_ERR_WORKSPACE;
     if (n == 0)
         return HDC_OK;
-    if (!Q || ldq < (perf.end + 63) / 64 || !argmin)
+    if (!Q || ldq < (perf.end + 63) / 64 || ldq % 2 || !aligned(Q, 16) || !argmin)
         return HDC_ERR_INVALID;
     return from_hip(launch_ham_prepared(Q, n, ldq, K, perf.start, perf.end, (const uint8_t *)ws, argmin,
                                         min_dist, dists, (hipStream_t)stream));

@@ -17,34 +17,48 @@
 // HBM-bound.
 //
 // Class operand table (built once per (classes, perforation) by
-// k_ham_table): for word w (relative to the first word of S), half h (low /
+// k_ham_table): for word w (counted from the even word w_lo at or below the
+// first word of S, padded with zero words to whole windows), half h (low /
 // high dword) and class tile kt, 64 lanes x 16 bytes where lane l, byte
 // b = 4*pl + i holds class kt*32 + l%32 at dimension 64w + 32h + 8i + p with
 // plane p = 4*(l/32) + pl.
+//
+// Streaming: a workgroup (4 waves, one per SIMD) owns ROWS query rows and
+// walks the words in windows of W; the query words and the class operand of
+// a window go from global memory straight into an LDS ring of NST stages
+// (global_load_lds, 16 bytes per lane), NST - 1 windows ahead of the
+// window being multiplied, with one barrier per window.
 #include <limits.h>
 
 #include "hdc_device.h"
 
 namespace hdc {
 
-// Shape per class-tile count: query tiles (32 queries) per wave, and words
-// per staged window (the class operand of a window takes WIN * 2 * KT KiB
-// of LDS beside the workgroup's query rows of WIN + 1 words).
+// Shape per class-tile count: query tiles (32 queries) per wave, words per
+// window, LDS stages.
 template <int KT> struct HmShape {
-    static constexpr int QT = KT == 4 ? 1 : 2;
-    static constexpr int WIN = KT == 4 ? 4 : 8;
-    static constexpr int ROWS = kWaves * QT * 32;   // queries per workgroup
+    static constexpr int QT = KT == 4 ? 2 : 4;
+    static constexpr int W = 4;                        // words per window
+    static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
+    static constexpr int QB = ROWS * W * 8;            // query bytes per stage
+    static constexpr int TB = W * 2 * KT * 1024;       // class operand bytes per window
+    static constexpr int NST = KT == 4 ? 3 : 4;        // LDS stages
+    static constexpr int NQL = QB / 1024 / kWaves;     // query loads per wave per window
+    static constexpr int NTL = TB / 1024 / kWaves;     // class loads per wave per window
+    static constexpr int SB = QB + TB;                 // bytes per stage
 };
+constexpr int kHmWin = 4;
 
 struct HamLayout {
-    int w_lo, w_hi, KT;
+    int w_lo, w_hi, nwin, KT;
     size_t off_popc, total;
     HamLayout(int start, int end, int K)
     {
-        w_lo = start >> 6;
+        w_lo = (start >> 6) & ~1;
         w_hi = (end + 63) >> 6;
+        nwin = (w_hi - w_lo + kHmWin - 1) / kHmWin;
         KT = class_tiles(K);
-        const size_t tab = (size_t)(w_hi - w_lo) * 2 * KT * 1024;
+        const size_t tab = (size_t)nwin * kHmWin * 2 * KT * 1024;
         off_popc = tab;
         total = off_popc + 128 * 4;
     }
@@ -95,79 +109,115 @@ __device__ __forceinline__ v4i planes(uint32_t d, uint32_t sh)
     return b;
 }
 
+// Query row r of a stage is 4 words = two 16-byte halves; half hh of the
+// window sits in slot hh ^ ((r >> 3) & 1), which keeps the 16-byte reads of
+// 16 consecutive rows on distinct banks.
+__device__ __forceinline__ int hm_slot(int r, int hh) { return hh ^ ((r >> 3) & 1); }
+
 template <int KT>
 __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq, int K,
-                                                      int w_lo, int w_hi, const int8_t *__restrict__ tab,
+                                                      int w_lo, int w_hi, int nwin, const int8_t *__restrict__ tab,
                                                       const int32_t *__restrict__ popc, int32_t *__restrict__ argmin,
                                                       int32_t *__restrict__ min_dist, int32_t *__restrict__ dists)
 {
-    constexpr int kHmQT = HmShape<KT>::QT, kHmWin = HmShape<KT>::WIN, ROWS = HmShape<KT>::ROWS;
-    __shared__ uint64_t qs[ROWS][kHmWin + 1];                 // odd row pitch: conflict-free column reads
-    __shared__ __align__(16) uint8_t ct[kHmWin * 2 * KT * 1024];
+    typedef HmShape<KT> S;
+    constexpr int QT = S::QT, W = S::W, ROWS = S::ROWS, NST = S::NST;
+    __shared__ __align__(16) uint8_t smem[NST * S::SB];
+    lds_u8 *L = (lds_u8 *)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
     const uint32_t sh = 4u * (uint32_t)g;
     const int64_t rbase = (int64_t)blockIdx.x * ROWS;
+    const uint64_t *Qwg = Q + rbase * ldq;   // this workgroup's rows
 
-    v16i acc[KT][kHmQT];
+    // Per-lane sources of the query loads: load i of a wave fills stage
+    // bytes [(i * 4 + wave) * 1024, +1024) = rows 32j .. 32j+31 (j = i * 4 +
+    // wave), lane l -> row 32j + l/2, slot l%2.  Rows past n re-read row n-1.
+    int qrow[S::NQL], qhalf[S::NQL];
+#pragma unroll
+    for (int i = 0; i < S::NQL; ++i) {
+        const int j = i * kWaves + wave;
+        int r = 32 * j + (lane >> 1);
+        qhalf[i] = hm_slot(r, lane & 1);
+        if (rbase + r >= n)
+            r = (int)(n - 1 - rbase);
+        qrow[i] = r;
+    }
+    // loads of window v (clamped to the last) into stage st
+    auto issue = [&](int v, int st) {
+        const int vc = v < nwin ? v : nwin - 1;
+        lds_u8 *sq = L + st * S::SB;
+#pragma unroll
+        for (int i = 0; i < S::NQL; ++i) {
+            // words past the hypervector re-read the first pair (class bytes are 0 there)
+            int w = w_lo + vc * W + 2 * qhalf[i];
+            if (w >= w_hi)
+                w = w_lo;
+            lds_dma16(Qwg, (uint32_t)(((int64_t)qrow[i] * ldq + w) * 8), sq + (i * kWaves + wave) * 1024);
+        }
+#pragma unroll
+        for (int i = 0; i < S::NTL; ++i) {
+            const int j = i * kWaves + wave;
+            lds_dma16(tab, (uint32_t)(vc * S::TB + j * 1024 + lane * 16), sq + S::QB + j * 1024);
+        }
+    };
+    constexpr int G = S::NQL + S::NTL;   // loads per wave per window
+
+    v16i acc[KT][QT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-        for (int qt = 0; qt < kHmQT; ++qt)
+        for (int qt = 0; qt < QT; ++qt)
             acc[kt][qt] = v16i{};
 
-    for (int w0 = w_lo; w0 < w_hi; w0 += kHmWin) {
-        const int nw = (w_hi - w0) < kHmWin ? (w_hi - w0) : kHmWin;
-        __syncthreads();   // previous window consumed
-        // queries: kHmWin lanes per row, consecutive words (coalesced rows)
 #pragma unroll
-        for (int p = 0; p < ROWS * kHmWin / 256; ++p) {
-            const int r = p * (256 / kHmWin) + t / kHmWin, ww = t % kHmWin;
-            const int64_t row = rbase + r;
-            uint64_t v = 0;
-            if (row < n && ww < nw)
-                v = Q[row * ldq + w0 + ww];
-            qs[r][ww] = v;
-        }
-        // class operand of the window, 16 bytes per thread per pass
-        {
-            const int64_t base = (int64_t)(w0 - w_lo) * 2 * KT * 1024;
-            const int bytes = nw * 2 * KT * 1024;
-            for (int o = t * 16; o < kHmWin * 2 * KT * 1024; o += 256 * 16) {
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (o < bytes)
-                    v = *(const uint4 *)(tab + base + o);
-                *(uint4 *)(ct + o) = v;
-            }
-        }
-        __syncthreads();
+    for (int v = 0; v < NST - 1; ++v)
+        issue(v, v);
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(G * (NST - 2)) : "memory");
 
-#pragma unroll 2
-        for (int ww = 0; ww < kHmWin; ++ww) {
-            uint64_t q[kHmQT];
+    int st = 0;
+    for (int v = 0; v < nwin; ++v) {
+        issue(v + NST - 1, st == 0 ? NST - 1 : st - 1);
+        const lds_u8 *sq = L + st * S::SB;
+        const lds_u8 *stb = sq + S::QB;
+        // query words of this wave's tiles: two 16-byte halves per row
+        v4i qv[QT][2];
 #pragma unroll
-            for (int qt = 0; qt < kHmQT; ++qt)
-                q[qt] = qs[(wave * kHmQT + qt) * 32 + (lane & 31)][ww];
+        for (int qt = 0; qt < QT; ++qt) {
+            const int r = (wave * QT + qt) * 32 + (lane & 31);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+                qv[qt][hh] = *(const lds_v4i *)(sq + r * (W * 8) + 16 * hm_slot(r, hh));
+        }
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 v4i af[KT];
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt)
-                    af[kt] = *(const v4i *)(ct + (((ww * 2 + h) * KT + kt) * 64 + lane) * 16);
+                    af[kt] = *(const lds_v4i *)(stb + (((ww * 2 + h) * KT + kt) * 64 + lane) * 16);
 #pragma unroll
-                for (int qt = 0; qt < kHmQT; ++qt) {
-                    const v4i bf = planes(h ? (uint32_t)(q[qt] >> 32) : (uint32_t)q[qt], sh);
+                for (int qt = 0; qt < QT; ++qt) {
+                    const uint32_t d = (uint32_t)qv[qt][ww >> 1][2 * (ww & 1) + h];
+                    const v4i bf = planes(d, sh);
 #pragma unroll
                     for (int kt = 0; kt < KT; ++kt)
                         acc[kt][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[kt], bf, acc[kt][qt], 0, 0, 0);
                 }
             }
         }
+        // window v+1 complete for this wave (only the window just issued may
+        // still be in flight), LDS reads done, all waves here
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(G * (NST - 2)) : "memory");
+        st = st == NST - 1 ? 0 : st + 1;
     }
+    // no load may still be writing this workgroup's LDS when it exits
+    __builtin_amdgcn_s_waitcnt(0);
 
     // argmin: lane holds query l%32 of each tile and classes 8(v/4)+4g+v%4
 #pragma unroll
-    for (int qt = 0; qt < kHmQT; ++qt) {
-        const int64_t q = rbase + (wave * kHmQT + qt) * 32 + (lane & 31);
+    for (int qt = 0; qt < QT; ++qt) {
+        const int64_t q = rbase + (wave * QT + qt) * 32 + (lane & 31);
         int bd = INT_MAX, bk = 0;
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
@@ -195,7 +245,7 @@ hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, 
                               hipStream_t st)
 {
     const HamLayout L(start, end, K);
-    const int64_t total = (int64_t)(L.w_hi - L.w_lo) * 2 * L.KT * 64;
+    const int64_t total = (int64_t)L.nwin * kHmWin * 2 * L.KT * 64;
     hipLaunchKernelGGL(k_ham_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc, start, end,
                        stride, L.w_lo, L.KT, total, (int8_t *)ws);
     hipError_t e = hipGetLastError();
@@ -216,7 +266,7 @@ hipError_t launch_ham_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K,
     if (L.KT == KT_) {                                                                                         \
         constexpr int R = HmShape<KT_>::ROWS;                                                                  \
         hipLaunchKernelGGL(k_hamming_mfma<KT_>, dim3((unsigned)((n + R - 1) / R)), dim3(256), 0, st, Q, n, ldq, \
-                           K, L.w_lo, L.w_hi, tab, popc, argmin, min_dist, dists);                             \
+                           K, L.w_lo, L.w_hi, L.nwin, tab, popc, argmin, min_dist, dists);                     \
         return hipGetLastError();                                                                              \
     }
     HDC_HM_CASE(1)

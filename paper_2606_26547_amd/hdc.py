@@ -197,6 +197,8 @@ class HammingPrepared:
 
     def __call__(self, Q: torch.Tensor, with_min=False, with_dists=False, out: torch.Tensor | None = None):
         n = Q.shape[0]
+        if Q.shape[1] % 2:                      # the search wants an even row pitch
+            Q = torch.nn.functional.pad(Q, (0, 1))
         lab = out if out is not None else torch.empty(n, dtype=torch.int32, device=Q.device)
         mn = torch.empty(n, dtype=torch.int32, device=Q.device) if with_min else None
         dists = torch.empty((n, self.K), dtype=torch.int32, device=Q.device) if with_dists else None

@@ -37,17 +37,20 @@ namespace hdc {
 // Shape per class-tile count: query tiles (32 queries) per wave, words per
 // window, LDS stages.
 template <int KT> struct HmShape {
-    static constexpr int QT = KT == 4 ? 2 : 4;
-    static constexpr int W = 4;                        // words per window
+    static constexpr int QT = KT == 1 ? 4 : 2;
+    static constexpr int W = KT == 4 ? 4 : 8;          // words per window (divides kHmWin)
+    static constexpr int U = W / 2;                    // 16-byte units per query row
+    static constexpr int RPL = 64 / U;                 // query rows per 1 KiB load
+    static constexpr int SWZ = U == 2 ? 3 : 2;         // row shift of the unit swizzle
     static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
     static constexpr int QB = ROWS * W * 8;            // query bytes per stage
     static constexpr int TB = W * 2 * KT * 1024;       // class operand bytes per window
-    static constexpr int NST = KT == 4 ? 3 : 4;        // LDS stages
+    static constexpr int NST = 3;                      // LDS stages
     static constexpr int NQL = QB / 1024 / kWaves;     // query loads per wave per window
     static constexpr int NTL = TB / 1024 / kWaves;     // class loads per wave per window
     static constexpr int SB = QB + TB;                 // bytes per stage
 };
-constexpr int kHmWin = 4;
+constexpr int kHmWin = 8;   // the class operand is padded to whole 8-word windows
 
 struct HamLayout {
     int w_lo, w_hi, nwin, KT;
@@ -109,10 +112,14 @@ __device__ __forceinline__ v4i planes(uint32_t d, uint32_t sh)
     return b;
 }
 
-// Query row r of a stage is 4 words = two 16-byte halves; half hh of the
-// window sits in slot hh ^ ((r >> 3) & 1), which keeps the 16-byte reads of
-// 16 consecutive rows on distinct banks.
-__device__ __forceinline__ int hm_slot(int r, int hh) { return hh ^ ((r >> 3) & 1); }
+// Query row r of a stage is W words = U 16-byte units; unit hh of the
+// window sits in slot hh ^ ((r >> SWZ) & (U - 1)), which keeps the 16-byte
+// reads of 16 consecutive rows on distinct banks.
+template <int KT> __device__ __forceinline__ int hm_slot(int r, int hh)
+{
+    typedef HmShape<KT> S;
+    return hh ^ ((r >> S::SWZ) & (S::U - 1));
+}
 
 template <int KT>
 __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq, int K,
@@ -130,14 +137,15 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
     const uint64_t *Qwg = Q + rbase * ldq;   // this workgroup's rows
 
     // Per-lane sources of the query loads: load i of a wave fills stage
-    // bytes [(i * 4 + wave) * 1024, +1024) = rows 32j .. 32j+31 (j = i * 4 +
-    // wave), lane l -> row 32j + l/2, slot l%2.  Rows past n re-read row n-1.
+    // bytes [(i * 4 + wave) * 1024, +1024) = rows RPL*j .. RPL*j + RPL-1
+    // (j = i * 4 + wave), lane l -> row RPL*j + l/U, slot l%U, which holds
+    // unit hm_slot(row, l%U) of the window.  Rows past n re-read row n-1.
     int qrow[S::NQL], qhalf[S::NQL];
 #pragma unroll
     for (int i = 0; i < S::NQL; ++i) {
         const int j = i * kWaves + wave;
-        int r = 32 * j + (lane >> 1);
-        qhalf[i] = hm_slot(r, lane & 1);
+        int r = S::RPL * j + lane / S::U;
+        qhalf[i] = hm_slot<KT>(r, lane % S::U);
         if (rbase + r >= n)
             r = (int)(n - 1 - rbase);
         qrow[i] = r;
@@ -179,14 +187,14 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
         issue(v + NST - 1, st == 0 ? NST - 1 : st - 1);
         const lds_u8 *sq = L + st * S::SB;
         const lds_u8 *stb = sq + S::QB;
-        // query words of this wave's tiles: two 16-byte halves per row
-        v4i qv[QT][2];
+        // query words of this wave's tiles: U 16-byte units per row
+        v4i qv[QT][S::U];
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt) {
             const int r = (wave * QT + qt) * 32 + (lane & 31);
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-                qv[qt][hh] = *(const lds_v4i *)(sq + r * (W * 8) + 16 * hm_slot(r, hh));
+            for (int hh = 0; hh < S::U; ++hh)
+                qv[qt][hh] = *(const lds_v4i *)(sq + r * (W * 8) + 16 * hm_slot<KT>(r, hh));
         }
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) {
@@ -264,9 +272,9 @@ hipError_t launch_ham_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K,
     const int32_t *popc = (const int32_t *)(ws + L.off_popc);
 #define HDC_HM_CASE(KT_)                                                                                       \
     if (L.KT == KT_) {                                                                                         \
-        constexpr int R = HmShape<KT_>::ROWS;                                                                  \
+        constexpr int R = HmShape<KT_>::ROWS, NW = kHmWin / HmShape<KT_>::W;                                   \
         hipLaunchKernelGGL(k_hamming_mfma<KT_>, dim3((unsigned)((n + R - 1) / R)), dim3(256), 0, st, Q, n, ldq, \
-                           K, L.w_lo, L.w_hi, L.nwin, tab, popc, argmin, min_dist, dists);                     \
+                           K, L.w_lo, L.w_hi, L.nwin * NW, tab, popc, argmin, min_dist, dists);                \
         return hipGetLastError();                                                                              \
     }
     HDC_HM_CASE(1)

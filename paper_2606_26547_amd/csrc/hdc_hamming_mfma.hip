@@ -27,7 +27,8 @@
 // walks the words in windows of W; the query words and the class operand of
 // a window go from global memory straight into an LDS ring of NST stages
 // (global_load_lds, 16 bytes per lane), NST - 1 windows ahead of the
-// window being multiplied, with one barrier per window.
+// window being multiplied, with one barrier per window; two workgroups
+// share each CU.
 #include <limits.h>
 
 #include "hdc_device.h"
@@ -36,16 +37,19 @@ namespace hdc {
 
 // Shape per class-tile count: query tiles (32 queries) per wave, words per
 // window, LDS stages.
+// Two stages keep the LDS footprint small enough for two workgroups per
+// CU: the second wave on each SIMD covers the first one's plane-building
+// VALU work, LDS waits and barriers, which pays more than deeper prefetch.
 template <int KT> struct HmShape {
-    static constexpr int QT = KT == 1 ? 4 : 2;
-    static constexpr int W = KT == 4 ? 4 : 8;          // words per window (divides kHmWin)
+    static constexpr int QT = KT == 4 ? 1 : 2;
+    static constexpr int W = KT == 1 ? 8 : 4;          // words per window (divides kHmWin)
     static constexpr int U = W / 2;                    // 16-byte units per query row
     static constexpr int RPL = 64 / U;                 // query rows per 1 KiB load
     static constexpr int SWZ = U == 2 ? 3 : 2;         // row shift of the unit swizzle
     static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
     static constexpr int QB = ROWS * W * 8;            // query bytes per stage
     static constexpr int TB = W * 2 * KT * 1024;       // class operand bytes per window
-    static constexpr int NST = 3;                      // LDS stages
+    static constexpr int NST = 2;                      // LDS stages
     static constexpr int NQL = QB / 1024 / kWaves;     // query loads per wave per window
     static constexpr int NTL = TB / 1024 / kWaves;     // class loads per wave per window
     static constexpr int SB = QB + TB;                 // bytes per stage

@@ -22,6 +22,7 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--batch 262144]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -52,6 +53,20 @@ def parse():
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(key: str, batch: int):
+    """HBM bytes per launch of a kernel from profiles/traffic.json (rocprofv3
+    FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when the kernel's
+    sources changed since the counters were taken or the batch differs."""
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in t["sources"])).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if h != t["sha256"] or int(t["batch"]) != batch:
+        return None
+    return float(t["bytes_per_launch"])
 
 
 def main():
@@ -143,7 +158,9 @@ def main():
         "accuracy_plain": acc_plain,
         "roofline": {"bound": "mfma", "kernel": "k_encode<int8, classify>", "achieved": achieved,
                      "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
-                     "traffic": None, "ms_per_launch": ms_kernel,
+                     "traffic": measured_traffic("k_encode_classify_speech_b262144", N),
+                     "traffic_unit": "bytes per launch (HBM read + write, profiles/traffic.json)",
+                     "ms_per_launch": ms_kernel,
                      "ops_per_launch": ops},
     }
 

@@ -242,6 +242,8 @@ def main():
         out["hamming_unfused"] = ham
         log("hamming GB/s: %s" % {k: (round(v["mfma"]["GB_s"], 1), round(v["popcount"]["GB_s"], 1), v["agree"])
                                   for k, v in ham.items()})
+        # -------------------------------------------------------- precision ladder
+        out["ladder"] = ladder(dev, dg, hdc, tuner, torch, np, event_loop, ds, Xte, Pd, Cw, Xqd, F, D)
         # -------------------------------------------------------- serving
         if args.serve_seconds > 0:
             out["serving"] = serving(args, dev, dg, hdc, tuner, torch)
@@ -263,6 +265,68 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
 
     print(json.dumps(out), flush=True)
+
+
+def flip_rate(Ha, Hb, nbits: int) -> float:
+    """Fraction of the first nbits bits of each row that differ."""
+    a = Ha.cpu().numpy().view(np.uint8)
+    b = Hb.cpu().numpy().view(np.uint8)
+    diff = np.unpackbits(a ^ b, axis=1, bitorder="little")[:, :nbits]
+    return float(diff.mean())
+
+
+def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F, D):
+    """The encoding precision ladder (int8 exact, bf16, fp8 E4M3) on both
+    integer workloads: bit flip rate of the query hypervectors against the
+    exact int8 encoding, accuracy, and fused-classifier throughput.  Speech:
+    its 1559 test queries (throughput on the 262144-query batch).  Image:
+    the uint8 workload trained on 60000 images, its 10000 test images, and
+    the 27-point (D', stride, dtype) grid of that workload evaluated in one
+    launch with the <= 1 point selection rule."""
+    res = {}
+    yte = torch.as_tensor(ds.y_test).to(dev)
+    Hx = hdc.encode(Xte, F, Pd, D, "int8")
+    sp = {}
+    for t in ("int8", "bf16", "fp8"):
+        H = hdc.encode(Xte, F, Pd, D, t)
+        lab = hdc.classify(Xte, F, Pd, D, Cw, t)
+        prep = hdc.Prepared(Cw, D, t)
+        lb = torch.empty(Xqd.shape[0], dtype=torch.int32, device=dev)
+        _, ms, _ = event_loop(lambda: prep(Xqd, F, Pd, lb), 5, 1)
+        sp[t] = {"flip_rate": flip_rate(H, Hx, D), "accuracy": float((lab == yte).float().mean().item()),
+                 "ms_batch": ms, "queries_per_s": Xqd.shape[0] / (ms / 1e3)}
+    res["speech"] = sp
+    log("ladder speech: %s" % {t: (round(v["flip_rate"], 5), round(v["accuracy"], 4), round(v["ms_batch"], 3))
+                               for t, v in sp.items()})
+    img = dg.ImageLike(3).dataset()
+    Fi, Ki, Di = img.F, img.K, img.D
+    Pi = hdc.pad_cols(img.P, dev)
+    Xi_tr = hdc.pad_cols(img.X_train, dev)
+    Xi_te = hdc.pad_cols(img.X_test, dev)
+    yi_tr = torch.as_tensor(img.y_train, dtype=torch.int32).to(dev)
+    yi_te = torch.as_tensor(img.y_test, dtype=torch.int32).to(dev)
+    Hi = hdc.encode(Xi_tr, Fi, Pi, Di, "int8")
+    Ci, _ = hdc.bundle(Hi, Di, yi_tr, Ki)
+    Hx = hdc.encode(Xi_te, Fi, Pi, Di, "int8")
+    im = {}
+    for t in ("int8", "bf16", "fp8"):
+        H = hdc.encode(Xi_te, Fi, Pi, Di, t)
+        lab = hdc.classify(Xi_te, Fi, Pi, Di, Ci, t)
+        prep = hdc.Prepared(Ci, Di, t)
+        lb = torch.empty(Xi_te.shape[0], dtype=torch.int32, device=dev)
+        _, ms, _ = event_loop(lambda: prep(Xi_te, Fi, Pi, lb), 5, 1)
+        im[t] = {"flip_rate": flip_rate(H, Hx, Di), "accuracy": float((lab == yi_te).float().mean().item()),
+                 "ms_10000": ms, "queries_per_s": Xi_te.shape[0] / (ms / 1e3)}
+    grid = [(d, k, 0, t) for d in (2048, 4096, 8192) for k in (1, 2, 4) for t in ("int8", "bf16", "fp8")]
+    results = tuner.sweep(Xi_te, Fi, yi_te, Pi, Di, Ci, grid)
+    best, plain = tuner.select_tuned(results, (Di, 1, 0, "int8"), 1.0,
+                                     timer=lambda c: tuner.time_config(c, Xi_te, Fi, Pi, Di, Ci))
+    im["grid"] = [{"cfg": list(r.cfg), "accuracy": r.accuracy, "device_us": r.device_us} for r in results]
+    im["tuned"] = {"cfg": list(best.cfg), "accuracy": best.accuracy, "accuracy_plain": plain.accuracy}
+    res["image"] = im
+    log("ladder image: %s; tuned %s" % ({t: (round(v["flip_rate"], 5), round(v["accuracy"], 4)) for t, v in im.items()
+                                        if t in ("int8", "bf16", "fp8")}, best.cfg))
+    return res
 
 
 def serving(args, dev, dg, hdc, tuner, torch):

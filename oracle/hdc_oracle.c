@@ -393,3 +393,55 @@ void or_eval_configs(const void *X, int x_type, int64_t n, int32_t F, int64_t ld
     }
     free(lab);
 }
+
+/* ------------------------------------------------------------------------
+ * Retraining: integer class accumulators and one epoch of mispredicted-row
+ * updates (see the header for the reading of the rule).
+ * ---------------------------------------------------------------------- */
+static int32_t bipolar(const uint64_t *h, int32_t d)
+{
+    return get_bit(h, d) ? -1 : 1;
+}
+
+void or_class_acc(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                  const int32_t *labels, int32_t K, int32_t *acc)
+{
+    memset(acc, 0, (size_t)K * nbits * sizeof(int32_t));
+    for (int64_t i = 0; i < n; i++) {
+        int32_t k = labels[i];
+        assert(k >= 0 && k < K);
+        for (int32_t d = 0; d < nbits; d++)
+            acc[(int64_t)k * nbits + d] += bipolar(H + i * ldh, d);
+    }
+}
+
+int64_t or_retrain_epoch(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                         const int32_t *labels, const int32_t *pred, int32_t K, int32_t *acc)
+{
+    int64_t wrong = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t y = labels[i], p = pred[i];
+        assert(y >= 0 && y < K && p >= 0 && p < K);
+        if (p == y)
+            continue;
+        wrong++;
+        for (int32_t d = 0; d < nbits; d++) {
+            int32_t b = bipolar(H + i * ldh, d);
+            acc[(int64_t)y * nbits + d] += b;
+            acc[(int64_t)p * nbits + d] -= b;
+        }
+    }
+    return wrong;
+}
+
+void or_binarize(const int32_t *acc, int32_t K, int32_t nbits, uint64_t *C, int64_t ldc)
+{
+    int64_t W = (nbits + 63) / 64;
+    for (int32_t k = 0; k < K; k++) {
+        uint64_t *c = C + (int64_t)k * ldc;
+        memset(c, 0, (size_t)W * sizeof(uint64_t));
+        for (int32_t d = 0; d < nbits; d++)
+            if (acc[(int64_t)k * nbits + d] < 0)
+                c[d / 64] |= 1ULL << (d % 64);
+    }
+}

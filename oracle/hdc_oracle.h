@@ -130,6 +130,24 @@ void or_eval_configs(const void *X, int x_type, int64_t n, int32_t F, int64_t ld
                      const int32_t *cfg, int32_t ncfg, int32_t *correct, int threads);
 
 /* Number of OpenMP threads a call with `threads` (<= 0: all) will use. */
+/* Retraining (Sec. 5, the TRAIN_ITERATIONS knob of the apps; the update
+ * rule is not stated in the paper -- the reading taken here is the usual
+ * perceptron-style one, applied to a whole epoch at once):
+ *   acc[k][d] = sum over rows i of class k of b_i(d),  b = +1 for bit 0, -1
+ *               for bit 1 (the bipolar sum that majority bundling
+ *               thresholds);
+ *   one epoch, with pred[i] the label the model at the start of the epoch
+ *   gives row i: for every row with pred[i] != labels[i],
+ *               acc[labels[i]] += b_i and acc[pred[i]] -= b_i;
+ *   binarised model: bit d of class k is 1 exactly when acc[k][d] < 0
+ *               (zero gives +1, as in bundling).
+ * acc is [K][nbits] int32. */
+void or_class_acc(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                  const int32_t *labels, int32_t K, int32_t *acc);
+int64_t or_retrain_epoch(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                         const int32_t *labels, const int32_t *pred, int32_t K, int32_t *acc);
+void or_binarize(const int32_t *acc, int32_t K, int32_t nbits, uint64_t *C, int64_t ldc);
+
 int or_threads(int threads);
 
 #ifdef __cplusplus

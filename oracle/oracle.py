@@ -50,6 +50,9 @@ def lib():
         L.or_round_e4m3.argtypes = [dbl]; L.or_round_e4m3.restype = dbl
         L.or_dims_count.argtypes = [i32, i32, i32]; L.or_dims_count.restype = i32
         L.or_threads.argtypes = [C.c_int]; L.or_threads.restype = C.c_int
+        L.or_class_acc.argtypes = [p, i64, i32, i64, p, i32, p]
+        L.or_retrain_epoch.argtypes = [p, i64, i32, i64, p, p, i32, p]; L.or_retrain_epoch.restype = i64
+        L.or_binarize.argtypes = [p, i32, i32, p, i64]
         L.or_encode.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, i64, C.c_int]
         L.or_project.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, p, C.c_int]
         L.or_bundle.argtypes = [p, i64, i32, i64, p, i32, p, i64, p]
@@ -202,3 +205,42 @@ def train(X, y, P, K, compute="int8", threads=0):
     """Class hypervectors of a training set: encode (exact) then bundle."""
     H = encode(X, P, compute, threads=threads)
     return bundle(H, y, K, P.shape[0])
+
+
+def class_acc(H, labels, K, nbits):
+    """Integer class accumulators acc[K][nbits] (bipolar sums per class)."""
+    H = _c(H, np.uint64)
+    labels = _c(labels, np.int32)
+    acc = np.zeros((K, nbits), dtype=np.int32)
+    lib().or_class_acc(_ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(acc))
+    return acc
+
+
+def retrain_epoch(H, labels, pred, acc, nbits):
+    """One retraining epoch in place on acc; returns the number of mispredicted rows."""
+    H = _c(H, np.uint64)
+    labels = _c(labels, np.int32)
+    pred = _c(pred, np.int32)
+    assert acc.dtype == np.int32 and acc.flags.c_contiguous
+    return int(lib().or_retrain_epoch(_ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), _ptr(pred),
+                                      acc.shape[0], _ptr(acc)))
+
+
+def binarize(acc, nbits):
+    acc = _c(acc, np.int32)
+    Cw = np.zeros((acc.shape[0], words(nbits)), dtype=np.uint64)
+    lib().or_binarize(_ptr(acc), acc.shape[0], nbits, _ptr(Cw), Cw.shape[1])
+    return Cw
+
+
+def retrain(H, labels, K, nbits, epochs):
+    """Bundle, then `epochs` retraining epochs, each predicting every row with
+    the model at the start of the epoch (exact Hamming over all nbits).
+    Returns (C, acc, wrong-per-epoch)."""
+    acc = class_acc(H, labels, K, nbits)
+    hist = []
+    for _ in range(epochs):
+        Cw = binarize(acc, nbits)
+        pred, _ = argmin(hamming_popcount(H, Cw, 0, nbits, 1))
+        hist.append(retrain_epoch(H, labels, pred, acc, nbits))
+    return binarize(acc, nbits), acc, hist

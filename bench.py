@@ -242,6 +242,8 @@ def main():
         out["hamming_unfused"] = ham
         log("hamming GB/s: %s" % {k: (round(v["mfma"]["GB_s"], 1), round(v["popcount"]["GB_s"], 1), v["agree"])
                                   for k, v in ham.items()})
+        # -------------------------------------------------------- retraining epochs
+        out["retrain"] = retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
         # -------------------------------------------------------- precision ladder
         out["ladder"] = ladder(dev, dg, hdc, tuner, torch, np, event_loop, ds, Xte, Pd, Cw, Xqd, F, D)
         # -------------------------------------------------------- serving
@@ -265,6 +267,33 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
 
     print(json.dumps(out), flush=True)
+
+
+def retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D, epochs=6):
+    """Retraining epochs on the speech workload (the apps' TRAIN_ITERATIONS):
+    training-set errors and test accuracy after each epoch, and the device
+    time of one epoch (predict all 6238 training rows + accumulator update)."""
+    from paper_2606_26547_amd import train
+    H = hdc.encode(Xtr, F, Pd, D)
+    yte = torch.as_tensor(ds.y_test).to(dev)
+    acc_by_epoch, wrong = [], []
+    for e in range(epochs + 1):
+        Cw, _, w = train.fit(H, D, ytr, K, e)
+        lab = hdc.classify(Xte, F, Pd, D, Cw)
+        acc_by_epoch.append(float((lab == yte).float().mean().item()))
+        if w:
+            wrong.append(int(w[-1].item()))
+    acc, Cw = hdc.class_acc(H, D, ytr, K)
+    pred = torch.empty(H.shape[0], dtype=torch.int32, device=dev)
+
+    def epoch():
+        hdc.HammingPrepared(Cw, 0, D, 1)(H, out=pred)
+        hdc.retrain_epoch(H, D, ytr, pred, acc, Cw)
+    _, ms, _ = event_loop(epoch, 5, 1)
+    log("retrain: test accuracy by epoch %s, training errors %s, %.3f ms/epoch" %
+        ([round(a, 4) for a in acc_by_epoch], wrong, ms))
+    return {"test_accuracy_by_epoch": acc_by_epoch, "train_errors_at_epoch_start": wrong, "ms_per_epoch": ms,
+            "rule": "mispredicted rows: acc[true] += b, acc[pred] -= b; model = sign(acc)"}
 
 
 def flip_rate(Ha, Hb, nbits: int) -> float:

@@ -127,6 +127,37 @@ hdc_status hdc_bundle(void *stream,
                       void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
+ * hdc_class_acc / hdc_retrain_epoch -- retraining (Sec. 5: the apps'
+ * TRAIN_ITERATIONS knob, whose iterations the tuner cuts; the update rule
+ * itself is not stated in the paper, the one implemented is the usual
+ * perceptron-style rule applied to a whole epoch).  With b_i the bipolar
+ * form of row i of H (+1 for bit 0, -1 for bit 1):
+ *   hdc_class_acc:     acc[k][d] = sum over rows i with labels[i] == k of
+ *                      b_i(d)  (the sum that majority bundling thresholds)
+ *   hdc_retrain_epoch: for every row with pred[i] != labels[i],
+ *                      acc[labels[i]] += b_i and acc[pred[i]] -= b_i
+ * Both then write the model C: bit d of class k is 1 exactly when
+ * acc[k][d] < 0 (zero gives +1, the bundling tie rule).  pred is the label
+ * each row gets from the model at the start of the epoch (e.g. from
+ * hdc_hamming_argmin over all nbits).  Integer updates: the result does not
+ * depend on the order rows are visited.
+ *   H       [n][ldh] uint64 training hypervectors (nbits valid bits)
+ *   labels  [n] int32 in [0, K)   pred [n] int32 in [0, K)
+ *   acc     [K][nbits] int32, written (class_acc) / updated (epoch)
+ *   C       [K][ldc] uint64 output, ldc >= ceil(nbits / 64)
+ *   n_wrong device int32 output (rows with pred != label), may be NULL
+ * Supports K <= 128.  No workspace.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_class_acc(void *stream,
+                         const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                         const int32_t *labels, int32_t K,
+                         int32_t *acc, uint64_t *C, int64_t ldc);
+hdc_status hdc_retrain_epoch(void *stream,
+                             const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                             const int32_t *labels, const int32_t *pred, int32_t K,
+                             int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong);
+
+/* ---------------------------------------------------------------------
  * hdc_hamming_argmin -- Hamming distance of each query hypervector to every
  * class hypervector with reduction perforation, then argmin (Sec. 2.2
  * Listing 1: hamming_distance, red_perf, arg_min; Sec. 4.2).

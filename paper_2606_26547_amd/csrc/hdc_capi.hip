@@ -192,6 +192,42 @@ hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_
                                    dists, (hipStream_t)stream));
 }
 
+static hdc_status check_retrain(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh, const int32_t *labels,
+                                int32_t K, const int32_t *acc, const uint64_t *C, int64_t ldc)
+{
+    if (n < 0 || nbits <= 0 || K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK)
+        return HDC_ERR_UNSUPPORTED;
+    const int64_t W = (nbits + 63) / 64;
+    if (!acc || !C || ldc < W || (n > 0 && (!H || !labels || ldh < W)))
+        return HDC_ERR_INVALID;
+    return HDC_OK;
+}
+
+hdc_status hdc_class_acc(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                         const int32_t *labels, int32_t K, int32_t *acc, uint64_t *C, int64_t ldc)
+{
+    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc);
+    if (s != HDC_OK)
+        return s;
+    return from_hip(launch_retrain(H, n, nbits, ldh, labels, nullptr, K, acc, C, ldc, nullptr,
+                                   (hipStream_t)stream));
+}
+
+hdc_status hdc_retrain_epoch(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                             const int32_t *labels, const int32_t *pred, int32_t K, int32_t *acc, uint64_t *C,
+                             int64_t ldc, int32_t *n_wrong)
+{
+    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc);
+    if (s != HDC_OK)
+        return s;
+    if (n > 0 && !pred)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_retrain(H, n, nbits, ldh, labels, pred, K, acc, C, ldc, n_wrong,
+                                   (hipStream_t)stream));
+}
+
 static hdc_status check_perf(hdc_dims perf, int32_t K)
 {
     if (K <= 0 || perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)

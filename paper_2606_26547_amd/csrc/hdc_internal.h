@@ -76,6 +76,9 @@ hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint6
 hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
                          int K, uint64_t *C, int64_t ldc, int32_t *counts, int32_t *ws_cnt,
                          hipStream_t st);
+hipError_t launch_retrain(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
+                          const int32_t *pred, int K, int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong,
+                          hipStream_t st);
 hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute,
                           float *out, hipStream_t st);
 

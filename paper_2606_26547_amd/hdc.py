@@ -36,7 +36,7 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
-           "hdc_convert_features"]
+           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch"]
 
 
 class Dims(C.Structure):
@@ -85,6 +85,8 @@ _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i3
 _lib.hdc_device_clock_hz.restype = C.c_double
 _lib.hdc_device_clock_hz.argtypes = []
 _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int, _p]
+_lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
+_lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
 for _name in EXPORTS:
     assert hasattr(_lib, _name)
 
@@ -259,6 +261,23 @@ class Prepared:
                                           _ptr(dists), _ptr(self.ws), self.ws.numel()),
                "hdc_classify_prepared")
         return (labels, dists) if with_dists else labels
+
+
+def class_acc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int):
+    """hdc_class_acc: (acc[K][nbits] int32, C[K][words] int64) from training rows."""
+    acc = torch.empty((K, nbits), dtype=torch.int32, device=H.device)
+    Cw = torch.empty((K, words(nbits)), dtype=torch.int64, device=H.device)
+    _check(_lib.hdc_class_acc(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(acc),
+                              _ptr(Cw), Cw.shape[1]), "hdc_class_acc")
+    return acc, Cw
+
+
+def retrain_epoch(H: torch.Tensor, nbits: int, labels: torch.Tensor, pred: torch.Tensor, acc: torch.Tensor,
+                  Cw: torch.Tensor, n_wrong: torch.Tensor | None = None):
+    """hdc_retrain_epoch: updates acc and Cw in place; n_wrong (device int32[1]) if given."""
+    _check(_lib.hdc_retrain_epoch(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), _ptr(pred),
+                                  acc.shape[0], _ptr(acc), _ptr(Cw), Cw.shape[1], _ptr(n_wrong)),
+           "hdc_retrain_epoch")
 
 
 def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:

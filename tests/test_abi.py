@@ -74,3 +74,15 @@ def test_validation_without_device(lib):
     assert lib.hdc_hamming_workspace_bytes(Dims(0, 70000, 1), 26) == 0
     lib.hdc_bundle_workspace_bytes.restype = C.c_size_t
     assert lib.hdc_bundle_workspace_bytes(10240, 26) == 4 * 26 * 10241
+
+
+def test_retrain_validation_without_device(lib):
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_class_acc.argtypes = [p, p, i64, i32, i64, p, i32, p, p, i64]
+    lib.hdc_retrain_epoch.argtypes = [p, p, i64, i32, i64, p, p, i32, p, p, i64, p]
+    fake = C.c_void_p(1 << 20)
+    assert lib.hdc_class_acc(None, fake, 4, 0, 1, fake, 3, fake, fake, 1) == 1        # nbits <= 0
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 200, fake, fake, 1) == 2     # K > 128
+    assert lib.hdc_class_acc(None, fake, 4, 130, 2, fake, 3, fake, fake, 3) == 1      # ldh < words
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, None, fake, 1) == 1       # no acc
+    assert lib.hdc_retrain_epoch(None, fake, 4, 64, 1, fake, None, 3, fake, fake, 1, None) == 1   # no pred

@@ -445,3 +445,58 @@ void or_binarize(const int32_t *acc, int32_t K, int32_t nbits, uint64_t *C, int6
                 c[d / 64] |= 1ULL << (d % 64);
     }
 }
+
+/* ------------------------------------------------------------------------
+ * ADC-chunked similarity (see the header for the reading of the quantiser).
+ * ---------------------------------------------------------------------- */
+int32_t or_adc_quantize(int32_t s, int32_t res, int32_t step, int32_t floor_, int32_t ceil_)
+{
+    int64_t x = s < floor_ ? floor_ : (s > ceil_ ? ceil_ : s);
+    /* floor((x - floor) / step + 1/2) with x - floor >= 0 */
+    int64_t code = (2 * (x - floor_) + step) / (2 * (int64_t)step);
+    int64_t top = (1LL << res) - 1;
+    if (code > top)
+        code = top;
+    return (int32_t)(floor_ + step * code);
+}
+
+void or_adc_scores(const uint64_t *Q, int64_t n, int64_t ldq,
+                   const uint64_t *C, int32_t K, int64_t ldc,
+                   int32_t start, int32_t end, int32_t stride,
+                   int32_t res, int32_t step, int32_t floor_, int32_t ceil_,
+                   int32_t *scores, int threads)
+{
+    int64_t nchunks = (end + 127) / 128;
+#pragma omp parallel for num_threads(or_threads(threads)) schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t k = 0; k < K; k++) {
+            int32_t total = 0;
+            for (int64_t c = 0; c < nchunks; c++) {
+                int32_t sc = 0, used = 0;
+                for (int64_t d = 128 * c; d < 128 * c + 128 && d < end; d++) {
+                    if (d < start || (d - start) % stride != 0)
+                        continue;
+                    int32_t bq = get_bit(Q + i * ldq, d) ? -1 : 1;
+                    int32_t bk = get_bit(C + (int64_t)k * ldc, d) ? -1 : 1;
+                    sc += bq * bk;
+                    used++;
+                }
+                if (used)   /* a chunk with no dimension of S is not converted */
+                    total += or_adc_quantize(sc, res, step, floor_, ceil_);
+            }
+            scores[i * K + k] = total;
+        }
+}
+
+void or_argmax(const int32_t *scores, int64_t n, int32_t K, int32_t *label, int32_t *max_score)
+{
+    for (int64_t i = 0; i < n; i++) {
+        int32_t best = 0;
+        for (int32_t k = 1; k < K; k++)
+            if (scores[i * K + k] > scores[i * K + best])
+                best = k;
+        label[i] = best;
+        if (max_score)
+            max_score[i] = scores[i * K + best];
+    }
+}

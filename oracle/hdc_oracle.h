@@ -148,6 +148,26 @@ int64_t or_retrain_epoch(const uint64_t *H, int64_t n, int32_t nbits, int64_t ld
                          const int32_t *labels, const int32_t *pred, int32_t K, int32_t *acc);
 void or_binarize(const int32_t *acc, int32_t K, int32_t nbits, uint64_t *C, int64_t ldc);
 
+/* ADC-chunked dot-product similarity (Sec. 3, in-memory accelerator knobs
+ * (I) ADC resolution and (III) analog quantisation scale; Sec. 6 SpecPCM:
+ * dot products over 128-element array chunks, each partial product
+ * quantised by the ADC before accumulation).  Reading of the unstated
+ * quantiser: with the partial s_c = sum over d in chunk c (dimensions
+ * [128c, 128c+128)) and in S of b_q(d) * b_k(d) (bipolar +-1),
+ *   x = min(max(s_c, floor), ceil),
+ *   code = min(floor((x - floor) / step + 1/2), 2^res - 1),
+ *   value = floor + step * code;
+ * score[i][k] = sum_c value_c over the chunks that hold at least one
+ * dimension of S (a chunk with none is not converted), label = first class
+ * with the largest score. */
+int32_t or_adc_quantize(int32_t s, int32_t res, int32_t step, int32_t floor_, int32_t ceil_);
+void or_adc_scores(const uint64_t *Q, int64_t n, int64_t ldq,
+                   const uint64_t *C, int32_t K, int64_t ldc,
+                   int32_t start, int32_t end, int32_t stride,
+                   int32_t res, int32_t step, int32_t floor_, int32_t ceil_,
+                   int32_t *scores, int threads);
+void or_argmax(const int32_t *scores, int64_t n, int32_t K, int32_t *label, int32_t *max_score);
+
 int or_threads(int threads);
 
 #ifdef __cplusplus

@@ -53,6 +53,9 @@ def lib():
         L.or_class_acc.argtypes = [p, i64, i32, i64, p, i32, p]
         L.or_retrain_epoch.argtypes = [p, i64, i32, i64, p, p, i32, p]; L.or_retrain_epoch.restype = i64
         L.or_binarize.argtypes = [p, i32, i32, p, i64]
+        L.or_adc_quantize.argtypes = [i32, i32, i32, i32, i32]; L.or_adc_quantize.restype = i32
+        L.or_adc_scores.argtypes = [p, i64, i64, p, i32, i64, i32, i32, i32, i32, i32, i32, i32, p, C.c_int]
+        L.or_argmax.argtypes = [p, i64, i32, p, p]
         L.or_encode.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, i64, C.c_int]
         L.or_project.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, p, C.c_int]
         L.or_bundle.argtypes = [p, i64, i32, i64, p, i32, p, i64, p]
@@ -244,3 +247,25 @@ def retrain(H, labels, K, nbits, epochs):
         pred, _ = argmin(hamming_popcount(H, Cw, 0, nbits, 1))
         hist.append(retrain_epoch(H, labels, pred, acc, nbits))
     return binarize(acc, nbits), acc, hist
+
+
+def adc_quantize(s, res, step, floor_, ceil_):
+    return int(lib().or_adc_quantize(int(s), res, step, floor_, ceil_))
+
+
+def adc_scores(Q, Cw, start, end, stride, res, step, floor_, ceil_, threads=0):
+    """ADC-chunked dot-product scores [n][K] (128-dimension chunks)."""
+    Q = _c(Q, np.uint64)
+    Cw = _c(Cw, np.uint64)
+    sc = np.zeros((Q.shape[0], Cw.shape[0]), dtype=np.int32)
+    lib().or_adc_scores(_ptr(Q), Q.shape[0], Q.shape[1], _ptr(Cw), Cw.shape[0], Cw.shape[1], start, end, stride,
+                        res, step, floor_, ceil_, _ptr(sc), threads)
+    return sc
+
+
+def argmax(scores):
+    scores = _c(scores, np.int32)
+    lab = np.zeros(scores.shape[0], dtype=np.int32)
+    mx = np.zeros(scores.shape[0], dtype=np.int32)
+    lib().or_argmax(_ptr(scores), scores.shape[0], scores.shape[1], _ptr(lab), _ptr(mx))
+    return lab, mx

@@ -242,6 +242,8 @@ def main():
         out["hamming_unfused"] = ham
         log("hamming GB/s: %s" % {k: (round(v["mfma"]["GB_s"], 1), round(v["popcount"]["GB_s"], 1), v["agree"])
                                   for k, v in ham.items()})
+        # -------------------------------------------------------- ADC-chunked similarity
+        out["adc"] = adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D)
         # -------------------------------------------------------- retraining epochs
         out["retrain"] = retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
         # -------------------------------------------------------- precision ladder
@@ -267,6 +269,28 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
 
     print(json.dumps(out), flush=True)
+
+
+def adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D):
+    """Dot-product similarity over 128-element chunks with ADC quantisation
+    (the in-memory accelerator knobs): test accuracy of the speech model for
+    the paper's reference ADC setting and the settings its tuner picked, and
+    the search throughput on 2^20 query hypervectors."""
+    yte = torch.as_tensor(ds.y_test).to(dev)
+    Hte = hdc.encode(Xte, F, Pd, D)
+    settings = {"reference 8b step1 [-127,128]": (8, 1, -127, 128), "tuned 8b step2 [-3,128]": (8, 2, -3, 128),
+                "6b step9 [-3,128]": (6, 9, -3, 128), "4b step16 [-127,128]": (4, 16, -127, 128)}
+    res = {"hamming_accuracy": float((hdc.hamming_argmin(Hte, Cw, 0, D, 1)[0] == yte).float().mean().item())}
+    for name, a in settings.items():
+        lab, _, _ = hdc.adc_argmax(Hte, Cw, 0, D, 1, a)
+        res[name] = {"adc": list(a), "accuracy": float((lab == yte).float().mean().item())}
+    nq = 1 << 20
+    Q = torch.randint(-(1 << 62), 1 << 62, (nq, D // 64), dtype=torch.int64, device=dev)
+    _, ms, _ = event_loop(lambda: hdc.adc_argmax(Q, Cw, 0, D, 1, (8, 2, -3, 128)), 5, 1)
+    res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9}
+    del Q
+    log("adc: %s" % {k: (v["accuracy"] if isinstance(v, dict) and "accuracy" in v else v) for k, v in res.items()})
+    return res
 
 
 def retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D, epochs=6):

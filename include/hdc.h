@@ -201,6 +201,36 @@ hdc_status hdc_hamming_argmin_prepared(void *stream,
                                        const void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
+ * hdc_adc_argmax -- dot-product similarity as an in-memory accelerator
+ * computes it (Sec. 3 "In-Memory Accelerator Approximations": (I) ADC
+ * resolution, (III) analog quantization scale; Sec. 6 SpecPCM: dot
+ * products over 128-element array chunks, each partial product quantized
+ * by the ADC before accumulation).  For query i and class k, with b the
+ * bipolar form of a hypervector (+1 for bit 0, -1 for bit 1) and chunk c
+ * the dimensions [128c, 128c+128) that lie in S(perf):
+ *     s_c   = sum over d in chunk c of b_q(d) * b_k(d)
+ *     x     = min(max(s_c, adc.floor), adc.ceil)
+ *     code  = min(floor((x - adc.floor) / adc.step + 1/2), 2^adc.res_bits - 1)
+ *     score = sum over chunks holding a dimension of S of adc.floor + adc.step * code
+ * label[i] is the lowest k with the largest score.  The paper's reference
+ * configuration {8, 1, -127, 128} reproduces the unquantized dot product
+ * (except a partial of -128, which clips to -127).
+ *   Q [n][ldq], C [K][ldc] uint64 (>= perf.end valid bits)
+ *   label [n] int32 output; max_score [n], scores [n][K] int32, may be NULL
+ * Supports K <= 128, perf.end <= 65536, 1 <= res_bits <= 16, step >= 1,
+ * floor <= ceil.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t res_bits, step, floor, ceil;
+} hdc_adc;
+
+hdc_status hdc_adc_argmax(void *stream,
+                          const uint64_t *Q, int64_t n, int64_t ldq,
+                          const uint64_t *C, int32_t K, int64_t ldc,
+                          hdc_dims perf, hdc_adc adc,
+                          int32_t *label, int32_t *max_score, int32_t *scores);
+
+/* ---------------------------------------------------------------------
  * hdc_classify -- the fused inference path: encode each query over the
  * dimensions S(dims) under `compute`, compare bit j of the query with bit
  * S_j of each (full-D) class hypervector, argmin.  Equal, bit for bit, to

@@ -228,6 +228,30 @@ hdc_status hdc_retrain_epoch(void *stream, const uint64_t *H, int64_t n, int32_t
                                    (hipStream_t)stream));
 }
 
+hdc_status hdc_adc_argmax(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int32_t K,
+                          int64_t ldc, hdc_dims perf, hdc_adc adc, int32_t *label, int32_t *max_score,
+                          int32_t *scores)
+{
+    if (n < 0 || K <= 0)
+        return HDC_ERR_INVALID;
+    if (K > kMaxK || perf.end > 65536)
+        return HDC_ERR_UNSUPPORTED;
+    if (perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)
+        return HDC_ERR_INVALID;
+    if (adc.res_bits < 1 || adc.res_bits > 16 || adc.step < 1 || adc.floor > adc.ceil)
+        return HDC_ERR_INVALID;
+    const int64_t W = (perf.end + 63) / 64;
+    if (!C || ldc < W)
+        return HDC_ERR_INVALID;
+    if (n == 0)
+        return HDC_OK;
+    if (!Q || ldq < W || !label)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_adc_argmax(Q, n, ldq, C, K, ldc, perf.start, perf.end, perf.stride, adc.res_bits,
+                                      adc.step, adc.floor, adc.ceil, label, max_score, scores,
+                                      (hipStream_t)stream));
+}
+
 static hdc_status check_perf(hdc_dims perf, int32_t K)
 {
     if (K <= 0 || perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)

@@ -79,6 +79,9 @@ hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, c
 hipError_t launch_retrain(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
                           const int32_t *pred, int K, int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong,
                           hipStream_t st);
+hipError_t launch_adc_argmax(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
+                             int start, int end, int stride, int res, int step, int floor_, int ceil_,
+                             int32_t *label, int32_t *max_score, int32_t *scores, hipStream_t st);
 hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute,
                           float *out, hipStream_t st);
 

@@ -36,11 +36,15 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
-           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch"]
+           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax"]
 
 
 class Dims(C.Structure):
     _fields_ = [("start", C.c_int32), ("end", C.c_int32), ("stride", C.c_int32)]
+
+
+class Adc(C.Structure):
+    _fields_ = [("res_bits", C.c_int32), ("step", C.c_int32), ("floor", C.c_int32), ("ceil", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -85,6 +89,7 @@ _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i3
 _lib.hdc_device_clock_hz.restype = C.c_double
 _lib.hdc_device_clock_hz.argtypes = []
 _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int, _p]
+_lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
 _lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
 _lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
 for _name in EXPORTS:
@@ -261,6 +266,18 @@ class Prepared:
                                           _ptr(dists), _ptr(self.ws), self.ws.numel()),
                "hdc_classify_prepared")
         return (labels, dists) if with_dists else labels
+
+
+def adc_argmax(Q: torch.Tensor, Cw: torch.Tensor, start: int, end: int, stride: int, adc, with_max=False,
+               with_scores=False):
+    """hdc_adc_argmax: adc = (res_bits, step, floor, ceil)."""
+    n, K = Q.shape[0], Cw.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device=Q.device)
+    mx = torch.empty(n, dtype=torch.int32, device=Q.device) if with_max else None
+    sc = torch.empty((n, K), dtype=torch.int32, device=Q.device) if with_scores else None
+    _check(_lib.hdc_adc_argmax(_stream(), _ptr(Q), n, Q.shape[1], _ptr(Cw), K, Cw.shape[1], Dims(start, end, stride),
+                               Adc(*adc), _ptr(lab), _ptr(mx), _ptr(sc)), "hdc_adc_argmax")
+    return lab, mx, sc
 
 
 def class_acc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int):

@@ -86,3 +86,20 @@ def test_retrain_validation_without_device(lib):
     assert lib.hdc_class_acc(None, fake, 4, 130, 2, fake, 3, fake, fake, 3) == 1      # ldh < words
     assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, None, fake, 1) == 1       # no acc
     assert lib.hdc_retrain_epoch(None, fake, 4, 64, 1, fake, None, 3, fake, fake, 1, None) == 1   # no pred
+
+
+class Adc(C.Structure):
+    _fields_ = [("res_bits", C.c_int32), ("step", C.c_int32), ("floor", C.c_int32), ("ceil", C.c_int32)]
+
+
+def test_adc_validation_without_device(lib):
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_adc_argmax.argtypes = [p, p, i64, i64, p, i32, i64, Dims, Adc, p, p, p]
+    fake = C.c_void_p(1 << 20)
+    ok = Adc(8, 1, -127, 128)
+    assert lib.hdc_adc_argmax(None, fake, 4, 2, fake, 3, 2, Dims(0, 128, 1), Adc(0, 1, -1, 1), fake, None, None) == 1
+    assert lib.hdc_adc_argmax(None, fake, 4, 2, fake, 3, 2, Dims(0, 128, 1), Adc(8, 0, -1, 1), fake, None, None) == 1
+    assert lib.hdc_adc_argmax(None, fake, 4, 2, fake, 3, 2, Dims(0, 128, 1), Adc(8, 1, 5, 1), fake, None, None) == 1
+    assert lib.hdc_adc_argmax(None, fake, 4, 2, fake, 300, 2, Dims(0, 128, 1), ok, fake, None, None) == 2
+    assert lib.hdc_adc_argmax(None, fake, 4, 1, fake, 3, 2, Dims(0, 128, 1), ok, fake, None, None) == 1   # ldq
+    assert lib.hdc_adc_argmax(None, None, 0, 2, fake, 3, 2, Dims(0, 128, 1), ok, None, None, None) == 0   # n == 0

@@ -1,0 +1,47 @@
+"""ADC-chunked similarity on the GPU against the oracle, element by element."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hdc():
+    O.build()
+    from paper_2606_26547_amd import hdc as H
+    return H
+
+
+CASES = [
+    # n, nbits, K, perf, adc
+    (1, 128, 2, (0, 128, 1), (8, 1, -127, 128)),
+    (300, 2048, 26, (0, 2048, 1), (8, 1, -127, 128)),
+    (300, 2048, 26, (0, 2048, 1), (8, 2, -3, 128)),
+    (257, 10240, 26, (0, 10240, 1), (6, 9, -3, 128)),
+    (129, 1000, 10, (3, 990, 4), (4, 16, -127, 128)),
+    (64, 8192, 100, (128, 4096, 2), (3, 1, -2, 2)),
+    (77, 1100, 5, (70, 1100, 1), (16, 1, -1000, 1000)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=str)
+def test_adc_argmax_bit_exact(hdc, case):
+    n, nbits, K, (s, e, k), adc = case
+    print("[case] adc", case, flush=True)
+    g = np.random.default_rng(n + nbits + K)
+    W = (nbits + 63) // 64
+    Q = g.integers(0, 2 ** 63, size=(n, W), dtype=np.int64).view(np.uint64)
+    Cw = g.integers(0, 2 ** 63, size=(K, W), dtype=np.int64).view(np.uint64)
+    if K >= 3:
+        Cw[2] = Cw[0]                           # equal scores: lower index wins
+    ref = O.adc_scores(Q, Cw, s, e, k, *adc)
+    lref, mref = O.argmax(ref)
+    lab, mx, sc = hdc.adc_argmax(torch.as_tensor(Q.view(np.int64)).cuda(), torch.as_tensor(Cw.view(np.int64)).cuda(),
+                                 s, e, k, adc, True, True)
+    torch.cuda.synchronize()
+    assert np.array_equal(sc.cpu().numpy(), ref)
+    assert np.array_equal(lab.cpu().numpy(), lref)
+    assert np.array_equal(mx.cpu().numpy(), mref)

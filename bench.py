@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1 << 18)
     ap.add_argument("--latency-calls", type=int, default=200)
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=98304)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -266,7 +266,20 @@ def main():
                                "sample": "first %d queries of the batch, plain config (exact int encode + "
                                          "bit-by-bit Hamming + argmin), %.1fs" % (n_cpu, dt),
                                "labels_agree_with_gpu": agree}
-        log("cpu oracle: %.1f q/s on %d threads (agree %.4f)" % (n_cpu / dt, O.threads(), agree))
+        # the tuned configuration on a smaller sample, and one thread
+        if "tuned" in out:
+            tc = out["tuned"]["config"]
+            n_t = max(1, n_cpu // 3)
+            t = time.perf_counter()
+            O.classify(Xq[:n_t], ds.P, Cref, tc["dtype"], tc["start"], tc["d_trunc"], tc["stride"])
+            out["cpu_baseline"]["tuned_value"] = n_t / (time.perf_counter() - t)
+        n_1 = 1024
+        t = time.perf_counter()
+        O.classify(Xq[:n_1], ds.P, Cref, threads=1)
+        out["cpu_baseline"]["single_thread_value"] = n_1 / (time.perf_counter() - t)
+        log("cpu oracle: %.1f q/s on %d threads (agree %.4f), tuned %.1f q/s, one thread %.1f q/s" %
+            (n_cpu / dt, O.threads(), agree, out["cpu_baseline"].get("tuned_value", 0.0),
+             out["cpu_baseline"]["single_thread_value"]))
 
     print(json.dumps(out), flush=True)
 

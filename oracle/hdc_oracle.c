@@ -500,3 +500,43 @@ void or_argmax(const int32_t *scores, int64_t n, int32_t K, int32_t *label, int3
             max_score[i] = scores[i * K + best];
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Cosine similarity against integer class accumulators (see the header).
+ * ---------------------------------------------------------------------- */
+void or_cosine_scores(const uint64_t *Q, int64_t n, int64_t ldq,
+                      const int32_t *acc, int32_t K, int64_t lda,
+                      int32_t start, int32_t end, int32_t stride,
+                      double *scores, int threads)
+{
+    double *rinv = malloc((size_t)K * sizeof(double));
+    assert(rinv);
+    for (int32_t k = 0; k < K; k++) {
+        int64_t nsq = 0;
+        for (int64_t d = start; d < end; d += stride)
+            nsq += (int64_t)acc[k * lda + d] * acc[k * lda + d];
+        rinv[k] = nsq > 0 ? 1.0 / sqrt((double)nsq) : 0.0;
+    }
+#pragma omp parallel for num_threads(or_threads(threads)) schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t k = 0; k < K; k++) {
+            int64_t dot = 0;
+            for (int64_t d = start; d < end; d += stride)
+                dot += (int64_t)(get_bit(Q + i * ldq, d) ? -1 : 1) * acc[k * lda + d];
+            scores[i * K + k] = (double)dot * rinv[k];
+        }
+    free(rinv);
+}
+
+void or_argmax_f64(const double *scores, int64_t n, int32_t K, int32_t *label, double *max_score)
+{
+    for (int64_t i = 0; i < n; i++) {
+        int32_t best = 0;
+        for (int32_t k = 1; k < K; k++)
+            if (scores[i * K + k] > scores[i * K + best])
+                best = k;
+        label[i] = best;
+        if (max_score)
+            max_score[i] = scores[i * K + best];
+    }
+}

@@ -168,6 +168,23 @@ void or_adc_scores(const uint64_t *Q, int64_t n, int64_t ldq,
                    int32_t *scores, int threads);
 void or_argmax(const int32_t *scores, int64_t n, int32_t K, int32_t *label, int32_t *max_score);
 
+/* Cosine similarity against non-binarised class hypervectors (Sec. 3
+ * "Algorithmic Choice": cosine similarity is the costly alternative to the
+ * Hamming distance; the apps' baselines use it).  Reading: the query is the
+ * binarised (bipolar) encoding, the class vectors are the integer
+ * accumulators acc[K][lda] (bipolar class sums, possibly retrained); over
+ * the dimensions S,
+ *   dot[k]   = sum over d in S of b_q(d) * acc[k][d]            (exact)
+ *   rinv[k]  = 1 / sqrt(sum over d in S of acc[k][d]^2), 0 if that is 0
+ *   score[k] = (double)dot[k] * rinv[k]
+ * (the query's norm sqrt|S| is the same for every class and is left out);
+ * label = first class with the largest score. */
+void or_cosine_scores(const uint64_t *Q, int64_t n, int64_t ldq,
+                      const int32_t *acc, int32_t K, int64_t lda,
+                      int32_t start, int32_t end, int32_t stride,
+                      double *scores, int threads);
+void or_argmax_f64(const double *scores, int64_t n, int32_t K, int32_t *label, double *max_score);
+
 int or_threads(int threads);
 
 #ifdef __cplusplus

@@ -56,6 +56,8 @@ def lib():
         L.or_adc_quantize.argtypes = [i32, i32, i32, i32, i32]; L.or_adc_quantize.restype = i32
         L.or_adc_scores.argtypes = [p, i64, i64, p, i32, i64, i32, i32, i32, i32, i32, i32, i32, p, C.c_int]
         L.or_argmax.argtypes = [p, i64, i32, p, p]
+        L.or_cosine_scores.argtypes = [p, i64, i64, p, i32, i64, i32, i32, i32, p, C.c_int]
+        L.or_argmax_f64.argtypes = [p, i64, i32, p, p]
         L.or_encode.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, i64, C.c_int]
         L.or_project.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, p, C.c_int]
         L.or_bundle.argtypes = [p, i64, i32, i64, p, i32, p, i64, p]
@@ -268,4 +270,22 @@ def argmax(scores):
     lab = np.zeros(scores.shape[0], dtype=np.int32)
     mx = np.zeros(scores.shape[0], dtype=np.int32)
     lib().or_argmax(_ptr(scores), scores.shape[0], scores.shape[1], _ptr(lab), _ptr(mx))
+    return lab, mx
+
+
+def cosine_scores(Q, acc, start, end, stride=1, threads=0):
+    """Cosine scores [n][K] (float64) of bipolar queries against integer class accumulators."""
+    Q = _c(Q, np.uint64)
+    acc = _c(acc, np.int32)
+    sc = np.zeros((Q.shape[0], acc.shape[0]), dtype=np.float64)
+    lib().or_cosine_scores(_ptr(Q), Q.shape[0], Q.shape[1], _ptr(acc), acc.shape[0], acc.shape[1], start, end,
+                           stride, _ptr(sc), threads)
+    return sc
+
+
+def argmax_f64(scores):
+    scores = _c(scores, np.float64)
+    lab = np.zeros(scores.shape[0], dtype=np.int32)
+    mx = np.zeros(scores.shape[0], dtype=np.float64)
+    lib().or_argmax_f64(_ptr(scores), scores.shape[0], scores.shape[1], _ptr(lab), _ptr(mx))
     return lab, mx

@@ -185,8 +185,8 @@ hdc_status hdc_hamming_argmin(void *stream,
  * batches against it.  Outputs are identical to hdc_hamming_argmin with the
  * same arguments.  `ws` must stay untouched between the calls; K and perf
  * must be the same in both.
- *   Q        16-byte aligned with an even row pitch ldq (the prepared
- *            search streams query words 16 bytes at a time)
+ *   Q        16-byte aligned with an even row pitch ldq <= 2^20 (the
+ *            prepared search streams query words 16 bytes at a time)
  *   ws       >= hdc_hamming_workspace_bytes(perf, K) bytes, 16-byte aligned
  * Supports K <= 128, perf.end <= 65536.
  * ------------------------------------------------------------------- */
@@ -199,6 +199,44 @@ hdc_status hdc_hamming_argmin_prepared(void *stream,
                                        int32_t K, hdc_dims perf,
                                        int32_t *argmin, int32_t *min_dist, int32_t *dists,
                                        const void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
+ * hdc_cosine_prepare / hdc_cosine_argmax_prepared -- cosine similarity of
+ * binary query hypervectors against NON-binarised class hypervectors, the
+ * alternative to Hamming distance the paper weighs in Sec. 3 "Algorithmic
+ * Choice" (integer class accumulators kept as they are, similarity by
+ * normalised dot product), under reduction perforation (Sec. 4.2).  With b
+ * the bipolar form of the query (+1 for bit 0, -1 for bit 1) and a_k the
+ * class accumulator (e.g. hdc_class_acc / hdc_retrain_epoch output):
+ *     score[i][k] = (double)(sum over d in S of b(d) * a_k(d))
+ *                   * (1 / sqrt(sum over d in S of a_k(d)^2))
+ * with the dot product exact (integer), the reciprocal square root and the
+ * product each correctly rounded in double, and 0 as the factor of an
+ * all-zero class over S.  The query's own norm is the same for every class
+ * and does not change the ranking; it is left out.  label[i] is the lowest
+ * k with the largest score.  _prepare builds the matrix-core operand, the
+ * per-class sums and norms in the workspace once; _argmax_prepared
+ * searches any number of query batches against it.  `ws` must stay
+ * untouched between the calls; K and perf must be the same in both.
+ *   acc      [K][lda] int32, lda >= perf.end; every entry over S must lie
+ *            in [-32639, 32639]: otherwise _prepare marks the workspace
+ *            and every label the search writes is -1 and every score NaN
+ *   Q        [n][ldq] uint64 (>= perf.end valid bits), 16-byte aligned,
+ *            even ldq <= 2^20
+ *   label    [n] int32 output; max_score [n], scores [n][K] double, may be
+ *            NULL
+ *   ws       >= hdc_cosine_workspace_bytes(perf, K) bytes, 16-byte aligned
+ * Supports K <= 128, perf.end <= 65536.
+ * ------------------------------------------------------------------- */
+size_t hdc_cosine_workspace_bytes(hdc_dims perf, int32_t K);
+hdc_status hdc_cosine_prepare(void *stream,
+                              const int32_t *acc, int32_t K, int64_t lda,
+                              hdc_dims perf, void *ws, size_t ws_bytes);
+hdc_status hdc_cosine_argmax_prepared(void *stream,
+                                      const uint64_t *Q, int64_t n, int64_t ldq,
+                                      int32_t K, hdc_dims perf,
+                                      int32_t *label, double *max_score, double *scores,
+                                      const void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
  * hdc_adc_argmax -- dot-product similarity as an in-memory accelerator

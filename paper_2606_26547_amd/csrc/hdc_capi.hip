@@ -297,8 +297,52 @@ hdc_status hdc_hamming_argmin_prepared(void *stream, const uint64_t *Q, int64_t 
         return HDC_OK;
     if (!Q || ldq < (perf.end + 63) / 64 || ldq % 2 || !aligned(Q, 16) || !argmin)
         return HDC_ERR_INVALID;
+    if (ldq > kMaxPreparedLdq)
+        return HDC_ERR_UNSUPPORTED;
     return from_hip(launch_ham_prepared(Q, n, ldq, K, perf.start, perf.end, (const uint8_t *)ws, argmin,
                                         min_dist, dists, (hipStream_t)stream));
+}
+
+size_t hdc_cosine_workspace_bytes(hdc_dims perf, int32_t K)
+{
+    if (check_perf(perf, K) != HDC_OK)
+        return 0;
+    return cos_workspace_bytes(perf.start, perf.end, K);
+}
+
+hdc_status hdc_cosine_prepare(void *stream, const int32_t *acc, int32_t K, int64_t lda, hdc_dims perf, void *ws,
+                              size_t ws_bytes)
+{
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (!acc || lda < perf.end)
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_cosine_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    return from_hip(launch_cos_prepare(acc, K, lda, perf.start, perf.end, perf.stride, (uint8_t *)ws,
+                                       (hipStream_t)stream));
+}
+
+hdc_status hdc_cosine_argmax_prepared(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, int32_t K,
+                                      hdc_dims perf, int32_t *label, double *max_score, double *scores,
+                                      const void *ws, size_t ws_bytes)
+{
+    if (n < 0)
+        return HDC_ERR_INVALID;
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (!ws || ws_bytes < hdc_cosine_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    if (!Q || ldq < (perf.end + 63) / 64 || ldq % 2 || !aligned(Q, 16) || !label)
+        return HDC_ERR_INVALID;
+    if (ldq > kMaxPreparedLdq)
+        return HDC_ERR_UNSUPPORTED;
+    return from_hip(launch_cos_prepared(Q, n, ldq, K, perf.start, perf.end, (const uint8_t *)ws, label, max_score,
+                                        scores, (hipStream_t)stream));
 }
 
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)

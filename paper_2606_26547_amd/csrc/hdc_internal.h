@@ -50,6 +50,9 @@ constexpr int kMaxF = 1024;
 constexpr int kMaxFFloat = 256;
 constexpr int kMaxK = 128;
 constexpr int kMaxConfigs = 4096;
+// The prepared searches address a workgroup's query rows with 32-bit byte
+// offsets from its first row (at most 256 rows).
+constexpr int64_t kMaxPreparedLdq = 1 << 20;
 
 inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
 inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
@@ -69,6 +72,12 @@ hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, 
                               hipStream_t st);
 hipError_t launch_ham_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K, int start, int end,
                                const uint8_t *ws, int32_t *argmin, int32_t *min_dist, int32_t *dists,
+                               hipStream_t st);
+size_t cos_workspace_bytes(int start, int end, int K);
+hipError_t launch_cos_prepare(const int32_t *acc, int K, int64_t lda, int start, int end, int stride, uint8_t *ws,
+                              hipStream_t st);
+hipError_t launch_cos_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K, int start, int end,
+                               const uint8_t *ws, int32_t *label, double *max_score, double *scores,
                                hipStream_t st);
 hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K,
                           int64_t ldc, int start, int end, int stride, int32_t *argmin,

@@ -36,7 +36,8 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
-           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax"]
+           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax",
+           "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared"]
 
 
 class Dims(C.Structure):
@@ -92,6 +93,10 @@ _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int
 _lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
 _lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
 _lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
+_lib.hdc_cosine_workspace_bytes.restype = _sz
+_lib.hdc_cosine_workspace_bytes.argtypes = [Dims, _i32]
+_lib.hdc_cosine_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
+_lib.hdc_cosine_argmax_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, _p, _p, _p, _p, _sz]
 for _name in EXPORTS:
     assert hasattr(_lib, _name)
 
@@ -213,6 +218,37 @@ class HammingPrepared:
                                                 _ptr(mn), _ptr(dists), _ptr(self.ws), self.ws.numel()),
                "hdc_hamming_argmin_prepared")
         return lab, mn, dists
+
+
+def cosine_workspace_bytes(start: int, end: int, stride: int, K: int) -> int:
+    return int(_lib.hdc_cosine_workspace_bytes(Dims(start, end, stride), K))
+
+
+class CosinePrepared:
+    """Integer class accumulators of one (classes, perforation) turned into
+    the matrix-core operand, sums and norms once; each call ranks a batch of
+    query hypervectors by cosine similarity (hdc_cosine_argmax_prepared).
+    Labels are -1 if an accumulator entry over the set lies outside
+    [-32639, 32639]."""
+
+    def __init__(self, acc: torch.Tensor, start: int, end: int, stride: int = 1):
+        self.K, self.perf = acc.shape[0], Dims(start, end, stride)
+        need = cosine_workspace_bytes(start, end, stride, self.K)
+        self.ws = torch.empty(max(need, 16), dtype=torch.uint8, device=acc.device)
+        _check(_lib.hdc_cosine_prepare(_stream(), _ptr(acc), self.K, acc.shape[1], self.perf, _ptr(self.ws),
+                                       self.ws.numel()), "hdc_cosine_prepare")
+
+    def __call__(self, Q: torch.Tensor, with_max=False, with_scores=False, out: torch.Tensor | None = None):
+        n = Q.shape[0]
+        if Q.shape[1] % 2:                      # the search wants an even row pitch
+            Q = torch.nn.functional.pad(Q, (0, 1))
+        lab = out if out is not None else torch.empty(n, dtype=torch.int32, device=Q.device)
+        mx = torch.empty(n, dtype=torch.float64, device=Q.device) if with_max else None
+        sc = torch.empty((n, self.K), dtype=torch.float64, device=Q.device) if with_scores else None
+        _check(_lib.hdc_cosine_argmax_prepared(_stream(), _ptr(Q), n, Q.shape[1], self.K, self.perf, _ptr(lab),
+                                               _ptr(mx), _ptr(sc), _ptr(self.ws), self.ws.numel()),
+               "hdc_cosine_argmax_prepared")
+        return lab, mx, sc
 
 
 def classify_workspace_bytes(n_dims: int, K: int) -> int:

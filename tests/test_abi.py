@@ -103,3 +103,33 @@ def test_adc_validation_without_device(lib):
     assert lib.hdc_adc_argmax(None, fake, 4, 2, fake, 300, 2, Dims(0, 128, 1), ok, fake, None, None) == 2
     assert lib.hdc_adc_argmax(None, fake, 4, 1, fake, 3, 2, Dims(0, 128, 1), ok, fake, None, None) == 1   # ldq
     assert lib.hdc_adc_argmax(None, None, 0, 2, fake, 3, 2, Dims(0, 128, 1), ok, None, None, None) == 0   # n == 0
+
+
+def test_cosine_validation_without_device(lib):
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_cosine_workspace_bytes.restype = C.c_size_t
+    lib.hdc_cosine_workspace_bytes.argtypes = [Dims, i32]
+    lib.hdc_cosine_prepare.argtypes = [p, p, i32, i64, Dims, p, C.c_size_t]
+    lib.hdc_cosine_argmax_prepared.argtypes = [p, p, i64, i64, i32, Dims, p, p, p, p, C.c_size_t]
+    tail = 128 * 8 * 2 + 128 * 4 + 16           # class sums, reciprocal norms, maxima, range flag
+    assert lib.hdc_cosine_workspace_bytes(Dims(0, 10240, 1), 26) == 20 * 8 * 4 * 1024 + tail
+    assert lib.hdc_cosine_workspace_bytes(Dims(64, 4096, 2), 100) == 8 * 8 * 4 * 4 * 1024 + tail
+    assert lib.hdc_cosine_workspace_bytes(Dims(200, 1000, 1), 5) == 2 * 8 * 4 * 1024 + tail
+    assert lib.hdc_cosine_workspace_bytes(Dims(0, 10240, 1), 129) == 0
+    assert lib.hdc_cosine_workspace_bytes(Dims(0, 70000, 1), 26) == 0
+    fake = C.c_void_p(1 << 20)
+    need = lib.hdc_cosine_workspace_bytes(Dims(0, 128, 1), 3)
+    assert lib.hdc_cosine_prepare(None, fake, 3, 100, Dims(0, 128, 1), fake, need) == 1        # lda < end
+    assert lib.hdc_cosine_prepare(None, None, 3, 128, Dims(0, 128, 1), fake, need) == 1        # no acc
+    assert lib.hdc_cosine_prepare(None, fake, 3, 128, Dims(0, 128, 1), fake, need - 1) == 3    # small ws
+    assert lib.hdc_cosine_prepare(None, fake, 200, 128, Dims(0, 128, 1), fake, 1 << 30) == 2   # K > 128
+    assert lib.hdc_cosine_argmax_prepared(None, fake, 4, 3, 3, Dims(0, 128, 1), fake, None, None, fake,
+                                          need) == 1                                            # odd ldq
+    assert lib.hdc_cosine_argmax_prepared(None, C.c_void_p((1 << 20) + 8), 4, 2, 3, Dims(0, 128, 1), fake, None,
+                                          None, fake, need) == 1                                # Q misaligned
+    assert lib.hdc_cosine_argmax_prepared(None, fake, 4, 2, 3, Dims(0, 128, 1), None, None, None, fake,
+                                          need) == 1                                            # no label
+    assert lib.hdc_cosine_argmax_prepared(None, None, 0, 2, 3, Dims(0, 128, 1), None, None, None, fake,
+                                          need) == 0                                            # n == 0
+    assert lib.hdc_cosine_argmax_prepared(None, fake, 4, (1 << 20) + 2, 3, Dims(0, 128, 1), fake, None, None, fake,
+                                          need) == 2                                            # ldq too large

@@ -244,6 +244,8 @@ def main():
                                   for k, v in ham.items()})
         # -------------------------------------------------------- ADC-chunked similarity
         out["adc"] = adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D)
+        # -------------------------------------------------------- cosine similarity
+        out["cosine"] = cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
         # -------------------------------------------------------- retraining epochs
         out["retrain"] = retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
         # -------------------------------------------------------- precision ladder
@@ -303,6 +305,37 @@ def adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D):
     res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9}
     del Q
     log("adc: %s" % {k: (v["accuracy"] if isinstance(v, dict) and "accuracy" in v else v) for k, v in res.items()})
+    return res
+
+
+def cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D):
+    """Cosine similarity against the integer class accumulators (no
+    binarisation) beside Hamming against their signs: test accuracy of the
+    speech model after bundling and after retraining, under truncation and
+    perforation, and the search throughput on 2^20 query hypervectors."""
+    from paper_2606_26547_amd import train
+    H = hdc.encode(Xtr, F, Pd, D)
+    Hte = hdc.encode(Xte, F, Pd, D)
+    yte = torch.as_tensor(ds.y_test).to(dev)
+    res = {}
+    for epochs in (0, 3):
+        Cw, acc, _ = train.fit(H, D, ytr, K, epochs)
+        row = {"max_abs_acc": int(acc.abs().max().item())}
+        for name, (s, e, k) in {"full": (0, D, 1), "D'=4096": (0, 4096, 1), "stride 4": (0, D, 4)}.items():
+            ham = hdc.HammingPrepared(Cw, s, e, k)(Hte)[0]
+            cos = hdc.CosinePrepared(acc, s, e, k)(Hte)[0]
+            row[name] = {"hamming": float((ham == yte).float().mean().item()),
+                         "cosine": float((cos == yte).float().mean().item())}
+        res["epochs=%d" % epochs] = row
+    nq = 1 << 20
+    Q = torch.randint(-(1 << 62), 1 << 62, (nq, D // 64), dtype=torch.int64, device=dev)
+    lab = torch.empty(nq, dtype=torch.int32, device=dev)
+    cp = hdc.CosinePrepared(acc, 0, D, 1)
+    _, ms, _ = event_loop(lambda: cp(Q, out=lab), 10, 2)
+    res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9, "queries_per_s": nq / (ms / 1e3),
+                          "int8_tops": 2 * nq * D * 32 * 2 / (ms / 1e3) / 1e12}
+    del Q
+    log("cosine: %s, 2^20 search %.3f ms" % ({k: v["full"] for k, v in res.items() if k.startswith("epochs")}, ms))
     return res
 
 

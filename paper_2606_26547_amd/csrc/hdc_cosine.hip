@@ -32,15 +32,15 @@
 
 namespace hdc {
 
-template <int KT> struct CosShape {
-    static constexpr int QT = KT == 4 ? 1 : 2;
+template <int KT, int QT_ = (KT == 4 ? 1 : 2), int NST_ = (KT == 1 ? 3 : 2)> struct CosShape {
+    static constexpr int QT = QT_;
     static constexpr int W = 4;                        // words per window (divides kCosWin)
     static constexpr int U = W / 2;                    // 16-byte units per query row
     static constexpr int RPL = 64 / U;                 // query rows per 1 KiB load
     static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
     static constexpr int QB = ROWS * W * 8;            // query bytes per stage
     static constexpr int TB = W * 4 * KT * 1024;       // operand bytes per window
-    static constexpr int NST = 2;
+    static constexpr int NST = NST_;
     static constexpr int NQL = QB / 1024 / kWaves;
     static constexpr int NTL = TB / 1024 / kWaves;
     static constexpr int SB = QB + TB;
@@ -162,15 +162,16 @@ __device__ __forceinline__ v4i spread_bits(uint32_t d, uint32_t sh)
     return b;
 }
 
-template <int KT>
+template <int KT, int QT_, int NST_>
 __global__ __launch_bounds__(256) void k_cosine_mfma(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq, int K,
                                                      int w_lo, int w_hi, int nwin, const int8_t *__restrict__ tab,
                                                      const int64_t *__restrict__ T, const double *__restrict__ rinv,
                                                      const int32_t *__restrict__ flag, int32_t *__restrict__ label, double *__restrict__ max_score,
                                                      double *__restrict__ scores)
 {
-    typedef CosShape<KT> S;
+    typedef CosShape<KT, QT_, NST_> S;
     constexpr int QT = S::QT, W = S::W, NST = S::NST;
+    constexpr int G = S::NQL + S::NTL;                 // loads per window and wave
     __shared__ __align__(16) uint8_t smem[NST * S::SB];
     lds_u8 *L = (lds_u8 *)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
@@ -218,11 +219,16 @@ __global__ __launch_bounds__(256) void k_cosine_mfma(const uint64_t *__restrict_
             ahi[kt][qt] = v16i{};
         }
 
-    issue(0, 0);
-    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    // ring of NST stages: window v lives in stage v % NST; loads run NST-1
+    // windows ahead, and vector memory operations complete in order, so
+    // vmcnt(G*(NST-2)) leaves only the newer windows in flight
+#pragma unroll
+    for (int v = 0; v < NST - 1; ++v)
+        issue(v, v);
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(G * (NST - 2)) : "memory");
     int st = 0;
     for (int v = 0; v < nwin; ++v) {
-        issue(v + 1, st ^ 1);
+        issue(v + NST - 1, st == 0 ? NST - 1 : st - 1);
         const lds_u8 *sq = L + st * S::SB;
         const lds_u8 *stb = sq + S::QB;
 #pragma unroll
@@ -252,8 +258,8 @@ __global__ __launch_bounds__(256) void k_cosine_mfma(const uint64_t *__restrict_
                 }
             }
         }
-        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        st ^= 1;
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(G * (NST - 2)) : "memory");
+        st = st == NST - 1 ? 0 : st + 1;
     }
     __builtin_amdgcn_s_waitcnt(0);
 
@@ -313,8 +319,10 @@ hipError_t launch_cos_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K,
     const int32_t *flag = (const int32_t *)(ws + L.off_flag);
 #define HDC_COS_CASE(KT_)                                                                                      \
     if (L.KT == KT_) {                                                                                         \
-        constexpr int R = CosShape<KT_>::ROWS, NW = kCosWin / CosShape<KT_>::W;                                \
-        hipLaunchKernelGGL(k_cosine_mfma<KT_>, dim3((unsigned)((n + R - 1) / R)), dim3(256), 0, st, Q, n, ldq,  \
+        typedef CosShape<KT_> S;                                                                               \
+        constexpr int R = S::ROWS, NW = kCosWin / S::W;                                                        \
+        hipLaunchKernelGGL((k_cosine_mfma<KT_, S::QT, S::NST>), dim3((unsigned)((n + R - 1) / R)), dim3(256), 0, \
+                           st, Q, n, ldq,                                                                      \
                            K, L.w_lo, L.w_hi, L.nwin * NW, tab, T, rinv, flag, label, max_score, scores);            \
         return hipGetLastError();                                                                              \
     }

@@ -540,3 +540,102 @@ void or_argmax_f64(const double *scores, int64_t n, int32_t K, int32_t *label, d
             max_score[i] = scores[i * K + best];
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Encoding with the reduction over features perforated (header: the sign
+ * of the rescaled product).
+ * ---------------------------------------------------------------------- */
+static int project_sub(const void *X, int x_type, int64_t ldx, int64_t i, int32_t fstart, int32_t fend,
+                       int32_t fstride, const int8_t *Prow, int compute, const int32_t *tab)
+{
+    if (tab) {
+        const uint8_t *x = (const uint8_t *)X + i * ldx;
+        int32_t y = 0;
+        for (int32_t f = fstart; f < fend; f += fstride)
+            y += tab[x[f]] * (int32_t)Prow[f];
+        return (y > 0) - (y < 0);
+    }
+    xacc a;
+    memset(&a, 0, sizeof a);
+    for (int32_t f = fstart; f < fend; f += fstride)
+        xacc_add(&a, or_feature(X, x_type, ldx, i, f, compute) * (double)Prow[f]);
+    return xacc_sign(&a);
+}
+
+void or_encode_fperf(const void *X, int x_type, int64_t n, int32_t F, int64_t ldx,
+                     const int8_t *P, int32_t D, int64_t ldp, int compute,
+                     int32_t fstart, int32_t fend, int32_t fstride,
+                     int32_t start, int32_t end, int32_t stride,
+                     uint64_t *H, int64_t ldh, int threads)
+{
+    assert(F <= (1 << 20) && end <= D && fend <= F);
+    int32_t nf = or_dims_count(fstart, fend, fstride);
+    assert(nf > 0);
+    double scale = (double)F / nf;          /* compensation for skipped terms */
+    int scale_sign = (scale > 0) - (scale < 0);
+    int32_t ns = or_dims_count(start, end, stride);
+    int64_t W = (ns + 63) / 64;
+    int32_t tab[256];
+    int use_tab = int_feature_table(x_type, compute, tab);
+#pragma omp parallel for num_threads(or_threads(threads)) schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t *h = H + i * ldh;
+        memset(h, 0, (size_t)W * sizeof(uint64_t));
+        for (int32_t j = 0; j < ns; j++) {
+            int64_t d = start + (int64_t)j * stride;
+            int s = scale_sign * project_sub(X, x_type, ldx, i, fstart, fend, fstride, P + d * ldp, compute,
+                                             use_tab ? tab : NULL);
+            if (s < 0)
+                h[j / 64] |= 1ULL << (j % 64);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Level-ID encoding (header: quantiser and bound-pair bundle).
+ * ---------------------------------------------------------------------- */
+void or_level_quantize(const float *X, int64_t n, int32_t F, int64_t ldx,
+                       const float *lo, const float *hi, int32_t L,
+                       uint16_t *lev, int64_t ldl)
+{
+    assert(L >= 1 && L <= 65536);
+    for (int64_t i = 0; i < n; i++)
+        for (int32_t f = 0; f < F; f++) {
+            volatile float t = X[i * ldx + f] - lo[f];
+            volatile float w = hi[f] - lo[f];
+            volatile float u = t * (float)L;
+            volatile float v = u / w;
+            int32_t level;
+            if (!(w > 0.0f) || !(v > 0.0f))
+                level = 0;
+            else if (v >= (float)(L - 1))
+                level = L - 1;
+            else
+                level = (int32_t)floorf(v);
+            lev[i * ldl + f] = (uint16_t)level;
+        }
+}
+
+void or_level_id_encode(const uint16_t *lev, int64_t n, int32_t F, int64_t ldl,
+                        const uint64_t *ID, int64_t ldid, const uint64_t *LV, int32_t L, int64_t ldlv,
+                        int32_t D, uint64_t *H, int64_t ldh, int threads)
+{
+    int64_t W = (D + 63) / 64;
+#pragma omp parallel for num_threads(or_threads(threads)) schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t *h = H + i * ldh;
+        memset(h, 0, (size_t)W * sizeof(uint64_t));
+        for (int32_t d = 0; d < D; d++) {
+            int32_t s = 0;
+            for (int32_t f = 0; f < F; f++) {
+                int32_t l = lev[i * ldl + f];
+                assert(l < L);
+                int32_t bid = get_bit(ID + (int64_t)f * ldid, d) ? -1 : 1;
+                int32_t blv = get_bit(LV + (int64_t)l * ldlv, d) ? -1 : 1;
+                s += bid * blv;
+            }
+            if (s < 0)
+                h[d / 64] |= 1ULL << (d % 64);
+        }
+    }
+}

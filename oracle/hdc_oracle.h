@@ -185,6 +185,42 @@ void or_cosine_scores(const uint64_t *Q, int64_t n, int64_t ldq,
                       double *scores, int threads);
 void or_argmax_f64(const double *scores, int64_t n, int32_t K, int32_t *label, double *max_score);
 
+/* Random-projection encoding with the encoding's own reduction (over the
+ * features) perforated (Sec. 4.2 "Reduction Perforation": a perforated
+ * matrix-vector product is rescaled for the skipped iterations).  With
+ * S_F = { fstart + m*fstride : < fend } and nf = |S_F|,
+ *   y[i][j] = (F / nf) * sum over f in S_F of x'_{if} * P[S_j][f],
+ * binarised as in or_encode (y < 0 -> bit 1, y == 0 -> +1).  The sum is
+ * exact, so the sign of y is exactly the sign of the rescaled value. */
+void or_encode_fperf(const void *X, int x_type, int64_t n, int32_t F, int64_t ldx,
+                     const int8_t *P, int32_t D, int64_t ldp, int compute,
+                     int32_t fstart, int32_t fend, int32_t fstride,
+                     int32_t start, int32_t end, int32_t stride,
+                     uint64_t *H, int64_t ldh, int threads);
+
+/* Level-ID encoding (Sec. 3 "Algorithmic Choice": ID-based encoding as the
+ * alternative to random projection; Sec. 5.3: the Level knob, the number of
+ * discrete levels continuous features are quantised to).  Reading: feature
+ * f of row i is quantised to a level, in binary32 arithmetic with every
+ * operation rounded to nearest even and nothing fused,
+ *   t = x - lo[f];  w = hi[f] - lo[f];  u = t * L;  v = u / w;
+ *   level = 0 if !(w > 0) or !(v > 0) (NaN included), L - 1 if v >= L - 1,
+ *           else floor(v);
+ * and the row's hypervector is the bundle of the bound pairs
+ *   s[i][d] = sum over f < F of b(ID_f, d) * b(LV_level(i,f), d),
+ *   bit d of H row i = (s < 0)   (s == 0 gives +1),
+ * with b(row, d) = +1 for bit 0, -1 for bit 1.  ID [F][ldid] and
+ * LV [L][ldlv] are packed hypervectors of D bits (the random identity and
+ * level hypervectors are inputs); lev is [n][ldl] uint16.  Multiplying
+ * by L before dividing keeps grid points exact: x = lo + k*(hi-lo)/L with
+ * an exact product lands on level k. */
+void or_level_quantize(const float *X, int64_t n, int32_t F, int64_t ldx,
+                       const float *lo, const float *hi, int32_t L,
+                       uint16_t *lev, int64_t ldl);
+void or_level_id_encode(const uint16_t *lev, int64_t n, int32_t F, int64_t ldl,
+                        const uint64_t *ID, int64_t ldid, const uint64_t *LV, int32_t L, int64_t ldlv,
+                        int32_t D, uint64_t *H, int64_t ldh, int threads);
+
 int or_threads(int threads);
 
 #ifdef __cplusplus

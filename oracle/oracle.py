@@ -58,6 +58,10 @@ def lib():
         L.or_argmax.argtypes = [p, i64, i32, p, p]
         L.or_cosine_scores.argtypes = [p, i64, i64, p, i32, i64, i32, i32, i32, p, C.c_int]
         L.or_argmax_f64.argtypes = [p, i64, i32, p, p]
+        L.or_encode_fperf.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, i32, i32,
+                                      i32, p, i64, C.c_int]
+        L.or_level_quantize.argtypes = [p, i64, i32, i64, p, p, i32, p, i64]
+        L.or_level_id_encode.argtypes = [p, i64, i32, i64, p, i64, p, i32, i64, i32, p, i64, C.c_int]
         L.or_encode.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, i64, C.c_int]
         L.or_project.argtypes = [p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, i32, i32, i32, p, p, C.c_int]
         L.or_bundle.argtypes = [p, i64, i32, i64, p, i32, p, i64, p]
@@ -289,3 +293,38 @@ def argmax_f64(scores):
     mx = np.zeros(scores.shape[0], dtype=np.float64)
     lib().or_argmax_f64(_ptr(scores), scores.shape[0], scores.shape[1], _ptr(lab), _ptr(mx))
     return lab, mx
+
+
+def encode_fperf(X, P, fstart, fend, fstride, compute="int8", start=0, end=None, stride=1, threads=0):
+    """Packed sign bits of the rescaled feature-perforated projection."""
+    X = np.ascontiguousarray(X)
+    P = _c(P, np.int8)
+    end = P.shape[0] if end is None else end
+    ns = dims_count(start, end, stride)
+    H = np.zeros((X.shape[0], words(ns)), dtype=np.uint64)
+    lib().or_encode_fperf(_ptr(X), _xtype(X), X.shape[0], X.shape[1], X.shape[1], _ptr(P), P.shape[0],
+                          P.shape[1], DTYPE.get(compute, compute), fstart, fend, fstride, start, end, stride,
+                          _ptr(H), H.shape[1], threads)
+    return H
+
+
+def level_quantize(X, lo, hi, L):
+    """Levels [n][F] uint16 of float32 features under per-feature ranges."""
+    X = _c(X, np.float32)
+    lo = _c(lo, np.float32)
+    hi = _c(hi, np.float32)
+    lev = np.zeros(X.shape, dtype=np.uint16)
+    lib().or_level_quantize(_ptr(X), X.shape[0], X.shape[1], X.shape[1], _ptr(lo), _ptr(hi), L, _ptr(lev),
+                            lev.shape[1])
+    return lev
+
+
+def level_id_encode(lev, ID, LV, D, threads=0):
+    """Packed Level-ID hypervectors [n][ceil(D/64)] of level rows lev [n][F]."""
+    lev = _c(lev, np.uint16)
+    ID = _c(ID, np.uint64)
+    LV = _c(LV, np.uint64)
+    H = np.zeros((lev.shape[0], words(D)), dtype=np.uint64)
+    lib().or_level_id_encode(_ptr(lev), lev.shape[0], lev.shape[1], lev.shape[1], _ptr(ID), ID.shape[1],
+                             _ptr(LV), LV.shape[0], LV.shape[1], D, _ptr(H), H.shape[1], threads)
+    return H

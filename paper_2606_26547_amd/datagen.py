@@ -33,7 +33,7 @@ import dataclasses
 import numpy as np
 
 # Stream identifiers (second word of the SeedSequence entropy).
-_S_MIX, _S_TRAIN, _S_TEST, _S_PROJ, _S_LABELS, _S_EXTRA, _S_MASK = range(1, 8)
+_S_MIX, _S_TRAIN, _S_TEST, _S_PROJ, _S_LABELS, _S_EXTRA, _S_MASK, _S_ID, _S_LEVEL = range(1, 10)
 
 
 def rng(seed: int, stream: int, *sub: int) -> np.random.Generator:
@@ -45,6 +45,43 @@ def projection_matrix(D: int, F: int, seed: int) -> np.ndarray:
     """Seeded +-1 projection matrix stored as P[D][F] int8 (P = B^T)."""
     bits = rng(seed, _S_PROJ, D, F).integers(0, 2, size=(D, F), dtype=np.int8)
     return (1 - 2 * bits).astype(np.int8)
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    """Rows of 0/1 values [n][D] as packed hypervector rows [n][ceil(D/64)]
+    uint64 (bit j of word w = element 64w + j, pad bits 0)."""
+    n, D = bits.shape
+    W = max(1, (D + 63) // 64)
+    b = np.zeros((n, W * 64), dtype=np.uint8)
+    b[:, :D] = bits
+    return np.packbits(b, axis=1, bitorder="little").view("<u8").astype(np.uint64)
+
+
+def id_hypervectors(F: int, D: int, seed: int) -> np.ndarray:
+    """Seeded random identity hypervectors, one per feature, packed [F][W]."""
+    return pack_bits(rng(seed, _S_ID, F, D).integers(0, 2, size=(F, D), dtype=np.uint8))
+
+
+def level_hypervectors(L: int, D: int, seed: int) -> np.ndarray:
+    """Seeded level hypervectors packed [L][W]: level 0 is random; level l
+    is level 0 with the first floor(l * (D/2) / (L-1)) positions of one
+    random permutation of the D dimensions flipped, so neighbouring levels
+    are close and levels 0 and L-1 differ in D/2 positions."""
+    g = rng(seed, _S_LEVEL, L, D)
+    base = g.integers(0, 2, size=D, dtype=np.uint8)
+    perm = g.permutation(D)
+    bits = np.repeat(base[None, :], L, axis=0)
+    for l in range(1, L):
+        m = (l * (D // 2)) // (L - 1)
+        bits[l, perm[:m]] ^= 1
+    return pack_bits(bits)
+
+
+def feature_ranges(X_train: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Per-feature [min, max] over the train set (float32), the range the
+    level quantiser maps onto its levels."""
+    X = X_train.astype(np.float32)
+    return X.min(axis=0), X.max(axis=0)
 
 
 def balanced_labels(n: int, K: int, g: np.random.Generator) -> np.ndarray:
@@ -163,6 +200,12 @@ class SpeechLike:
         y = balanced_labels(n, self.c["K"], rng(self.seed, _S_LABELS, 1 + stream))
         Xf = self.mix.sample(y, rng(self.seed, _S_EXTRA, stream))
         return quantize_int8(Xf, self.scales), y
+
+    def float_split(self) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        """The train and test draws of ``dataset`` before quantisation
+        (fp32), for encoders that take continuous features."""
+        yte = balanced_labels(self.c["n_test"], self.c["K"], rng(self.seed, _S_LABELS, 1000))
+        return self.X_train_f, self.y_train, self.mix.sample(yte, rng(self.seed, _S_TEST)), yte
 
     def dataset(self) -> Dataset:
         c = self.c

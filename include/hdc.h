@@ -357,6 +357,61 @@ hdc_status hdc_eval_configs(void *stream,
 double hdc_device_clock_hz(void);
 
 /* ---------------------------------------------------------------------
+ * hdc_feature_perforate -- reduction perforation applied to the encoding's
+ * own reduction, the one over features (Sec. 4.2 "Reduction Perforation":
+ * a perforated matrix-vector product is rescaled for the iterations it
+ * skips).  Copies the columns S(fperf) = { fperf.start + j*fperf.stride <
+ * fperf.end } of a row-major matrix into a dense one, so that hdc_encode /
+ * hdc_classify on the result with F' = |S(fperf)| features compute the
+ * perforated product.  The rescale factor F/F' is positive and changes no
+ * sign, so the binarised encoding needs no rescale.  Apply it to the
+ * features X and, once per configuration, to the projection rows P (int8,
+ * n = D).
+ *   X   [n][ldx] of x_type (HDC_INT8, HDC_UINT8 or HDC_FP32), ldx >= F
+ *   Y   [n][ldy]: column j < F' holds X column fperf.start + j*fperf.stride,
+ *       columns F'..ldy-1 are 0; ldy >= F', ldy * element size a multiple
+ *       of 16 bytes, Y 16-byte aligned
+ * Requires 0 <= fperf.start < fperf.end <= F, fperf.stride >= 1.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_feature_perforate(void *stream,
+                                 const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                 hdc_dims fperf, void *Y, int64_t ldy);
+
+/* ---------------------------------------------------------------------
+ * hdc_level_quantize / hdc_level_id_encode -- Level-ID encoding, the
+ * ID-based alternative to random projection (Sec. 3 "Algorithmic Choice";
+ * Sec. 5.3: the Level knob, how many discrete levels continuous features
+ * are quantised to before they map to hypervectors).
+ * _quantize: for feature f of row i, in binary32 with every operation
+ * rounded to nearest even and nothing fused,
+ *     v = ((x - lo[f]) * L) / (hi[f] - lo[f])
+ *     lev[i][f] = 0 if hi[f] - lo[f] is not > 0 or v is not > 0 (NaN
+ *                 included), L - 1 if v >= L - 1, floor(v) otherwise.
+ *   X [n][ldx] float, lo / hi [F] float, lev [n][ldl] uint16 output,
+ *   ldx, ldl >= F; 1 <= L <= 65535.
+ * _encode: with b(row, d) = +1 for bit 0 and -1 for bit 1,
+ *     s = sum over f < F of b(ID_f, d) * b(LV_lev[i][f], d)
+ *     bit d of H row i = (s < 0)   (s == 0 gives +1)
+ * i.e. the bundle of the bound (ID, level) pairs of the row.  The identity
+ * hypervectors ID [F][ldid] and level hypervectors LV [L][ldlv] are inputs
+ * (packed, D bits, pad bits 0); lev entries must be < L (a larger entry
+ * reads as L - 1).  H [n][ldh] uint64 output, pad bits written as 0.
+ *   ldid, ldlv, ldh >= ceil(D / 64); for _encode, lev 16-byte aligned
+ *   and ldl >= F rounded up to a multiple of 8 (levels are read 8 at a
+ *   time; the pad entries are read and ignored).
+ * Supports F <= 1024, L <= 1024.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_level_quantize(void *stream,
+                              const float *X, int64_t n, int32_t F, int64_t ldx,
+                              const float *lo, const float *hi, int32_t L,
+                              uint16_t *lev, int64_t ldl);
+hdc_status hdc_level_id_encode(void *stream,
+                               const uint16_t *lev, int64_t n, int32_t F, int64_t ldl,
+                               const uint64_t *ID, int64_t ldid,
+                               const uint64_t *LV, int32_t L, int64_t ldlv,
+                               int32_t D, uint64_t *H, int64_t ldh);
+
+/* ---------------------------------------------------------------------
  * hdc_convert_features -- diagnostic: the value each feature takes inside
  * the encoder under `compute` (the device conversion the kernels use),
  * written as float: out[i][f] for f < F.  out is [n][F] float.

@@ -345,6 +345,56 @@ hdc_status hdc_cosine_argmax_prepared(void *stream, const uint64_t *Q, int64_t n
                                         scores, (hipStream_t)stream));
 }
 
+hdc_status hdc_feature_perforate(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                                 hdc_dims fperf, void *Y, int64_t ldy)
+{
+    if (n < 0 || F <= 0 || fperf.stride < 1 || fperf.start < 0 || fperf.end <= fperf.start || fperf.end > F)
+        return HDC_ERR_INVALID;
+    int elem;
+    if (x_type == HDC_INT8 || x_type == HDC_UINT8)
+        elem = 1;
+    else if (x_type == HDC_FP32)
+        elem = 4;
+    else
+        return HDC_ERR_UNSUPPORTED;
+    const int32_t nf = dims_count(fperf);
+    if (n == 0)
+        return HDC_OK;
+    if (!X || !Y || ldx < F || ldy < nf || (ldy * elem) % 16 || !aligned(Y, 16))
+        return HDC_ERR_INVALID;
+    return from_hip(launch_gather_cols(X, elem, n, ldx, fperf.start, fperf.stride, nf, Y, ldy, (hipStream_t)stream));
+}
+
+hdc_status hdc_level_quantize(void *stream, const float *X, int64_t n, int32_t F, int64_t ldx, const float *lo,
+                              const float *hi, int32_t L, uint16_t *lev, int64_t ldl)
+{
+    if (n < 0 || F <= 0 || L < 1 || L > 65535)
+        return HDC_ERR_INVALID;
+    if (n == 0)
+        return HDC_OK;
+    if (!X || !lo || !hi || !lev || ldx < F || ldl < F)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_level_quantize(X, n, F, ldx, lo, hi, L, lev, ldl, (hipStream_t)stream));
+}
+
+hdc_status hdc_level_id_encode(void *stream, const uint16_t *lev, int64_t n, int32_t F, int64_t ldl,
+                               const uint64_t *ID, int64_t ldid, const uint64_t *LV, int32_t L, int64_t ldlv,
+                               int32_t D, uint64_t *H, int64_t ldh)
+{
+    if (n < 0 || F <= 0 || L < 1 || D <= 0)
+        return HDC_ERR_INVALID;
+    if (F > kMaxLevelIdF || L > kMaxLevels)
+        return HDC_ERR_UNSUPPORTED;
+    const int64_t W = (D + 63) / 64;
+    if (!ID || !LV || ldid < W || ldlv < W)
+        return HDC_ERR_INVALID;
+    if (n == 0)
+        return HDC_OK;
+    if (!lev || !H || ldl < (F + 7) / 8 * 8 || ldl % 8 || !aligned(lev, 16) || ldh < W)
+        return HDC_ERR_INVALID;
+    return from_hip(launch_level_id(lev, n, F, ldl, ID, ldid, LV, L, ldlv, D, H, ldh, (hipStream_t)stream));
+}
+
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
 {
     if (n_dims <= 0 || K <= 0 || K > kMaxK)

@@ -53,6 +53,10 @@ constexpr int kMaxConfigs = 4096;
 // The prepared searches address a workgroup's query rows with 32-bit byte
 // offsets from its first row (at most 256 rows).
 constexpr int64_t kMaxPreparedLdq = 1 << 20;
+// Level-ID encoding keeps a window of every identity and level hypervector
+// in LDS.
+constexpr int kMaxLevelIdF = 1024;
+constexpr int kMaxLevels = 1024;
 
 inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
 inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
@@ -91,6 +95,13 @@ hipError_t launch_retrain(const uint64_t *H, int64_t n, int nbits, int64_t ldh, 
 hipError_t launch_adc_argmax(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
                              int start, int end, int stride, int res, int step, int floor_, int ceil_,
                              int32_t *label, int32_t *max_score, int32_t *scores, hipStream_t st);
+hipError_t launch_gather_cols(const void *X, int elem, int64_t n, int64_t ldx, int start, int stride, int nf,
+                              void *Y, int64_t ldy, hipStream_t st);
+hipError_t launch_level_quantize(const float *X, int64_t n, int F, int64_t ldx, const float *lo, const float *hi,
+                                 int L, uint16_t *lev, int64_t ldl, hipStream_t st);
+hipError_t launch_level_id(const uint16_t *lev, int64_t n, int F, int64_t ldl, const uint64_t *ID, int64_t ldid,
+                           const uint64_t *LV, int L, int64_t ldlv, int D, uint64_t *H, int64_t ldh,
+                           hipStream_t st);
 hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute,
                           float *out, hipStream_t st);
 

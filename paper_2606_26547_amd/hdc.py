@@ -37,7 +37,8 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
            "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax",
-           "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared"]
+           "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared",
+           "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode"]
 
 
 class Dims(C.Structure):
@@ -93,6 +94,9 @@ _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int
 _lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
 _lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
 _lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
+_lib.hdc_feature_perforate.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, Dims, _p, _i64]
+_lib.hdc_level_quantize.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _i64]
+_lib.hdc_level_id_encode.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i64, _p, _i32, _i64, _i32, _p, _i64]
 _lib.hdc_cosine_workspace_bytes.restype = _sz
 _lib.hdc_cosine_workspace_bytes.argtypes = [Dims, _i32]
 _lib.hdc_cosine_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
@@ -218,6 +222,52 @@ class HammingPrepared:
                                                 _ptr(mn), _ptr(dists), _ptr(self.ws), self.ws.numel()),
                "hdc_hamming_argmin_prepared")
         return lab, mn, dists
+
+
+def feature_perforate(X: torch.Tensor, F: int, start: int, end: int, stride: int = 1,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """hdc_feature_perforate: the feature columns {start + j*stride < end}
+    of X (int8 / uint8 / float32 rows, or projection rows P) as a dense
+    matrix whose pitch (a multiple of 64 elements) the encoder accepts."""
+    nf = dims_count(start, end, stride)
+    ldy = max(64, (nf + 63) // 64 * 64)
+    if out is None:
+        out = torch.empty((X.shape[0], ldy), dtype=X.dtype, device=X.device)
+    _check(_lib.hdc_feature_perforate(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1],
+                                      Dims(start, end, stride), _ptr(out), out.shape[1]), "hdc_feature_perforate")
+    return out
+
+
+def level_quantize(X: torch.Tensor, lo: torch.Tensor, hi: torch.Tensor, L: int,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """hdc_level_quantize: levels [n][F] (uint16 values in an int16 tensor),
+    row pitch rounded up to 8 (as hdc_level_id_encode reads them); the
+    returned tensor is the [n][F] view."""
+    n, F = X.shape
+    if out is None:
+        out = torch.zeros((n, (F + 7) // 8 * 8), dtype=torch.int16, device=X.device)[:, :F]
+    _check(_lib.hdc_level_quantize(_stream(), _ptr(X), n, F, X.stride(0), _ptr(lo), _ptr(hi), L, _ptr(out),
+                                   out.stride(0)), "hdc_level_quantize")
+    return out
+
+
+def level_id_encode(lev: torch.Tensor, ID: torch.Tensor, LV: torch.Tensor, D: int,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """hdc_level_id_encode: packed Level-ID hypervectors [n][ceil(D/64)].
+    lev may be a column view of a row-major tensor whose pitch is a
+    multiple of 8; other layouts are copied into one."""
+    n, F = lev.shape
+    if lev.stride(1) != 1 or lev.stride(0) % 8 or lev.stride(0) < F or lev.data_ptr() % 16:
+        ld = (F + 7) // 8 * 8
+        buf = torch.zeros((n, ld), dtype=lev.dtype, device=lev.device)
+        buf[:, :F] = lev
+        lev = buf[:, :F]
+    W = (D + 63) // 64
+    if out is None:
+        out = torch.empty((n, W), dtype=torch.int64, device=lev.device)
+    _check(_lib.hdc_level_id_encode(_stream(), _ptr(lev), n, F, lev.stride(0), _ptr(ID), ID.shape[1], _ptr(LV),
+                                    LV.shape[0], LV.shape[1], D, _ptr(out), out.shape[1]), "hdc_level_id_encode")
+    return out
 
 
 def cosine_workspace_bytes(start: int, end: int, stride: int, K: int) -> int:

@@ -133,3 +133,23 @@ def test_cosine_validation_without_device(lib):
                                           need) == 0                                            # n == 0
     assert lib.hdc_cosine_argmax_prepared(None, fake, 4, (1 << 20) + 2, 3, Dims(0, 128, 1), fake, None, None, fake,
                                           need) == 2                                            # ldq too large
+
+
+def test_f3_validation_without_device(lib):
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_feature_perforate.argtypes = [p, p, C.c_int, i64, i32, i64, Dims, p, i64]
+    lib.hdc_level_quantize.argtypes = [p, p, i64, i32, i64, p, p, i32, p, i64]
+    lib.hdc_level_id_encode.argtypes = [p, p, i64, i32, i64, p, i64, p, i32, i64, i32, p, i64]
+    fake = C.c_void_p(1 << 20)
+    assert lib.hdc_feature_perforate(None, fake, 0, 4, 100, 128, Dims(0, 101, 1), fake, 128) == 1   # end > F
+    assert lib.hdc_feature_perforate(None, fake, 2, 4, 100, 128, Dims(0, 100, 1), fake, 128) == 2   # bf16 storage
+    assert lib.hdc_feature_perforate(None, fake, 4, 4, 100, 128, Dims(0, 100, 2), fake, 50) == 1    # ldy*4 % 16
+    assert lib.hdc_feature_perforate(None, fake, 0, 4, 100, 128, Dims(0, 100, 2), fake, 49) == 1    # ldy < nf
+    assert lib.hdc_level_quantize(None, fake, 4, 10, 10, fake, fake, 0, fake, 10) == 1               # L < 1
+    assert lib.hdc_level_quantize(None, fake, 4, 10, 9, fake, fake, 4, fake, 10) == 1                # ldx < F
+    assert lib.hdc_level_id_encode(None, fake, 4, 1025, 1025, fake, 2, fake, 4, 2, 128, fake, 2) == 2  # F > 1024
+    assert lib.hdc_level_id_encode(None, fake, 4, 10, 16, fake, 2, fake, 1025, 2, 128, fake, 2) == 2   # L > 1024
+    assert lib.hdc_level_id_encode(None, fake, 4, 10, 10, fake, 2, fake, 4, 2, 128, fake, 2) == 1      # ldl % 8
+    assert lib.hdc_level_id_encode(None, fake, 4, 10, 10, fake, 1, fake, 4, 2, 128, fake, 2) == 1      # ldid
+    assert lib.hdc_level_id_encode(None, fake, 4, 10, 16, fake, 2, fake, 4, 2, 128, fake, 1) == 1      # ldh
+    assert lib.hdc_level_id_encode(None, None, 0, 10, 10, fake, 2, fake, 4, 2, 128, None, 2) == 0      # n == 0

@@ -246,6 +246,9 @@ def main():
         out["adc"] = adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D)
         # -------------------------------------------------------- cosine similarity
         out["cosine"] = cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
+        # -------------------------------------------------------- encode-side knobs
+        out["encode_side"] = encode_side(dev, hdc, dg, torch, np, event_loop, sp, Xtr, ytr, Xte, Pd, Xqd, yqd,
+                                         F, K, D)
         # -------------------------------------------------------- retraining epochs
         out["retrain"] = retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
         # -------------------------------------------------------- precision ladder
@@ -336,6 +339,64 @@ def cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, 
                           "int8_tops": 2 * nq * D * 32 * 2 / (ms / 1e3) / 1e12}
     del Q
     log("cosine: %s, 2^20 search %.3f ms" % ({k: v["full"] for k, v in res.items() if k.startswith("epochs")}, ms))
+    return res
+
+
+def encode_side(dev, hdc, dg, torch, np, event_loop, sp, Xtr, ytr, Xte, Pd, Xqd, yqd, F, K, D):
+    """The encoder's own knobs on the speech workload: (a) perforating the
+    reduction over features (gather the columns, encode, bundle, classify)
+    -- test accuracy and the time of gather + fused classify on the bench
+    batch; (b) Level-ID encoding from the unquantised features -- test
+    accuracy for a few (levels, D) and the time of quantise + encode +
+    prepared Hamming search on the bench batch."""
+    yte = torch.as_tensor(sp.float_split()[3]).to(dev)
+    res = {"feature_perforation": {}, "level_id": {}}
+    n = Xqd.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+    for k in (1, 2, 4):
+        nf = hdc.dims_count(0, F, k)
+        Pg = hdc.feature_perforate(Pd, F, 0, F, k)
+        Htr = hdc.encode(hdc.feature_perforate(Xtr, F, 0, F, k), nf, Pg, D)
+        Cw, _ = hdc.bundle(Htr, D, ytr, K)
+        acc_te = float((hdc.classify(hdc.feature_perforate(Xte, F, 0, F, k), nf, Pg, D, Cw) == yte)
+                       .float().mean().item())
+        prep = hdc.Prepared(Cw, D, "int8")
+        Xg = torch.empty((n, max(64, (nf + 63) // 64 * 64)), dtype=torch.int8, device=dev)
+
+        def step():
+            hdc.feature_perforate(Xqd, F, 0, F, k, out=Xg)
+            prep(Xg, nf, Pg, lab)
+        ms_wall, ms, _ = event_loop(step, 5, 1)
+        res["feature_perforation"]["stride %d" % k] = {
+            "features": nf, "test_accuracy": acc_te, "batch_accuracy": float((lab == yqd).float().mean().item()),
+            "ms": ms, "queries_per_s": n / (ms / 1e3)}
+    Xtr_f, ytr_f, Xte_f, _ = sp.float_split()
+    lo, hi = dg.feature_ranges(Xtr_f)
+    lo_d, hi_d = torch.as_tensor(lo).to(dev), torch.as_tensor(hi).to(dev)
+    Xtr_d, Xte_d = torch.as_tensor(Xtr_f).to(dev), torch.as_tensor(Xte_f).to(dev)
+    Xq_f = torch.as_tensor(sp.mix.sample(yqd.cpu().numpy(), dg.rng(2, 99))).to(dev)
+    for L, Dl in ((16, 1024), (128, 1024), (128, 10240)):
+        ID = torch.as_tensor(dg.id_hypervectors(F, Dl, 21).view(np.int64)).to(dev)
+        LV = torch.as_tensor(dg.level_hypervectors(L, Dl, 22).view(np.int64)).to(dev)
+        Htr = hdc.level_id_encode(hdc.level_quantize(Xtr_d, lo_d, hi_d, L), ID, LV, Dl)
+        Cw, _ = hdc.bundle(Htr, Dl, ytr, K)
+        Hte = hdc.level_id_encode(hdc.level_quantize(Xte_d, lo_d, hi_d, L), ID, LV, Dl)
+        hp = hdc.HammingPrepared(Cw, 0, Dl, 1)
+        acc_te = float((hp(Hte)[0] == yte).float().mean().item())
+        lev = hdc.level_quantize(Xq_f, lo_d, hi_d, L)
+        Hq = torch.empty((n, Dl // 64), dtype=torch.int64, device=dev)
+
+        def step():
+            hdc.level_quantize(Xq_f, lo_d, hi_d, L, out=lev)
+            hdc.level_id_encode(lev, ID, LV, Dl, out=Hq)
+            hp(Hq, out=lab)
+        ms_wall, ms, _ = event_loop(step, 3, 1)
+        res["level_id"]["L=%d D=%d" % (L, Dl)] = {
+            "test_accuracy": acc_te, "batch_accuracy": float((lab == yqd).float().mean().item()),
+            "ms": ms, "queries_per_s": n / (ms / 1e3),
+            "word_features_per_s": n * F * (Dl / 32) / (ms / 1e3)}
+    log("encode-side: %s" % {g: {k: (round(v["test_accuracy"], 4), round(v["ms"], 3)) for k, v in r.items()}
+                             for g, r in res.items()})
     return res
 
 

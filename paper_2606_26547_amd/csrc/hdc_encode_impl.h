@@ -120,7 +120,10 @@ static hipError_t launch_encode_ct(const EncodeArgs &a, int mode, Tile tile, hip
         constexpr int K1 = 64 / KSTEP > 0 ? 64 / KSTEP : 1;
         if (F <= 64) return launch_bucket<CT, 0, K1>(a, mode, tile, st);
         if (F <= 128) return launch_bucket<CT, 0, 128 / KSTEP>(a, mode, tile, st);
+        if (F <= 192) return launch_bucket<CT, 0, 192 / KSTEP>(a, mode, tile, st);
         if (F <= 256) return launch_bucket<CT, 0, 256 / KSTEP>(a, mode, tile, st);
+        if (F <= 320) return launch_bucket<CT, 0, 320 / KSTEP>(a, mode, tile, st);
+        if (F <= 384) return launch_bucket<CT, 0, 384 / KSTEP>(a, mode, tile, st);
         if (F <= 512) return launch_bucket<CT, 0, 512 / KSTEP>(a, mode, tile, st);
         if (F <= 640) return launch_bucket<CT, 0, 640 / KSTEP>(a, mode, tile, st);
         if (F <= 832) return launch_bucket<CT, 0, 832 / KSTEP>(a, mode, tile, st);

@@ -87,7 +87,8 @@ hipError_t launch_level_quantize(const float *X, int64_t n, int F, int64_t ldx, 
 
 // ---------------------------------------------------------------- Level-ID
 constexpr int kLidWords = 8;    // 64-bit words (512 dimensions) per workgroup
-constexpr int kLidRows = 32;    // rows per workgroup
+constexpr int kLidRows = 32;    // rows per pass of a workgroup (256 threads / 8 words)
+constexpr int kLidPasses = 4;   // passes over one staged window (128 rows per workgroup)
 constexpr int kLidLvPitch = 9;  // padded level-row pitch in LDS (64-bit words)
 constexpr int kLidBig = 7;      // planes of the weight-16 counter (F <= 1024 -> count/16 <= 64)
 
@@ -97,7 +98,7 @@ size_t lid_lds_bytes(int F, int L) { return ((size_t)F * kLidWords + (size_t)L *
 __device__ __forceinline__ void csa(uint64_t &h, uint64_t &l, uint64_t a, uint64_t b, uint64_t c)
 {
     const uint64_t u = a ^ b;
-    h = (a & b) | (u & c);
+    h = ((a ^ c) & u) ^ a;      // a where a == b, c elsewhere (a bit select)
     l = u ^ c;
 }
 
@@ -154,35 +155,12 @@ struct LidCounter {
     }
 };
 
-__global__ __launch_bounds__(256) void k_level_id(const uint16_t *__restrict__ lev, int64_t n, int F, int64_t ldl,
-                                                  const uint64_t *__restrict__ ID, int64_t ldid,
-                                                  const uint64_t *__restrict__ LV, int L, int64_t ldlv, int D,
-                                                  uint64_t *__restrict__ H, int64_t ldh)
+// Bit word of one row: dimensions of the thread's word where more than half
+// of the F bound pairs are -1.
+__device__ __forceinline__ uint64_t level_id_word(const uint16_t *__restrict__ lrow, int F, int L,
+                                                  const HDC_LDS uint64_t *sidw, const HDC_LDS uint64_t *slvw)
 {
-    extern __shared__ __align__(16) uint64_t lds[];
-    uint64_t *sid = lds;                               // [F][kLidWords]
-    uint64_t *slv = lds + (size_t)F * kLidWords;       // [L][kLidLvPitch]
-    const int t = threadIdx.x;
-    const int W = (D + 63) / 64;
-    const int w0 = blockIdx.x * kLidWords;
-    const int nw = min(kLidWords, W - w0);
-    for (int e = t; e < F * kLidWords; e += 256) {
-        const int f = e / kLidWords, w = e % kLidWords;
-        sid[e] = w < nw ? ID[(int64_t)f * ldid + w0 + w] : 0ull;
-    }
-    for (int e = t; e < L * kLidWords; e += 256) {
-        const int l = e / kLidWords, w = e % kLidWords;
-        slv[l * kLidLvPitch + w] = w < nw ? LV[(int64_t)l * ldlv + w0 + w] : 0ull;
-    }
-    __syncthreads();
-
-    const int wi = t % kLidWords;
-    const int64_t row = (int64_t)blockIdx.y * kLidRows + t / kLidWords;
-    if (row >= n || wi >= nw)
-        return;
-    const uint4 *lr = (const uint4 *)(lev + row * ldl);   // 8 levels per 16 bytes
-    const uint64_t *sidw = sid + wi;
-    const uint64_t *slvw = slv + wi;
+    const uint4 *lr = (const uint4 *)lrow;                 // 8 levels per 16 bytes
     LidCounter cnt;
     const int Ffull = F & ~15;
     int f0 = 0;
@@ -192,8 +170,8 @@ __global__ __launch_bounds__(256) void k_level_id(const uint16_t *__restrict__ l
         uint64_t x[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int l = min((int)((lw[u / 2] >> (16 * (u & 1))) & 0xffffu), L - 1);
-            x[u] = sidw[(f0 + u) * kLidWords] ^ slvw[l * kLidLvPitch];
+            const uint32_t l = min((lw[u / 2] >> (16 * (u & 1))) & 0xffffu, (uint32_t)L - 1u);
+            x[u] = sidw[(f0 + u) * kLidWords] ^ slvw[__umul24(l, (uint32_t)kLidLvPitch)];
         }
         cnt.add16(x);
     }
@@ -203,33 +181,83 @@ __global__ __launch_bounds__(256) void k_level_id(const uint16_t *__restrict__ l
         for (int u = 0; u < 16; ++u) {
             x[u] = 0;
             if (f0 + u < F) {
-                const int l = min((int)lev[row * ldl + f0 + u], L - 1);
+                const int l = min((int)lrow[f0 + u], L - 1);
                 x[u] = sidw[(f0 + u) * kLidWords] ^ slvw[l * kLidLvPitch];
             }
         }
         cnt.add16(x);
     }
-    uint64_t gt = cnt.greater((uint32_t)F >> 1);
+    return cnt.greater((uint32_t)F >> 1);
+}
+
+__global__ __launch_bounds__(256) void k_level_id(const uint16_t *__restrict__ lev, int64_t n, int F, int64_t ldl,
+                                                  const uint64_t *__restrict__ ID, int64_t ldid,
+                                                  const uint64_t *__restrict__ LV, int L, int64_t ldlv, int D,
+                                                  uint64_t *__restrict__ H, int64_t ldh)
+{
+    extern __shared__ __align__(16) uint64_t lds_raw[];
+    typedef HDC_LDS uint64_t lds_u64;
+    lds_u64 *sid = (lds_u64 *)lds_raw;                 // [F][kLidWords]
+    lds_u64 *slv = sid + F * kLidWords;                // [L][kLidLvPitch]
+    const int t = threadIdx.x;
+    const int W = (D + 63) / 64;
+    const int w0 = blockIdx.x * kLidWords;
+    const int nw = min(kLidWords, W - w0);
+    // staging: 8 independent loads in flight per thread before their stores
+    {
+        const int ne = (F + L) * kLidWords;
+        for (int e0 = 0; e0 < ne; e0 += 8 * 256) {
+            uint64_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = e0 + j * 256 + t;
+                const int r = e / kLidWords, w = e % kLidWords;
+                v[j] = 0;
+                if (e < ne && w < nw)
+                    v[j] = r < F ? ID[(int64_t)r * ldid + w0 + w] : LV[(int64_t)(r - F) * ldlv + w0 + w];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = e0 + j * 256 + t;
+                const int r = e / kLidWords, w = e % kLidWords;
+                if (e < ne) {
+                    if (r < F)
+                        sid[e] = v[j];
+                    else
+                        slv[(r - F) * kLidLvPitch + w] = v[j];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    const int wi = t % kLidWords;
+    if (wi >= nw)
+        return;
+    const lds_u64 *sidw = sid + wi;
+    const lds_u64 *slvw = slv + wi;
     const int wg = w0 + wi;
-    if (wg == W - 1 && (D & 63))
-        gt &= (1ull << (D & 63)) - 1ull;
-    H[row * ldh + wg] = gt;
+    const uint64_t tail_mask = (wg == W - 1 && (D & 63)) ? (1ull << (D & 63)) - 1ull : ~0ull;
+    for (int pass = 0; pass < kLidPasses; ++pass) {
+        const int64_t row = ((int64_t)blockIdx.y * kLidPasses + pass) * kLidRows + t / kLidWords;
+        if (row >= n)
+            break;
+        H[row * ldh + wg] = level_id_word(lev + row * ldl, F, L, sidw, slvw) & tail_mask;
+    }
 }
 
 hipError_t launch_level_id(const uint16_t *lev, int64_t n, int F, int64_t ldl, const uint64_t *ID, int64_t ldid,
                            const uint64_t *LV, int L, int64_t ldlv, int D, uint64_t *H, int64_t ldh, hipStream_t st)
 {
     const size_t lds = lid_lds_bytes(F, L);
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute((const void *)k_level_id,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
+    // once per process (thread-safe static initialisation)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_level_id,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess)
+        return attr;
     const int W = (D + 63) / 64;
-    const dim3 grid((unsigned)((W + kLidWords - 1) / kLidWords), (unsigned)((n + kLidRows - 1) / kLidRows));
+    const int64_t rows_per_wg = (int64_t)kLidRows * kLidPasses;
+    const dim3 grid((unsigned)((W + kLidWords - 1) / kLidWords), (unsigned)((n + rows_per_wg - 1) / rows_per_wg));
     hipLaunchKernelGGL(k_level_id, grid, dim3(256), lds, st, lev, n, F, ldl, ID, ldid, LV, L, ldlv, D, H, ldh);
     return hipGetLastError();
 }

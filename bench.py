@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 MFMA_INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
+# 32-bit VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the fp32
+# vector peak of 157.3 TFLOP/s counts an FMA as two flops and packs two lanes)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -285,8 +288,57 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f), tuned %.1f q/s, one thread %.1f q/s" %
             (n_cpu / dt, O.threads(), agree, out["cpu_baseline"].get("tuned_value", 0.0),
              out["cpu_baseline"]["single_thread_value"]))
+        if not args.no_extras:
+            out["cpu_baseline"]["rows"] = oracle_rows(O, np, ds, F, K, D)
 
     print(json.dumps(out), flush=True)
+
+
+def oracle_rows(O, np, ds, F, K, D):
+    """The oracle timed on a bounded sample of each path beside the headline
+    one (same shapes as the GPU figures in the sections above; seeded
+    random operands, whose values do not change the oracle's work)."""
+    g = np.random.default_rng(77)
+    W = D // 64
+    rows = {}
+
+    def timed(name, n, unit, fn, sample):
+        t = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t
+        rows[name] = {"value": n / dt, "unit": unit, "cores": O.threads(), "kind": "oracle",
+                      "sample": "%s, %.2fs" % (sample, dt)}
+
+    Q = g.integers(0, 2 ** 63, size=(1 << 18, W), dtype=np.int64).view(np.uint64)
+    C = g.integers(0, 2 ** 63, size=(K, W), dtype=np.int64).view(np.uint64)
+    acc = g.integers(-300, 301, size=(K, D), dtype=np.int32)
+    timed("hamming_search", 1 << 18, "queries/s", lambda: O.argmin(O.hamming_popcount(Q, C, 0, D, 1)),
+          "262144 queries x %d classes x %d bits, popcount distances + argmin" % (K, D))
+    timed("cosine", 4096, "queries/s", lambda: O.argmax_f64(O.cosine_scores(Q[:4096], acc, 0, D, 1)),
+          "4096 queries x %d classes x %d dimensions" % (K, D))
+    timed("adc", 4096, "queries/s", lambda: O.argmax(O.adc_scores(Q[:4096], C, 0, D, 1, 8, 2, -3, 128)),
+          "4096 queries, ADC (8, 2, -3, 128)")
+    X = np.ascontiguousarray(ds.X_train[:4096])
+    timed("feature_perforation_stride2", 4096, "queries/s", lambda: O.encode_fperf(X, ds.P, 0, F, 2),
+          "4096 speech rows, feature stride 2, D = %d" % D)
+    L = 128
+    lev = g.integers(0, L, size=(256, F)).astype(np.uint16)
+    IDh = g.integers(0, 2 ** 63, size=(F, W), dtype=np.int64).view(np.uint64)
+    LVh = g.integers(0, 2 ** 63, size=(L, W), dtype=np.int64).view(np.uint64)
+    timed("level_id_encode", 256, "rows/s", lambda: O.level_id_encode(lev, IDh, LVh, D),
+          "256 rows x %d features, L = %d, D = %d" % (F, L, D))
+    n_tr = ds.X_train.shape[0]
+    H = g.integers(0, 2 ** 63, size=(n_tr, W), dtype=np.int64).view(np.uint64)
+    acc_tr = O.class_acc(H, ds.y_train, K, D)
+
+    def epochs():
+        for _ in range(20):
+            pred, _ = O.argmin(O.hamming_popcount(H, O.binarize(acc_tr, D), 0, D, 1))
+            O.retrain_epoch(H, ds.y_train, pred, acc_tr, D)
+    timed("retrain_epoch", 20 * n_tr, "training rows/s", epochs,
+          "20 epochs over %d training rows (predict + update), D = %d" % (n_tr, D))
+    log("cpu oracle rows: %s" % {k: "%.3g %s" % (v["value"], v["unit"]) for k, v in rows.items()})
+    return rows
 
 
 def adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D):
@@ -305,7 +357,13 @@ def adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D):
     nq = 1 << 20
     Q = torch.randint(-(1 << 62), 1 << 62, (nq, D // 64), dtype=torch.int64, device=dev)
     _, ms, _ = event_loop(lambda: hdc.adc_argmax(Q, Cw, 0, D, 1, (8, 2, -3, 128)), 5, 1)
-    res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9}
+    res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9, "queries_per_s": nq / (ms / 1e3)}
+    # VALU-bound: per (query, class, 128-dimension chunk) two words' XOR,
+    # AND, popcount and add, a table read and an add (about 8 operations)
+    ops = nq * Cw.shape[0] * (D / 128) * 8
+    res["roofline"] = {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": VALU_PEAK_TOPS,
+                       "unit": "TOP/s", "frac": ops / (ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                       "ops_per_launch": ops}
     del Q
     log("adc: %s" % {k: (v["accuracy"] if isinstance(v, dict) and "accuracy" in v else v) for k, v in res.items()})
     return res
@@ -337,6 +395,12 @@ def cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, 
     _, ms, _ = event_loop(lambda: cp(Q, out=lab), 10, 2)
     res["search_2^20"] = {"ms": ms, "GB_s": nq * D / 8 / (ms / 1e3) / 1e9, "queries_per_s": nq / (ms / 1e3),
                           "int8_tops": 2 * nq * D * 32 * 2 / (ms / 1e3) / 1e12}
+    # matrix cores: two int8 32x32x32 MFMAs per (32 queries, 32 dimensions,
+    # class tile of 32): 2 * 2 * n * D * 32 ops executed for K <= 32
+    ops = 2 * 2 * nq * D * 32
+    res["roofline"] = {"bound": "mfma", "achieved": ops / (ms / 1e3) / 1e12, "peak": MFMA_INT8_PEAK_TOPS,
+                       "unit": "TOP/s", "frac": ops / (ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS, "ops_per_launch": ops,
+                       "algorithmic_ops_per_launch": 2 * nq * D * K}
     del Q
     log("cosine: %s, 2^20 search %.3f ms" % ({k: v["full"] for k, v in res.items() if k.startswith("epochs")}, ms))
     return res
@@ -367,9 +431,13 @@ def encode_side(dev, hdc, dg, torch, np, event_loop, sp, Xtr, ytr, Xte, Pd, Xqd,
             hdc.feature_perforate(Xqd, F, 0, F, k, out=Xg)
             prep(Xg, nf, Pg, lab)
         ms_wall, ms, _ = event_loop(step, 5, 1)
+        ops = 2.0 * n * nf * D                 # algorithmic encode ops of the perforated product
         res["feature_perforation"]["stride %d" % k] = {
             "features": nf, "test_accuracy": acc_te, "batch_accuracy": float((lab == yqd).float().mean().item()),
-            "ms": ms, "queries_per_s": n / (ms / 1e3)}
+            "ms": ms, "queries_per_s": n / (ms / 1e3),
+            "roofline": {"bound": "mfma", "achieved": ops / (ms / 1e3) / 1e12, "peak": MFMA_INT8_PEAK_TOPS,
+                         "unit": "TOP/s", "frac": ops / (ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS,
+                         "note": "gather + fused classify per batch"}}
     Xtr_f, ytr_f, Xte_f, _ = sp.float_split()
     lo, hi = dg.feature_ranges(Xtr_f)
     lo_d, hi_d = torch.as_tensor(lo).to(dev), torch.as_tensor(hi).to(dev)
@@ -391,10 +459,17 @@ def encode_side(dev, hdc, dg, torch, np, event_loop, sp, Xtr, ytr, Xte, Pd, Xqd,
             hdc.level_id_encode(lev, ID, LV, Dl, out=Hq)
             hp(Hq, out=lab)
         ms_wall, ms, _ = event_loop(step, 3, 1)
+        _, ms_enc, _ = event_loop(lambda: hdc.level_id_encode(lev, ID, LV, Dl, out=Hq), 3, 1)
+        # VALU-bound: about 5 operations (bind XOR + carry-save adders) per
+        # (row, feature, 32 dimensions)
+        ops = n * F * (Dl / 32) * 5
         res["level_id"]["L=%d D=%d" % (L, Dl)] = {
             "test_accuracy": acc_te, "batch_accuracy": float((lab == yqd).float().mean().item()),
-            "ms": ms, "queries_per_s": n / (ms / 1e3),
-            "word_features_per_s": n * F * (Dl / 32) / (ms / 1e3)}
+            "ms": ms, "queries_per_s": n / (ms / 1e3), "encode_ms": ms_enc,
+            "word_features_per_s": n * F * (Dl / 32) / (ms_enc / 1e3),
+            "roofline": {"bound": "alu", "achieved": ops / (ms_enc / 1e3) / 1e12, "peak": VALU_PEAK_TOPS,
+                         "unit": "TOP/s", "frac": ops / (ms_enc / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                         "ops_per_launch": ops}}
     log("encode-side: %s" % {g: {k: (round(v["test_accuracy"], 4), round(v["ms"], 3)) for k, v in r.items()}
                              for g, r in res.items()})
     return res

@@ -7,7 +7,7 @@
 // The second sum runs as int8 MFMAs (rows = classes, columns = queries,
 // K = 32 dimensions): a_kd = 256 * hi + lo with hi, lo in [-128, 127]
 // (|a| <= 32639), one MFMA per part; the query operand holds the bits as
-// bytes {0, 1}, spread from the packed dword with one multiply per 4 bits.
+// bytes {0, 1}, two operations per register (see spread_bits).
 // score_k = (double)dot_k * rinv_k with rinv_k = 1 / sqrt(sum_S a_kd^2)
 // (0 for an all-zero class), both roundings correctly rounded, so the
 // scores equal a plain double computation bit for bit; label = first class
@@ -17,9 +17,11 @@
 //
 // Prepared operand (hdc_cosine_prepare): for word w (from the even word at
 // or below the first word of S, padded to whole 8-word windows), dword half
-// h, part p (lo, hi) and class tile kt, 64 lanes x 16 bytes: lane l, byte b
-// holds part p of a_kd for class kt*32 + l%32 at dimension
-// 64w + 32h + 16*(l/32) + b (0 outside S); then T_k = sum_S a_kd (int64)
+// h, part p (lo, hi) and class tile kt, 64 lanes x 16 bytes: lane l, byte
+// b = 4r + i holds part p of a_kd for class kt*32 + l%32 at dimension
+// 64w + 32h + 4*(l/32) + r + 8i (0 outside S), the order in which the
+// query operand takes the dword's bits (register r of lane half g =
+// (dword >> (4g + r)) & 0x01010101); then T_k = sum_S a_kd (int64)
 // and rinv_k (double) for 128 classes, max |a_kd| over S per class (int32)
 // and the range flag.
 //
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(256) void k_cos_table(const int32_t *__restrict__ a
     if (k < K) {
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
-            const int64_t d = w * 64 + 32 * h + 16 * g + b;
+            const int64_t d = w * 64 + 32 * h + 4 * g + (b >> 2) + 8 * (b & 3);
             if (in_set(d, start, end, stride)) {
                 const int a = acc[k * lda + d];
                 const int hi = (a + 128) >> 8;
@@ -150,15 +152,15 @@ __global__ __launch_bounds__(128) void k_cos_flag(const int32_t *__restrict__ am
         flag[0] = bad ? 0 : 1;
 }
 
-// Query bits as bytes: register r of lane half g holds, in byte i, bit
-// 16g + 4r + i of the dword (the multiply moves bit i of a nibble to bit 8i).
+// Query bits as bytes {0, 1}: register r of lane half g holds, in byte i,
+// bit 4g + r + 8i of the dword (two operations per register).
 __device__ __forceinline__ v4i spread_bits(uint32_t d, uint32_t sh)
 {
     const uint32_t e = d >> sh;
     v4i b;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        b[r] = (int)((((e >> (4 * r)) & 0xFu) * 0x00204081u) & 0x01010101u);
+        b[r] = (int)((e >> r) & 0x01010101u);
     return b;
 }
 
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) void k_cosine_mfma(const uint64_t *__restrict_
     __shared__ __align__(16) uint8_t smem[NST * S::SB];
     lds_u8 *L = (lds_u8 *)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
-    const uint32_t sh = 16u * (uint32_t)g;
+    const uint32_t sh = 4u * (uint32_t)g;
     const int64_t rbase = (int64_t)blockIdx.x * S::ROWS;
     const uint64_t *Qwg = Q + rbase * ldq;
 

@@ -34,6 +34,9 @@ from concurrent.futures import Future
 
 import numpy as np
 
+# Largest configuration job a slot holds results for (the sweep's own limit).
+MAX_JOB_CONFIGS = 4096
+
 
 # ---------------------------------------------------------------- requests
 @dataclasses.dataclass
@@ -141,16 +144,19 @@ class Scheduler:
 class GpuExecutor:
     """Resident models and per-model streams; runs batches asynchronously.
 
-    Inference batches use a pool of staging slots (pinned host + device
-    buffers for the queries and the labels, sized for ``max_batch`` queries
-    of the widest model), reused once allocated: the pool grows only to the
-    largest number of batches in flight, so a steady-state launch allocates
-    nothing.  The queries are copied into the slot's pinned buffer, then one
-    H2D copy, one fused-classifier launch and one D2H copy are queued on the
-    model's stream and closed by the slot's event."""
+    Every batch, inference or configuration job, runs out of a staging slot
+    (pinned host + device buffers for the queries, labels or truth, and the
+    per-configuration results, sized for ``max_batch`` queries of the widest
+    model).  The pool is allocated up front for every batch the scheduler
+    can have in flight (``depth`` per model lane and per configuration job
+    in flight, plus headroom), because a pinned allocation of a new slot
+    takes milliseconds and stalls every request behind it; it still grows
+    if more are ever needed.  The queries are copied into the slot's pinned
+    buffer, then one H2D copy, the launch and one D2H copy are queued on the
+    lane's stream and closed by the slot's event."""
 
     def __init__(self, models, device="cuda", max_batch: int = 16384, job_workgroups: int = 64,
-                 slots: int = 4):
+                 slots: int | None = None, depth: int = 2):
         import torch
 
         from . import hdc
@@ -170,6 +176,8 @@ class GpuExecutor:
         self.ld_max = max(m.P.shape[1] for m in models)
         self.free = collections.deque()
         self.nslots = 0
+        if slots is None:
+            slots = depth * (len(models) + 2)
         for _ in range(slots):
             self.free.append(self._new_slot())
 
@@ -194,8 +202,9 @@ class GpuExecutor:
         n, ld = self.max_batch, self.ld_max
         return {"hx": torch.empty(n * ld, dtype=torch.int8, pin_memory=True),
                 "dx": torch.empty(n * ld, dtype=torch.int8, device=self.dev),
-                "hl": torch.empty(n, dtype=torch.int32, pin_memory=True),
+                "hl": torch.empty(n, dtype=torch.int32, pin_memory=True),   # labels / truth
                 "dl": torch.empty(n, dtype=torch.int32, device=self.dev),
+                "hc": torch.empty(MAX_JOB_CONFIGS, dtype=torch.int32, pin_memory=True),
                 "ev": torch.cuda.Event()}
 
     @staticmethod
@@ -207,26 +216,11 @@ class GpuExecutor:
         torch, hdc = self.torch, self.hdc
         r0 = b.requests[0]
         m = self.models[r0.model]
-        if r0.kind == "configs":
-            stream = self.cfg_stream
-            ld = m.P.shape[1]
-            host = torch.zeros((b.n, ld), dtype=torch.int8, pin_memory=True)
-            host.numpy()[:, :m.F] = r0.X
-            with torch.cuda.stream(stream):
-                X = host.to(self.dev, non_blocking=True)
-                truth = torch.as_tensor(r0.truth, dtype=torch.int32).pin_memory().to(self.dev, non_blocking=True)
-                correct, _ = hdc.eval_configs(X, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws,
-                                              max_workgroups=self.job_workgroups)
-                out = torch.empty(len(r0.cfgs), dtype=torch.int32, pin_memory=True)
-                out.copy_(correct, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(stream)
-            b.handle = ("configs", ev, out, host, X, truth)
-            return
         if b.n > self.max_batch:
             raise ValueError("batch of %d queries exceeds max_batch %d" % (b.n, self.max_batch))
+        if r0.kind == "configs" and len(r0.cfgs) > MAX_JOB_CONFIGS:
+            raise ValueError("configuration job of %d configurations exceeds %d" % (len(r0.cfgs), MAX_JOB_CONFIGS))
         slot = self.free.popleft() if self.free else self._new_slot()
-        stream = self.streams[r0.model]
         ld = m.P.shape[1]
         hxt = slot["hx"][:b.n * ld].view(b.n, ld)
         hx = hxt.numpy()
@@ -234,6 +228,21 @@ class GpuExecutor:
             hx[off:off + r.n, :m.F] = r.X
         if ld > m.F:
             hx[:, m.F:] = 0
+        if r0.kind == "configs":
+            nc = len(r0.cfgs)
+            slot["hl"].numpy()[:b.n] = r0.truth
+            with torch.cuda.stream(self.cfg_stream):
+                dx = slot["dx"][:b.n * ld].view(b.n, ld)
+                dx.copy_(hxt, non_blocking=True)
+                truth = slot["dl"][:b.n]
+                truth.copy_(slot["hl"][:b.n], non_blocking=True)
+                correct, _ = hdc.eval_configs(dx, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws,
+                                              max_workgroups=self.job_workgroups)
+                slot["hc"][:nc].copy_(correct, non_blocking=True)
+                slot["ev"].record(self.cfg_stream)
+            b.handle = ("configs", slot, nc)
+            return
+        stream = self.streams[r0.model]
         with torch.cuda.stream(stream):
             dx = slot["dx"][:b.n * ld].view(b.n, ld)
             dx.copy_(hxt, non_blocking=True)
@@ -244,18 +253,17 @@ class GpuExecutor:
         b.handle = ("infer", slot)
 
     def ready(self, b: Batch) -> bool:
-        h = b.handle
-        return (h[1] if h[0] == "configs" else h[1]["ev"]).query()
+        return b.handle[1]["ev"].query()
 
     def results(self, b: Batch):
         h = b.handle
-        if h[0] == "configs":
-            h[1].synchronize()
-            return [h[2].numpy().copy()]
         slot = h[1]
         slot["ev"].synchronize()
-        res = slot["hl"].numpy()
-        out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
+        if h[0] == "configs":
+            out = [slot["hc"].numpy()[:h[2]].copy()]
+        else:
+            res = slot["hl"].numpy()
+            out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
         self.free.append(slot)
         return out
 

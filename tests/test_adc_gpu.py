@@ -45,3 +45,23 @@ def test_adc_argmax_bit_exact(hdc, case):
     assert np.array_equal(sc.cpu().numpy(), ref)
     assert np.array_equal(lab.cpu().numpy(), lref)
     assert np.array_equal(mx.cpu().numpy(), mref)
+
+
+def test_adc_full_size_sampled(hdc):
+    """2^20 query hypervectors of 10240 bits against 26 classes under the
+    tuned ADC setting (the launch the search figure times); 2048 sampled
+    rows' scores and labels against the oracle."""
+    print("[case] adc 2^20 x 10240 x 26", flush=True)
+    n, D, K = 1 << 20, 10240, 26
+    g = torch.Generator(device="cuda").manual_seed(31)
+    Q = torch.randint(-(1 << 62), 1 << 62, (n, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    Cw = torch.randint(-(1 << 62), 1 << 62, (K, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    lab, mx, _ = hdc.adc_argmax(Q, Cw, 0, D, 1, (8, 2, -3, 128), True)
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(31).choice(n, 2048, replace=False))
+    rows[-1] = n - 1
+    r = torch.as_tensor(rows).cuda()
+    ref = O.adc_scores(Q[r].cpu().numpy().view(np.uint64), Cw.cpu().numpy().view(np.uint64), 0, D, 1, 8, 2, -3, 128)
+    lref, mref = O.argmax(ref)
+    assert np.array_equal(lab[r].cpu().numpy(), lref)
+    assert np.array_equal(mx[r].cpu().numpy(), mref)

@@ -165,3 +165,30 @@ def test_level_id_full_size_sampled(hdc):
     r = torch.as_tensor(rows).cuda()
     ls = lev[r].cpu().numpy().view(np.uint16)
     assert np.array_equal(H[r].cpu().numpy().view(np.uint64), O.level_id_encode(ls, ID, LV, D))
+
+
+def test_fperf_full_size_sampled(hdc):
+    """The bench batch: 2^18 speech-shaped int8 queries, features perforated
+    with stride 2, gathered and classified by the fused kernel against 26
+    classes at D = 10240; 512 sampled rows' labels and distances against the
+    oracle's rescaled perforated encoding."""
+    print("[case] fperf 2^18 x 617 x 10240", flush=True)
+    n, F, D, K = 1 << 18, 617, 10240, 26
+    gen = torch.Generator(device="cuda").manual_seed(41)
+    Xd = torch.zeros((n, 640), dtype=torch.int8, device="cuda")
+    Xd[:, :F] = torch.randint(-127, 128, (n, F), dtype=torch.int8, device="cuda", generator=gen)
+    P = dg.projection_matrix(D, F, 41)
+    Cw = torch.randint(-(1 << 62), 1 << 62, (K, D // 64), dtype=torch.int64, device="cuda", generator=gen)
+    Pg = hdc.feature_perforate(torch.as_tensor(_pad64(P)).cuda(), F, 0, F, 2)
+    nf = O.dims_count(0, F, 2)
+    prep = hdc.Prepared(Cw, D, "int8")
+    lab, dists = prep(hdc.feature_perforate(Xd, F, 0, F, 2), nf, Pg, with_dists=True)
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(41).choice(n, 512, replace=False))
+    rows[-1] = n - 1
+    r = torch.as_tensor(rows).cuda()
+    Xs = Xd[r, :F].cpu().numpy()
+    Hq = O.encode_fperf(Xs, P, 0, F, 2)
+    ref = O.hamming(Hq, Cw.cpu().numpy().view(np.uint64), 0, D, 1)
+    assert np.array_equal(dists[r].cpu().numpy(), ref)
+    assert np.array_equal(lab[r].cpu().numpy(), O.argmin(ref)[0])

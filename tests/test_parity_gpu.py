@@ -160,9 +160,10 @@ def test_hamming_prepared_bit_exact(hdc, case):
 
 
 def test_hamming_prepared_full_size(hdc):
-    """2^18 speech-shaped queries (D = 10240, 26 classes) and a perforated
-    search: both search kernels agree everywhere, the oracle on a sample."""
-    n, D, K = 1 << 18, 10240, 26
+    """2^20 speech-shaped queries (D = 10240, 26 classes; the launch the
+    search throughput figure times) and a perforated search: both search
+    kernels agree everywhere, the oracle on a sample."""
+    n, D, K = 1 << 20, 10240, 26
     say("hamming_prepared_full", n, D, K)
     g = torch.Generator(device="cuda").manual_seed(17)
     Qd = torch.randint(-2 ** 63, 2 ** 63 - 1, (n, D // 64), dtype=torch.int64, device="cuda", generator=g)
@@ -174,6 +175,7 @@ def test_hamming_prepared_full_size(hdc):
         torch.cuda.synchronize()
         assert torch.equal(lab, lab2) and torch.equal(mn, mn2)
         idx = torch.arange(0, n, 997, device="cuda")
+        idx[-1] = n - 1
         Qs = Qd[idx].cpu().numpy().view(np.uint64)
         lref, mref = O.argmin(O.hamming(Qs, Cd.cpu().numpy().view(np.uint64), s, e, k))
         assert np.array_equal(lab[idx].cpu().numpy(), lref)

@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=98304)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
+    ap.add_argument("--no-autotune", action="store_true", help="built-in tile choices, no tuning launches")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     return ap.parse_args()
 
@@ -58,16 +59,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(key: str, batch: int):
+def measured_traffic(key: str, batch: int, tile: str):
     """HBM bytes per launch of a kernel from profiles/traffic.json (rocprofv3
     FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when the kernel's
-    sources changed since the counters were taken or the batch differs."""
+    sources changed since the counters were taken, the batch differs or the
+    launch uses another tile variant."""
     try:
         t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
         h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in t["sources"])).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    if h != t["sha256"] or int(t["batch"]) != batch:
+    if h != t["sha256"] or int(t["batch"]) != batch or t.get("tile") != tile:
         return None
     return float(t["bytes_per_launch"])
 
@@ -131,6 +133,21 @@ def main():
         durs = [a.elapsed_time(b) for a, b in ev]          # ms, on the launch stream
         return wall * 1e3 / steps, float(np.mean(durs)), durs
 
+    # ------------------------------------------------------------ tile autotuning
+    # the buckets this run launches: the speech classifier and encoder and
+    # the configuration sweep (2000 queries, the 256 sampled slots)
+    from paper_2606_26547_amd import autotune as AT
+    slots = [(d, k, 0, t) for (d, k, t) in dg.sweep_slots(4)]
+    tile_shapes = [AT.Shape("classify", F, K, D, 65536), AT.Shape("encode", F, 1, D, 8192),
+                   AT.Shape("sweep", F, K, D, dg.C4["n_queries"], cfgs=slots)]
+    t0 = time.time()
+    tiles = AT.autotune(tile_shapes) if not args.no_autotune else []
+    cls_tile = hdc.TILE_NAMES["classify"][hdc.get_tile("classify", "int8", "int8", F, K) or
+                                          hdc.tile_variants("classify", "int8", "int8", F, K)[0]]
+    log("tiles (%.1fs): %s" % (time.time() - t0, {c.shape.kind: (c.chosen_name, {k: round(v, 3) for k, v in
+                                                                                 c.variants.items()})
+                                                  for c in tiles}))
+
     # ------------------------------------------------------------ plain steps
     plain = hdc.Prepared(Cw, D, "int8")
     labels = torch.empty(N, dtype=torch.int32, device=dev)
@@ -159,9 +176,11 @@ def main():
                                "plain config, batch of %d fresh queries; model bundled from 6238 train vectors" % N,
                    "F": F, "K": K, "D": D, "batch": N, "parallelism": "none (1 GPU)"},
         "accuracy_plain": acc_plain,
+        "tiles": AT.to_json(tiles) if tiles else None,
         "roofline": {"bound": "mfma", "kernel": "k_encode<int8, classify>", "achieved": achieved,
                      "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
-                     "traffic": measured_traffic("k_encode_classify_speech_b262144", N),
+                     "traffic": measured_traffic("k_encode_classify_speech_b262144", N, cls_tile),
+                     "tile": cls_tile,
                      "traffic_unit": "bytes per launch (HBM read + write, profiles/traffic.json)",
                      "ms_per_launch": ms_kernel,
                      "ops_per_launch": ops},
@@ -174,7 +193,6 @@ def main():
                         "note": "encode of the training set + majority bundle"}
         # -------------------------------------------------------- sweep + tuned selection
         grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
-        slots = [(d, k, 0, t) for (d, k, t) in dg.sweep_slots(4)]
         tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)                  # warm-up launch
         torch.cuda.synchronize()
         t = time.perf_counter()

@@ -353,6 +353,56 @@ hdc_status hdc_eval_configs(void *stream,
                             hdc_config_result *out,
                             void *ws, size_t ws_bytes, int32_t max_workgroups);
 
+/* ---------------------------------------------------------------------
+ * Tile table -- the kernel shape each launch uses, for an autotuner that
+ * times the variants of a shape on the device and keeps the fastest (the
+ * sweep of approximation configurations, and the encoder and classifier,
+ * run with tiles picked this way).  A bucket is (kind, x_type, compute,
+ * the compiled feature width the launch uses for F, the class tiles of K:
+ * 1, 2 or 4 for K <= 32, 64, 128; the sweep compiles 1 or 4).  Every
+ * variant of a bucket computes identical results; only the time differs.
+ *   kind      HDC_KERNEL_ENCODE (hdc_encode), HDC_KERNEL_CLASSIFY
+ *             (hdc_classify, hdc_classify_prepared), HDC_KERNEL_SWEEP
+ *             (hdc_eval_configs; compute is ignored, x_type is the
+ *             feature type of the job)
+ *   variants  encoder / classifier: HDC_TILE_DMA_2X2 and HDC_TILE_DMA_1X1
+ *             (projection staged straight into LDS; two query tiles x two
+ *             dimension tiles per wave, or one of each; int8 features on the
+ *             int8 path), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
+ *             staging, two or one query tiles of 32 per wave);
+ *             sweep: HDC_TILE_SWEEP_128 (work items of 128 queries) and
+ *             HDC_TILE_SWEEP_256 (items of 256: int8 slots take two query
+ *             tiles per wave where the registers allow)
+ * hdc_tile_variants writes up to `cap` (host array) variant ids the bucket
+ * is compiled with, the built-in choice first, and returns how many there
+ * are, or -1 for a shape outside the compiled kernels.  hdc_set_tile sets
+ * the bucket's variant, 0 restoring the built-in choice; a variant the
+ * bucket does not have gives HDC_ERR_UNSUPPORTED, a shape outside the
+ * compiled kernels HDC_ERR_INVALID.  The table is process-wide and read at
+ * each launch (no stream ordering: set it before enqueuing the launches it
+ * is meant for).  hdc_get_tile returns the bucket's variant, or -1.
+ * ------------------------------------------------------------------- */
+typedef enum {
+    HDC_KERNEL_ENCODE = 0,
+    HDC_KERNEL_CLASSIFY = 1,
+    HDC_KERNEL_SWEEP = 2
+} hdc_kernel;
+
+enum {
+    HDC_TILE_DMA_2X2 = 1,
+    HDC_TILE_DMA_1X1 = 2,
+    HDC_TILE_REG_QT1 = 3,
+    HDC_TILE_REG_QT2 = 4,
+    HDC_TILE_SWEEP_128 = 1,
+    HDC_TILE_SWEEP_256 = 2
+};
+
+int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
+                          int32_t *variants, int32_t cap);
+hdc_status hdc_set_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
+                        int32_t variant);
+int32_t hdc_get_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K);
+
 /* Frequency in Hz of the device wall clock that hdc_eval_configs reads. */
 double hdc_device_clock_hz(void);
 

@@ -144,7 +144,8 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
     EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
     a.H32 = (uint32_t *)H;
     a.ldh32 = 2 * ldh;
-    return from_hip(launch_encode(a, ct, M_ENCODE, Tile{0}, (hipStream_t)stream));
+    const int v = get_tile(KK_ENCODE, xt, ct, F, 1);
+    return from_hip(launch_encode(a, ct, M_ENCODE, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
 }
 
 size_t hdc_bundle_workspace_bytes(int32_t nbits, int32_t K)
@@ -395,6 +396,54 @@ hdc_status hdc_level_id_encode(void *stream, const uint16_t *lev, int64_t n, int
     return from_hip(launch_level_id(lev, n, F, ldl, ID, ldid, LV, L, ldlv, D, H, ldh, (hipStream_t)stream));
 }
 
+// (kernel-side feature kind, compute type) of a tile-table bucket, false if
+// the pair has no kernels
+static bool tile_key(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int *xt, int *ct)
+{
+    *xt = xtype_of(x_type);
+    if (*xt < 0)
+        return false;
+    if (kind == HDC_KERNEL_SWEEP) {
+        *ct = C_I8;
+        return *xt != X_FP32;
+    }
+    if (kind != HDC_KERNEL_ENCODE && kind != HDC_KERNEL_CLASSIFY)
+        return false;
+    *ct = compute_of(x_type, compute);
+    return *ct >= 0;
+}
+
+int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
+                          int32_t *variants, int32_t cap)
+{
+    int xt, ct;
+    if (!tile_key(kind, x_type, compute, &xt, &ct) || F <= 0 || (cap > 0 && !variants))
+        return -1;
+    int v[8];
+    const int n = tile_variants((int)kind, xt, ct, F, kind == HDC_KERNEL_ENCODE ? 1 : K, v, 8);
+    for (int i = 0; i < n && i < cap; ++i)
+        variants[i] = v[i];
+    return n;
+}
+
+hdc_status hdc_set_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
+                        int32_t variant)
+{
+    int xt, ct;
+    const int32_t Kk = kind == HDC_KERNEL_ENCODE ? 1 : K;
+    if (!tile_key(kind, x_type, compute, &xt, &ct) || F <= 0 || get_tile((int)kind, xt, ct, F, Kk) < 0)
+        return HDC_ERR_INVALID;
+    return set_tile((int)kind, xt, ct, F, Kk, variant) ? HDC_OK : HDC_ERR_UNSUPPORTED;
+}
+
+int32_t hdc_get_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K)
+{
+    int xt, ct;
+    if (!tile_key(kind, x_type, compute, &xt, &ct) || F <= 0)
+        return -1;
+    return get_tile((int)kind, xt, ct, F, kind == HDC_KERNEL_ENCODE ? 1 : K);
+}
+
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
 {
     if (n_dims <= 0 || K <= 0 || K > kMaxK)
@@ -444,7 +493,8 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
     a.K = K;
     a.labels = labels;
     a.dists = dists;
-    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{0}, (hipStream_t)stream));
+    const int v = get_tile(KK_CLASSIFY, xt, ct, F, K);
+    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
 }
 
 hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,

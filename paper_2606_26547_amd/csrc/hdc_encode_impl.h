@@ -41,44 +41,43 @@ static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
 }
 
 // int8 features on the int8 path stage the projection straight into LDS.
-// Where the registers allow, each wave (one per SIMD) multiplies two query
-// tiles by two row tiles per chunk: four independent accumulator chains,
-// each projection fragment read from LDS feeds two MFMAs, and a barrier
-// every 80 MFMAs.  Otherwise one tile of each, two waves per SIMD.
-template <int KS, int KT> struct BigTile {
-    static constexpr bool value = KS <= 20 && KT <= 2;
-};
+// Where the registers allow (big_tile), each wave (one per SIMD) multiplies
+// two query tiles by two row tiles per chunk: four independent accumulator
+// chains, each projection fragment read from LDS feeds two MFMAs, and a
+// barrier every 80 MFMAs.  Otherwise (or when the tile table asks for it)
+// one tile of each, two waves per SIMD.
 template <int KS, int KT, int MODE>
-static hipError_t launch_dma(const EncodeArgs &a, hipStream_t st)
+static hipError_t launch_dma(const EncodeArgs &a, int variant, hipStream_t st)
 {
-    if constexpr (BigTile<KS, KT>::value)
-        return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 2>(a, st);
-    else
-        return launch_one<C_I8, 0, 1, KS, KT, MODE, true, 1>(a, st);
+    if constexpr (big_tile(KS, KT)) {
+        if (variant != TV_DMA_1X1)
+            return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 2>(a, st);
+    }
+    return launch_one<C_I8, 0, 1, KS, KT, MODE, true, 1>(a, st);
 }
 
-// Largest QT whose query registers fit comfortably beside the accumulators.
-template <int CT, int KS> struct QtMax {
-    static constexpr int value = ((CT == C_I8 && KS <= 16) || (CT == C_F32 && KS <= 64)) ? 2 : 1;
-};
-
+// One feature-width bucket: the tile variant picks direct or register
+// staging and the query tiles per wave; 0 is the built-in rule (direct
+// staging for int8 features on the int8 path, else as many query tiles as
+// fit).
 template <int CT, int XF, int KS>
 static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStream_t st)
 {
+    const int v = tile.variant;
     if constexpr (CT == C_I8 && XF == 0) {
-        if (a.x_type == X_INT8) {
+        if (a.x_type == X_INT8 && (v == TV_AUTO || v == TV_DMA_2X2 || v == TV_DMA_1X1)) {
             if (mode == M_ENCODE)
-                return launch_dma<KS, 1, M_ENCODE>(a, st);
+                return launch_dma<KS, 1, M_ENCODE>(a, v, st);
             const int kt = class_tiles(a.K);
             if (kt == 1)
-                return launch_dma<KS, 1, M_CLASSIFY>(a, st);
+                return launch_dma<KS, 1, M_CLASSIFY>(a, v, st);
             if (kt == 2)
-                return launch_dma<KS, 2, M_CLASSIFY>(a, st);
-            return launch_dma<KS, 4, M_CLASSIFY>(a, st);
+                return launch_dma<KS, 2, M_CLASSIFY>(a, v, st);
+            return launch_dma<KS, 4, M_CLASSIFY>(a, v, st);
         }
     }
-    constexpr int QM = QtMax<CT, KS>::value;
-    const int qt = (tile.qt == 1 || QM == 1) ? 1 : 2;
+    constexpr int QM = qt2_fits(CT, KS) ? 2 : 1;
+    const int qt = (v == TV_REG_QT1 || QM == 1) ? 1 : 2;
     if (mode == M_ENCODE) {
         if (qt == 2)
             return launch_one<CT, XF, QM, KS, 1, M_ENCODE>(a, st);

@@ -39,10 +39,12 @@ struct EncodeArgs {
 // Mode of the encode kernel.
 enum Mode : int { M_ENCODE = 0, M_CLASSIFY = 1 };
 
-// Kernel shape choice for one launch (queries per wave in 32-query tiles).
+// Kernel shape of one encode / classify launch (TileVariant; 0 = the
+// built-in rule).
 struct Tile {
-    int qt;                // 1 or 2
+    int variant;
 };
+
 
 constexpr int kDimChunk = 32;       // dimensions per MFMA row tile / LDS chunk
 constexpr int kWaves = 4;           // waves per workgroup of the encoder
@@ -65,6 +67,43 @@ inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
 constexpr int kMaxRT = 2;
 inline int64_t table_chunks(int nd) { return (chunks(nd) + kMaxRT - 1) / kMaxRT * kMaxRT; }
 inline size_t class_table_bytes(int nd, int K) { return (size_t)table_chunks(nd) * class_tiles(K) * 1024; }
+
+// Tile variants of the encoder: direct-to-LDS staging of the projection
+// with two query tiles x two row tiles per wave or one of each (int8
+// features on the int8 path), or register staging with one or two query
+// tiles per wave.
+enum TileVariant : int { TV_AUTO = 0, TV_DMA_2X2 = 1, TV_DMA_1X1 = 2, TV_REG_QT1 = 3, TV_REG_QT2 = 4 };
+// Tile variants of the configuration sweep: work items of 128 queries (one
+// query tile per wave) or of 256 (int8 slots with two query tiles per wave
+// where the registers allow, other slots in two passes).
+enum SweepVariant : int { SV_AUTO = 0, SV_ITEM128 = 1, SV_ITEM256 = 2 };
+enum KernelKind : int { KK_ENCODE = 0, KK_CLASSIFY = 1, KK_SWEEP = 2 };
+
+// Shape rules shared by the kernel templates and the variant listing.
+// Direct staging with 2x2 tiles fits the registers up to 20 K steps and two
+// class tiles.
+constexpr bool big_tile(int ks, int kt) { return ks <= 20 && kt <= 2; }
+// Two query tiles per wave fit beside the accumulators (register staging).
+constexpr bool qt2_fits(int ct, int ks) { return (ct == C_I8 && ks <= 16) || (ct == C_F32 && ks <= 64); }
+// K step (features per MFMA) of a compute type.
+constexpr int kstep_of(int ct) { return ct == C_I8 ? 32 : ct == C_FP8 ? 64 : ct == C_BF16 ? 16 : 2; }
+
+// Compiled feature widths of the encoder (integer features / fp32
+// features); a launch uses the smallest width >= F.
+constexpr int kIntWidths[] = {64, 128, 192, 256, 320, 384, 512, 640, 832, 1024};
+constexpr int kF32Widths[] = {64, 128, 256};
+// Compiled feature widths of the sweep.
+constexpr int kSweepWidths[] = {128, 256, 512, 640, 832, 1024};
+int width_index(int x_type, int F);          // -1 if F is beyond the compiled widths
+int sweep_width_index(int F);
+// Class tiles a launch is compiled for.
+inline int encoder_kt(int mode, int K) { return mode == M_ENCODE ? 1 : class_tiles(K); }
+inline int sweep_kt(int K) { return K <= 32 ? 1 : 4; }
+
+// Process-wide tile table (written by hdc_set_tile, read at every launch).
+int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap);
+int get_tile(int kind, int x_type, int ct, int F, int K);
+bool set_tile(int kind, int x_type, int ct, int F, int K, int variant);
 
 hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st);
 hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,

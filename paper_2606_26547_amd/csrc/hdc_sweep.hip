@@ -22,12 +22,10 @@ struct SlotDesc {
     int64_t cost;
 };
 
-constexpr int kSweepQT = 1;
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Class tiles compiled into the sweep kernel: 1 (K <= 32) or 4 (K <= 128).
-inline int sweep_kt(int K) { return K <= 32 ? 1 : 4; }
 inline size_t sweep_table_bytes(int D, int K) { return (size_t)chunks(D) * sweep_kt(K) * 1024; }
 
 struct SweepLayout {
@@ -144,18 +142,20 @@ __global__ __launch_bounds__(256) void k_sweep_popc(const uint64_t *__restrict__
         popc[k] = part[0];
 }
 
-template <int CT, int KS, int KT>
-__device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
+// One encoder pass of QT query tiles per wave over the queries from qblock,
+// adding the correct labels to the slot's count.
+template <int CT, int QT, int KS, int KT>
+__device__ __forceinline__ void sweep_pass(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
                                            hdc_config_result *res)
 {
-    typedef Encoder<CT, 0, kSweepQT, KS, KT, M_CLASSIFY, 1> E;
-    v16i dacc[KT][kSweepQT];
+    typedef Encoder<CT, 0, QT, KS, KT, M_CLASSIFY, 1> E;
+    v16i dacc[KT][QT];
     E::run(a, smem, qblock, dacc);
-    int32_t lab[kSweepQT];
+    int32_t lab[QT];
     E::finish(a, qblock, dacc, lab);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int qt = 0; qt < kSweepQT; ++qt) {
+    for (int qt = 0; qt < QT; ++qt) {
         const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
         const bool ok = lane < 32 && q < a.n && lab[qt] == truth[q];
         const uint64_t m = __ballot(ok);
@@ -164,16 +164,41 @@ __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *sme
     }
 }
 
-template <int FB, int KT>
-struct SweepLds {
-    static constexpr int a = Encoder<C_I8, 0, kSweepQT, FB / 32, KT, M_CLASSIFY, 1>::LDS;
-    static constexpr int b = Encoder<C_FP8, 0, kSweepQT, FB / 64, KT, M_CLASSIFY, 1>::LDS;
-    static constexpr int c = Encoder<C_BF16, 0, kSweepQT, FB / 16, KT, M_CLASSIFY, 1>::LDS;
-    static constexpr int ab = a > b ? a : b;
-    static constexpr int value = ab > c ? ab : c;
-};
+// Two int8 query tiles per wave fit the sweep's one wave per SIMD up to 20
+// K steps (640 features).
+constexpr bool sweep_qt2(int ct, int ks, int kt) { return ct == C_I8 && ks <= 20 && kt == 1; }
+
+// A work item of IQ * 128 queries: with IQ = 2, int8 slots take both query
+// tiles per wave in one pass where the registers allow (each projection
+// fragment staged once for 256 queries), other slots run two passes.
+template <int CT, int KS, int KT, int IQ>
+__device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
+                                                     hdc_config_result *res)
+{
+    if constexpr (IQ == 2 && sweep_qt2(CT, KS, KT)) {
+        sweep_pass<CT, 2, KS, KT>(a, smem, qblock, truth, res);
+    } else {
+#pragma unroll 1
+        for (int p = 0; p < IQ; ++p) {
+            if (p > 0)
+                __syncthreads();    // the previous pass's last LDS reads are done
+            sweep_pass<CT, 1, KS, KT>(a, smem, qblock + (int64_t)p * 32 * kWaves, truth, res);
+        }
+    }
+}
 
 template <int FB, int KT>
+struct SweepLds {
+    static constexpr int a = Encoder<C_I8, 0, 2, FB / 32, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int b = Encoder<C_FP8, 0, 1, FB / 64, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int c = Encoder<C_BF16, 0, 1, FB / 16, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int d = Encoder<C_I8, 0, 1, FB / 32, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int ab = a > b ? a : b;
+    static constexpr int cd = c > d ? c : d;
+    static constexpr int value = ab > cd ? ab : cd;
+};
+
+template <int FB, int KT, int IQ>
 __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *__restrict__ truth,
                                                uint8_t *__restrict__ ws, hdc_config_result *__restrict__ out,
                                                size_t off_desc, size_t off_order, size_t off_regions,
@@ -204,43 +229,49 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         a.nd = s.nd;
         a.ctab = (const int8_t *)(ws + off_regions + region * slot);
         a.cpop = (const int32_t *)(ws + off_regions + region * slot + table_bytes);
-        const int64_t qblock = (int64_t)tile * kSweepQT * 32 * kWaves;
+        const int64_t qblock = (int64_t)tile * IQ * 32 * kWaves;
         if (s.ct == C_I8)
-            sweep_item<C_I8, FB / 32, KT>(a, smem, qblock, truth, &out[slot]);
+            sweep_item<C_I8, FB / 32, KT, IQ>(a, smem, qblock, truth, &out[slot]);
         else if (s.ct == C_FP8)
-            sweep_item<C_FP8, FB / 64, KT>(a, smem, qblock, truth, &out[slot]);
+            sweep_item<C_FP8, FB / 64, KT, IQ>(a, smem, qblock, truth, &out[slot]);
         else
-            sweep_item<C_BF16, FB / 16, KT>(a, smem, qblock, truth, &out[slot]);
+            sweep_item<C_BF16, FB / 16, KT, IQ>(a, smem, qblock, truth, &out[slot]);
         if (threadIdx.x == 0)
             atomicAdd((unsigned long long *)&out[slot].ticks, (unsigned long long)(wall_clock64() - t0));
     }
 }
 
-template <int FB, int KT>
+template <int FB, int KT, int IQ>
 static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a, const SweepLayout &L,
-                                      size_t table_bytes, int tiles, hipStream_t st)
+                                      size_t table_bytes, hipStream_t st)
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<FB, KT>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<FB, KT, IQ>, 256, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     int grid = cus * per_cu;
     if (a.max_wg > 0 && a.max_wg < grid)
         grid = a.max_wg;
-    hipLaunchKernelGGL((k_sweep<FB, KT>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, a.out, L.off_desc,
+    const int tiles = (int)((a.n + IQ * 32 * kWaves - 1) / (IQ * 32 * kWaves));
+    hipLaunchKernelGGL((k_sweep<FB, KT, IQ>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, a.out, L.off_desc,
                        L.off_order, L.off_regions, L.region, table_bytes, a.ncfg, tiles);
     return hipGetLastError();
 }
 
+// Work-item size from the tile table (0: the built-in 128 queries).
 template <int FB>
 static hipError_t launch_sweep_fb(const EncodeArgs &base, const SweepArgs &a, const SweepLayout &L,
-                                  size_t table_bytes, int tiles, hipStream_t st)
+                                  size_t table_bytes, hipStream_t st)
 {
+    const bool big = get_tile(KK_SWEEP, a.x_type, C_I8, a.F, a.K) == SV_ITEM256;
     if (sweep_kt(a.K) == 1)
-        return launch_sweep_kernel<FB, 1>(base, a, L, table_bytes, tiles, st);
-    return launch_sweep_kernel<FB, 4>(base, a, L, table_bytes, tiles, st);
+        return big ? launch_sweep_kernel<FB, 1, 2>(base, a, L, table_bytes, st)
+                   : launch_sweep_kernel<FB, 1, 1>(base, a, L, table_bytes, st);
+    return big ? launch_sweep_kernel<FB, 4, 2>(base, a, L, table_bytes, st)
+               : launch_sweep_kernel<FB, 4, 1>(base, a, L, table_bytes, st);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
@@ -269,13 +300,12 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     base.P = a.P;
     base.ldp = a.ldp;
     base.K = a.K;
-    const int tiles = (int)((a.n + kSweepQT * 32 * kWaves - 1) / (kSweepQT * 32 * kWaves));
-    if (a.F <= 128) return launch_sweep_fb<128>(base, a, L, table_bytes, tiles, st);
-    if (a.F <= 256) return launch_sweep_fb<256>(base, a, L, table_bytes, tiles, st);
-    if (a.F <= 512) return launch_sweep_fb<512>(base, a, L, table_bytes, tiles, st);
-    if (a.F <= 640) return launch_sweep_fb<640>(base, a, L, table_bytes, tiles, st);
-    if (a.F <= 832) return launch_sweep_fb<832>(base, a, L, table_bytes, tiles, st);
-    return launch_sweep_fb<1024>(base, a, L, table_bytes, tiles, st);
+    if (a.F <= 128) return launch_sweep_fb<128>(base, a, L, table_bytes, st);
+    if (a.F <= 256) return launch_sweep_fb<256>(base, a, L, table_bytes, st);
+    if (a.F <= 512) return launch_sweep_fb<512>(base, a, L, table_bytes, st);
+    if (a.F <= 640) return launch_sweep_fb<640>(base, a, L, table_bytes, st);
+    if (a.F <= 832) return launch_sweep_fb<832>(base, a, L, table_bytes, st);
+    return launch_sweep_fb<1024>(base, a, L, table_bytes, st);
 }
 
 }  // namespace hdc

@@ -38,7 +38,8 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
            "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax",
            "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared",
-           "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode"]
+           "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode",
+           "hdc_tile_variants", "hdc_set_tile", "hdc_get_tile"]
 
 
 class Dims(C.Structure):
@@ -94,6 +95,11 @@ _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int
 _lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
 _lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
 _lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
+_lib.hdc_tile_variants.restype = _i32
+_lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _p, _i32]
+_lib.hdc_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _i32]
+_lib.hdc_get_tile.restype = _i32
+_lib.hdc_get_tile.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32]
 _lib.hdc_feature_perforate.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, Dims, _p, _i64]
 _lib.hdc_level_quantize.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _i64]
 _lib.hdc_level_id_encode.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i64, _p, _i32, _i64, _i32, _p, _i64]
@@ -268,6 +274,29 @@ def level_id_encode(lev: torch.Tensor, ID: torch.Tensor, LV: torch.Tensor, D: in
     _check(_lib.hdc_level_id_encode(_stream(), _ptr(lev), n, F, lev.stride(0), _ptr(ID), ID.shape[1], _ptr(LV),
                                     LV.shape[0], LV.shape[1], D, _ptr(out), out.shape[1]), "hdc_level_id_encode")
     return out
+
+
+KERNEL = {"encode": 0, "classify": 1, "sweep": 2}
+TILE_NAMES = {"encode": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
+              "classify": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
+              "sweep": {1: "items_128", 2: "items_256"}}
+
+
+def tile_variants(kind: str, x_type: str, compute: str, F: int, K: int) -> list[int]:
+    """hdc_tile_variants: the variant ids of a bucket, the built-in one first."""
+    buf = (C.c_int32 * 8)()
+    n = _lib.hdc_tile_variants(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K, buf, 8)
+    if n < 0:
+        raise HDCError(1, "hdc_tile_variants")
+    return list(buf[:n])
+
+
+def set_tile(kind: str, x_type: str, compute: str, F: int, K: int, variant: int):
+    _check(_lib.hdc_set_tile(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K, variant), "hdc_set_tile")
+
+
+def get_tile(kind: str, x_type: str, compute: str, F: int, K: int) -> int:
+    return int(_lib.hdc_get_tile(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K))
 
 
 def cosine_workspace_bytes(start: int, end: int, stride: int, K: int) -> int:

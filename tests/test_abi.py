@@ -153,3 +153,41 @@ def test_f3_validation_without_device(lib):
     assert lib.hdc_level_id_encode(None, fake, 4, 10, 10, fake, 1, fake, 4, 2, 128, fake, 2) == 1      # ldid
     assert lib.hdc_level_id_encode(None, fake, 4, 10, 16, fake, 2, fake, 4, 2, 128, fake, 1) == 1      # ldh
     assert lib.hdc_level_id_encode(None, None, 0, 10, 10, fake, 2, fake, 4, 2, 128, None, 2) == 0      # n == 0
+
+
+def test_tile_table_without_device(lib):
+    """Variant lists follow the compiled shapes; set/get round-trip; invalid
+    shapes and variants are rejected; 0 restores the built-in choice."""
+    p, i32 = C.c_void_p, C.c_int32
+    lib.hdc_tile_variants.restype = i32
+    lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32, p, i32]
+    lib.hdc_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32, i32]
+    lib.hdc_get_tile.restype = i32
+    lib.hdc_get_tile.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32]
+    ENC, CLS, SWP = 0, 1, 2
+    INT8, UINT8, BF16, FP8, FP32 = 0, 1, 2, 3, 4
+
+    def variants(*a):
+        buf = (C.c_int32 * 8)()
+        n = lib.hdc_tile_variants(*a, buf, 8)
+        return None if n < 0 else list(buf[:n])
+    # 617 features -> 640-wide int8 kernels: 20 K steps, no two-tile register staging
+    assert variants(CLS, INT8, INT8, 617, 26) == [1, 2, 3]
+    assert variants(CLS, INT8, INT8, 617, 100) == [2, 3]          # four class tiles: one query tile
+    assert variants(CLS, UINT8, INT8, 512, 10) == [4, 3]          # uint8 features: register staging
+    assert variants(CLS, INT8, BF16, 617, 26) == [3]
+    assert variants(ENC, FP32, FP32, 64, 0) == [4, 3]
+    assert variants(SWP, INT8, INT8, 617, 26) == [1, 2]
+    assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
+    assert variants(CLS, INT8, INT8, 2000, 26) is None            # beyond the compiled widths
+    assert variants(SWP, FP32, FP32, 64, 2) is None
+    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 0
+    assert lib.hdc_set_tile(CLS, INT8, INT8, 600, 20, 2) == 0     # same bucket as (617, 26)
+    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 2
+    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 40) == 0        # two class tiles: another bucket
+    assert lib.hdc_set_tile(CLS, INT8, INT8, 617, 26, 4) == 2     # not compiled for this bucket
+    assert lib.hdc_set_tile(CLS, INT8, INT8, 2000, 26, 1) == 1
+    assert lib.hdc_set_tile(CLS, INT8, INT8, 617, 26, 0) == 0
+    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 0
+    assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 2) == 0 and lib.hdc_get_tile(SWP, UINT8, FP8, 640, 1) == 2
+    assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 0) == 0

@@ -611,7 +611,10 @@ def serving(args, dev, dg, hdc, tuner, torch):
               "budget_bytes": 16 << 30}
     for mode in ("plain", "tuned"):
         ex = serve.GpuExecutor(models)
-        ex.warm(job_cfgs)
+        tiles = ex.warm(job_cfgs, tune_tiles=(mode == "plain"))
+        if tiles:
+            report["tiles"] = {"%s F=%d K=%d D=%d" % (c.shape.kind, c.shape.F, c.shape.K, c.shape.D): c.chosen_name
+                               for c in tiles}
         srv = serve.Server(ex, budget=16 << 30)
         # a short untimed stream first (staging slots, allocator caches)
         for _, f in serve.open_loop(srv, srcs, 2000.0, 0.3, seed=99, tuned=(mode == "tuned"), job_cfgs=job_cfgs):

@@ -181,11 +181,26 @@ class GpuExecutor:
         for _ in range(slots):
             self.free.append(self._new_slot())
 
-    def warm(self, job_cfgs=None):
+    def warm(self, job_cfgs=None, tune_tiles: bool = False):
         """Run every kernel the server will use once (each model's plain and
         tuned classifier, and its configuration sweep when ``job_cfgs(m)``
-        is given), so that first-launch costs stay out of request latency."""
+        is given), so that first-launch costs stay out of request latency.
+        With ``tune_tiles`` the tile autotuner first picks the tiles of each
+        model's classifier (at a mid-size batch) and sweep buckets; the
+        choices are returned."""
         torch, hdc = self.torch, self.hdc
+        choices = []
+        if tune_tiles:
+            from . import autotune as AT
+            shapes, seen = [], set()
+            for i, m in enumerate(self.models):
+                for sh in [AT.Shape("classify", m.F, m.K, m.D, 2048)] + \
+                        ([AT.Shape("sweep", m.F, m.K, m.D, 512, cfgs=job_cfgs(i))] if job_cfgs else []):
+                    key = (sh.kind, sh.F, sh.K, sh.D)
+                    if key not in seen:
+                        seen.add(key)
+                        shapes.append(sh)
+            choices = AT.autotune(shapes, reps=3)
         for i, m in enumerate(self.models):
             X = torch.zeros((64, m.P.shape[1]), dtype=torch.int8, device=self.dev)
             m.plain(X, m.F, m.P)
@@ -195,6 +210,7 @@ class GpuExecutor:
                 hdc.eval_configs(X, m.F, y, m.P, m.D, m.C, job_cfgs(i), ws=m.sweep_ws,
                                  max_workgroups=self.job_workgroups)
         torch.cuda.synchronize()
+        return choices
 
     def _new_slot(self):
         torch = self.torch

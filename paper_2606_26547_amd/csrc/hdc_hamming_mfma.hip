@@ -3,31 +3,28 @@
 // With q'_d in {0,1} the query bit (1 = element -1) and c_d = +1 / -1 the
 // class element, the Hamming distance over S is
 //     dist = popc_S(c) + sum_{d in S} q'_d * c_d.
-// The sum runs as an int8 MFMA (rows = classes, columns = queries, K = 32
-// dimensions per instruction).  The query operand is built from the packed
-// words with one shift and four ANDs per dword: lanes of the first half
-// take bit planes 0-3 of every byte, lanes of the second half planes 4-7
-// (the dword shifted down by 4), so byte i of plane register pl is 2^pl
-// when its bit is set.  The class operand holds c_d * 2^(6-pl), so every
-// set query bit contributes exactly 64 * c_d and the accumulator is
-// 64 * sum q' c.  Dimensions outside S (perforated, or past the end) have
-// class byte 0, so query bits there contribute nothing and the queries need
-// no masking.  This costs ~0.2 VALU ops per dimension instead of the
-// popcount form's 2 per dimension per class, so large class counts stay
-// HBM-bound.
+// The sum runs as an FP4 (E2M1) MFMA with fp32 accumulation (rows =
+// classes, columns = queries, K = 64 dimensions = one query word per
+// instruction): the query operand holds 0.5 for a set bit and 0 otherwise,
+// the class operand 2.0 * c_d (0 outside S), so every product is exactly
+// +-1 or 0 and every partial sum is an integer far below 2^24: the fp32
+// accumulator is exact.  Lane half g takes dword g of the word; its register
+// r is (dword >> r) & 0x11111111, i.e. nibble j holds bit 4j + r, so one
+// shift and one AND per register build the operand.  Dimensions outside S
+// (perforated, or past the end) have class nibble 0, so query bits there
+// contribute nothing and the queries need no masking.
 //
 // Class operand table (built once per (classes, perforation) by
 // k_ham_table): for word w (counted from the even word w_lo at or below the
-// first word of S, padded with zero words to whole windows), half h (low /
-// high dword) and class tile kt, 64 lanes x 16 bytes where lane l, byte
-// b = 4*pl + i holds class kt*32 + l%32 at dimension 64w + 32h + 8i + p with
-// plane p = 4*(l/32) + pl.
+// first word of S, padded with zero words to whole windows) and class tile
+// kt, 64 lanes x 16 bytes where lane l, nibble j of dword r holds class
+// kt*32 + l%32 at dimension 64w + 32*(l/32) + 4j + r.
 //
 // Streaming: a workgroup (4 waves, one per SIMD) owns ROWS query rows and
 // walks the words in windows of W; the query words and the class operand of
 // a window go from global memory straight into an LDS ring of NST stages
 // (global_load_lds, 16 bytes per lane), NST - 1 windows ahead of the
-// window being multiplied, with one barrier per window; two workgroups
+// window being multiplied, with one barrier per window; several workgroups
 // share each CU.
 #include <limits.h>
 
@@ -48,7 +45,7 @@ template <int KT> struct HmShape {
     static constexpr int SWZ = U == 2 ? 3 : 2;         // row shift of the unit swizzle
     static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
     static constexpr int QB = ROWS * W * 8;            // query bytes per stage
-    static constexpr int TB = W * 2 * KT * 1024;       // class operand bytes per window
+    static constexpr int TB = W * KT * 1024;           // class operand bytes per window
     static constexpr int NST = 2;                      // LDS stages
     static constexpr int NQL = QB / 1024 / kWaves;     // query loads per wave per window
     static constexpr int NTL = TB / 1024 / kWaves;     // class loads per wave per window
@@ -65,7 +62,7 @@ struct HamLayout {
         w_hi = (end + 63) >> 6;
         nwin = (w_hi - w_lo + kHmWin - 1) / kHmWin;
         KT = class_tiles(K);
-        const size_t tab = (size_t)nwin * kHmWin * 2 * KT * 1024;
+        const size_t tab = (size_t)nwin * kHmWin * KT * 1024;
         off_popc = tab;
         total = off_popc + 128 * 4;
     }
@@ -82,37 +79,32 @@ __global__ __launch_bounds__(256) void k_ham_table(const uint64_t *__restrict__ 
         return;
     const int lane = (int)(idx & 63);
     const int kt = (int)((idx >> 6) % KT);
-    const int64_t wh = (idx >> 6) / KT;   // word * 2 + half
-    const int64_t w = w_lo + (wh >> 1);
-    const int h = (int)(wh & 1);
+    const int64_t w = w_lo + (idx >> 6) / KT;
     const int k = kt * 32 + (lane & 31), g = lane >> 5;
     uint32_t o[4] = {0, 0, 0, 0};
     if (k < K) {
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            const int pl = b >> 2, i = b & 3, p = 4 * g + pl;
-            const int64_t d = w * 64 + 32 * h + 8 * i + p;
-            if (d >= start && d < end && (d - start) % stride == 0) {
-                const int bit = (int)((C[k * ldc + (d >> 6)] >> (d & 63)) & 1u);
-                const int c = bit ? -1 : 1;
-                const int v = c * (1 << (6 - pl));
-                o[pl] |= ((uint32_t)v & 0xffu) << (8 * i);
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t d = w * 64 + 32 * g + 4 * j + r;
+                if (d >= start && d < end && (d - start) % stride == 0) {
+                    const int bit = (int)((C[k * ldc + (d >> 6)] >> (d & 63)) & 1u);
+                    o[r] |= (bit ? 0xCu : 0x4u) << (4 * j);   // E2M1 -2.0 / +2.0
+                }
             }
-        }
     }
     *(uint4 *)(tab + idx * 16) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Bit planes of one query dword as the B operand of one MFMA; sh is 0 for
-// lanes of the first half and 4 for the second.
-__device__ __forceinline__ v4i planes(uint32_t d, uint32_t sh)
+// Query bits of one dword as the FP4 B operand (0.5 per set bit): register
+// r, nibble j = bit 4j + r.  The upper half of the operand is unused by FP4.
+__device__ __forceinline__ v8i query_nibbles(uint32_t d)
 {
-    const uint32_t e = d >> sh;
-    v4i b;
-    b[0] = (int)(e & 0x01010101u);
-    b[1] = (int)(e & 0x02020202u);
-    b[2] = (int)(e & 0x04040404u);
-    b[3] = (int)(e & 0x08080808u);
+    v8i b = {};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        b[r] = (int)((d >> r) & 0x11111111u);
     return b;
 }
 
@@ -136,7 +128,6 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
     __shared__ __align__(16) uint8_t smem[NST * S::SB];
     lds_u8 *L = (lds_u8 *)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
-    const uint32_t sh = 4u * (uint32_t)g;
     const int64_t rbase = (int64_t)blockIdx.x * ROWS;
     const uint64_t *Qwg = Q + rbase * ldq;   // this workgroup's rows
 
@@ -174,12 +165,12 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
     };
     constexpr int G = S::NQL + S::NTL;   // loads per wave per window
 
-    v16i acc[KT][QT];
+    v16f acc[KT][QT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt)
-            acc[kt][qt] = v16i{};
+            acc[kt][qt] = v16f{};
 
 #pragma unroll
     for (int v = 0; v < NST - 1; ++v)
@@ -202,20 +193,21 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
         }
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) {
+            v8i af[KT];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                v4i af[KT];
+            for (int kt = 0; kt < KT; ++kt) {
+                const v4i a4 = *(const lds_v4i *)(stb + ((ww * KT + kt) * 64 + lane) * 16);
+                af[kt] = v8i{a4[0], a4[1], a4[2], a4[3], 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt) {
+                const v4i u = qv[qt][ww >> 1];
+                const uint32_t d = (uint32_t)(g ? u[2 * (ww & 1) + 1] : u[2 * (ww & 1)]);
+                const v8i bf = query_nibbles(d);
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt)
-                    af[kt] = *(const lds_v4i *)(stb + (((ww * 2 + h) * KT + kt) * 64 + lane) * 16);
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) {
-                    const uint32_t d = (uint32_t)qv[qt][ww >> 1][2 * (ww & 1) + h];
-                    const v4i bf = planes(d, sh);
-#pragma unroll
-                    for (int kt = 0; kt < KT; ++kt)
-                        acc[kt][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[kt], bf, acc[kt][qt], 0, 0, 0);
-                }
+                    acc[kt][qt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[kt], bf, acc[kt][qt], 4, 4, 0,
+                                                                                 0, 0, 0);
             }
         }
         // window v+1 complete for this wave (only the window just issued may
@@ -237,7 +229,7 @@ __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict
             for (int v = 0; v < 16; ++v) {
                 const int k = kt * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
                 if (k < K) {
-                    const int d = popc[k] + (acc[kt][qt][v] >> 6);
+                    const int d = popc[k] + (int)acc[kt][qt][v];
                     if (d < bd) { bd = d; bk = k; }
                     if (dists && q < n)
                         dists[q * K + k] = d;
@@ -257,7 +249,7 @@ hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, 
                               hipStream_t st)
 {
     const HamLayout L(start, end, K);
-    const int64_t total = (int64_t)L.nwin * kHmWin * 2 * L.KT * 64;
+    const int64_t total = (int64_t)L.nwin * kHmWin * L.KT * 64;
     hipLaunchKernelGGL(k_ham_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc, start, end,
                        stride, L.w_lo, L.KT, total, (int8_t *)ws);
     hipError_t e = hipGetLastError();

@@ -66,10 +66,10 @@ def test_validation_without_device(lib):
     assert lib.hdc_classify_workspace_bytes(10240, 200) == 0
     lib.hdc_hamming_workspace_bytes.restype = C.c_size_t
     lib.hdc_hamming_workspace_bytes.argtypes = [Dims, i32]
-    assert lib.hdc_hamming_workspace_bytes(Dims(0, 10240, 1), 26) == 160 * 2 * 1024 + 512
+    assert lib.hdc_hamming_workspace_bytes(Dims(0, 10240, 1), 26) == 160 * 1024 + 512
     # words from the even word at or below start, whole windows of 4 words
-    assert lib.hdc_hamming_workspace_bytes(Dims(64, 4096, 2), 100) == 64 * 2 * 4 * 1024 + 512
-    assert lib.hdc_hamming_workspace_bytes(Dims(200, 1000, 1), 5) == 16 * 2 * 1024 + 512
+    assert lib.hdc_hamming_workspace_bytes(Dims(64, 4096, 2), 100) == 64 * 4 * 1024 + 512
+    assert lib.hdc_hamming_workspace_bytes(Dims(200, 1000, 1), 5) == 16 * 1024 + 512
     assert lib.hdc_hamming_workspace_bytes(Dims(0, 10240, 1), 129) == 0
     assert lib.hdc_hamming_workspace_bytes(Dims(0, 70000, 1), 26) == 0
     lib.hdc_bundle_workspace_bytes.restype = C.c_size_t

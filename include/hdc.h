@@ -269,6 +269,30 @@ hdc_status hdc_adc_argmax(void *stream,
                           int32_t *label, int32_t *max_score, int32_t *scores);
 
 /* ---------------------------------------------------------------------
+ * hdc_adc_prepare / hdc_adc_argmax_prepared -- the similarity of
+ * hdc_adc_argmax (same definition, same outputs bit for bit) split in two
+ * for resident class hypervectors: _prepare turns the classes and the
+ * perforation set S(perf) into a matrix-core operand and per-chunk counts
+ * in the workspace once; _argmax_prepared searches any number of query
+ * batches under any ADC setting against it.  `ws` must stay untouched
+ * between the calls; K and perf must be the same in both.
+ *   Q        [n][ldq] uint64 (>= perf.end valid bits), 16-byte aligned,
+ *            even ldq <= 2^20
+ *   ws       >= hdc_adc_workspace_bytes(perf, K) bytes, 16-byte aligned
+ * Supports K <= 128, perf.end <= 65536, and the ADC settings of
+ * hdc_adc_argmax.
+ * ------------------------------------------------------------------- */
+size_t hdc_adc_workspace_bytes(hdc_dims perf, int32_t K);
+hdc_status hdc_adc_prepare(void *stream,
+                           const uint64_t *C, int32_t K, int64_t ldc,
+                           hdc_dims perf, void *ws, size_t ws_bytes);
+hdc_status hdc_adc_argmax_prepared(void *stream,
+                                   const uint64_t *Q, int64_t n, int64_t ldq,
+                                   int32_t K, hdc_dims perf, hdc_adc adc,
+                                   int32_t *label, int32_t *max_score, int32_t *scores,
+                                   const void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------------
  * hdc_classify -- the fused inference path: encode each query over the
  * dimensions S(dims) under `compute`, compare bit j of the query with bit
  * S_j of each (full-D) class hypervector, argmin.  Equal, bit for bit, to

@@ -444,6 +444,51 @@ int32_t hdc_get_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32
     return get_tile((int)kind, xt, ct, F, kind == HDC_KERNEL_ENCODE ? 1 : K);
 }
 
+size_t hdc_adc_workspace_bytes(hdc_dims perf, int32_t K)
+{
+    if (check_perf(perf, K) != HDC_OK)
+        return 0;
+    return adc_workspace_bytes(perf.start, perf.end, K);
+}
+
+hdc_status hdc_adc_prepare(void *stream, const uint64_t *C, int32_t K, int64_t ldc, hdc_dims perf, void *ws,
+                           size_t ws_bytes)
+{
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (!C || ldc < (perf.end + 63) / 64)
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_adc_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    return from_hip(launch_adc_prepare(C, K, ldc, perf.start, perf.end, perf.stride, (uint8_t *)ws,
+                                       (hipStream_t)stream));
+}
+
+hdc_status hdc_adc_argmax_prepared(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, int32_t K,
+                                   hdc_dims perf, hdc_adc adc, int32_t *label, int32_t *max_score, int32_t *scores,
+                                   const void *ws, size_t ws_bytes)
+{
+    if (n < 0)
+        return HDC_ERR_INVALID;
+    const hdc_status s = check_perf(perf, K);
+    if (s != HDC_OK)
+        return s;
+    if (adc.res_bits < 1 || adc.res_bits > 16 || adc.step < 1 || adc.floor > adc.ceil)
+        return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_adc_workspace_bytes(perf, K) || !aligned(ws, 16))
+        return HDC_ERR_WORKSPACE;
+    if (n == 0)
+        return HDC_OK;
+    if (!Q || ldq < (perf.end + 63) / 64 || ldq % 2 || !aligned(Q, 16) || !label)
+        return HDC_ERR_INVALID;
+    if (ldq > kMaxPreparedLdq)
+        return HDC_ERR_UNSUPPORTED;
+    return from_hip(launch_adc_prepared(Q, n, ldq, K, perf.start, perf.end, adc.res_bits, adc.step, adc.floor,
+                                        adc.ceil, (const uint8_t *)ws, label, max_score, scores,
+                                        (hipStream_t)stream));
+}
+
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K)
 {
     if (n_dims <= 0 || K <= 0 || K > kMaxK)

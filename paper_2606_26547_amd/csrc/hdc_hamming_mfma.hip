@@ -15,7 +15,7 @@
 // contribute nothing and the queries need no masking.
 //
 // Class operand table (built once per (classes, perforation) by
-// k_ham_table): for word w (counted from the even word w_lo at or below the
+// k_sign_table with codes +-2.0): for word w (counted from the even word w_lo at or below the
 // first word of S, padded with zero words to whole windows) and class tile
 // kt, 64 lanes x 16 bytes where lane l, nibble j of dword r holds class
 // kt*32 + l%32 at dimension 64w + 32*(l/32) + 4j + r.
@@ -28,30 +28,9 @@
 // share each CU.
 #include <limits.h>
 
-#include "hdc_device.h"
+#include "hdc_stream.h"
 
 namespace hdc {
-
-// Shape per class-tile count: query tiles (32 queries) per wave, words per
-// window, LDS stages.
-// Two stages keep the LDS footprint small enough for two workgroups per
-// CU: the second wave on each SIMD covers the first one's plane-building
-// VALU work, LDS waits and barriers, which pays more than deeper prefetch.
-template <int KT> struct HmShape {
-    static constexpr int QT = KT == 4 ? 1 : 2;
-    static constexpr int W = KT == 1 ? 8 : 4;          // words per window (divides kHmWin)
-    static constexpr int U = W / 2;                    // 16-byte units per query row
-    static constexpr int RPL = 64 / U;                 // query rows per 1 KiB load
-    static constexpr int SWZ = U == 2 ? 3 : 2;         // row shift of the unit swizzle
-    static constexpr int ROWS = kWaves * QT * 32;      // queries per workgroup
-    static constexpr int QB = ROWS * W * 8;            // query bytes per stage
-    static constexpr int TB = W * KT * 1024;           // class operand bytes per window
-    static constexpr int NST = 2;                      // LDS stages
-    static constexpr int NQL = QB / 1024 / kWaves;     // query loads per wave per window
-    static constexpr int NTL = TB / 1024 / kWaves;     // class loads per wave per window
-    static constexpr int SB = QB + TB;                 // bytes per stage
-};
-constexpr int kHmWin = 8;   // the class operand is padded to whole 8-word windows
 
 struct HamLayout {
     int w_lo, w_hi, nwin, KT;
@@ -69,53 +48,6 @@ struct HamLayout {
 };
 
 size_t ham_workspace_bytes(int start, int end, int K) { return HamLayout(start, end, K).total; }
-
-__global__ __launch_bounds__(256) void k_ham_table(const uint64_t *__restrict__ C, int K, int64_t ldc, int start,
-                                                   int end, int stride, int w_lo, int KT, int64_t total,
-                                                   int8_t *__restrict__ tab)
-{
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= total)
-        return;
-    const int lane = (int)(idx & 63);
-    const int kt = (int)((idx >> 6) % KT);
-    const int64_t w = w_lo + (idx >> 6) / KT;
-    const int k = kt * 32 + (lane & 31), g = lane >> 5;
-    uint32_t o[4] = {0, 0, 0, 0};
-    if (k < K) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t d = w * 64 + 32 * g + 4 * j + r;
-                if (d >= start && d < end && (d - start) % stride == 0) {
-                    const int bit = (int)((C[k * ldc + (d >> 6)] >> (d & 63)) & 1u);
-                    o[r] |= (bit ? 0xCu : 0x4u) << (4 * j);   // E2M1 -2.0 / +2.0
-                }
-            }
-    }
-    *(uint4 *)(tab + idx * 16) = make_uint4(o[0], o[1], o[2], o[3]);
-}
-
-// Query bits of one dword as the FP4 B operand (0.5 per set bit): register
-// r, nibble j = bit 4j + r.  The upper half of the operand is unused by FP4.
-__device__ __forceinline__ v8i query_nibbles(uint32_t d)
-{
-    v8i b = {};
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        b[r] = (int)((d >> r) & 0x11111111u);
-    return b;
-}
-
-// Query row r of a stage is W words = U 16-byte units; unit hh of the
-// window sits in slot hh ^ ((r >> SWZ) & (U - 1)), which keeps the 16-byte
-// reads of 16 consecutive rows on distinct banks.
-template <int KT> __device__ __forceinline__ int hm_slot(int r, int hh)
-{
-    typedef HmShape<KT> S;
-    return hh ^ ((r >> S::SWZ) & (S::U - 1));
-}
 
 template <int KT>
 __global__ __launch_bounds__(256) void k_hamming_mfma(const uint64_t *__restrict__ Q, int64_t n, int64_t ldq, int K,
@@ -250,8 +182,9 @@ hipError_t launch_ham_prepare(const uint64_t *C, int K, int64_t ldc, int start, 
 {
     const HamLayout L(start, end, K);
     const int64_t total = (int64_t)L.nwin * kHmWin * L.KT * 64;
-    hipLaunchKernelGGL(k_ham_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K, ldc, start, end,
-                       stride, L.w_lo, L.KT, total, (int8_t *)ws);
+    // E2M1 +2.0 / -2.0
+    hipLaunchKernelGGL((k_sign_table<0x4u, 0xCu>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, C, K,
+                       ldc, start, end, stride, L.w_lo, L.KT, total, (int8_t *)ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -141,6 +141,12 @@ hipError_t launch_level_quantize(const float *X, int64_t n, int F, int64_t ldx, 
 hipError_t launch_level_id(const uint16_t *lev, int64_t n, int F, int64_t ldl, const uint64_t *ID, int64_t ldid,
                            const uint64_t *LV, int L, int64_t ldlv, int D, uint64_t *H, int64_t ldh,
                            hipStream_t st);
+size_t adc_workspace_bytes(int start, int end, int K);
+hipError_t launch_adc_prepare(const uint64_t *C, int K, int64_t ldc, int start, int end, int stride, uint8_t *ws,
+                              hipStream_t st);
+hipError_t launch_adc_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K, int start, int end, int res,
+                               int step, int floor_, int ceil_, const uint8_t *ws, int32_t *label,
+                               int32_t *max_score, int32_t *scores, hipStream_t st);
 hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t ldx, int compute,
                           float *out, hipStream_t st);
 

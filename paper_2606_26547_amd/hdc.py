@@ -39,7 +39,8 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax",
            "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared",
            "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode",
-           "hdc_tile_variants", "hdc_set_tile", "hdc_get_tile"]
+           "hdc_tile_variants", "hdc_set_tile", "hdc_get_tile",
+           "hdc_adc_workspace_bytes", "hdc_adc_prepare", "hdc_adc_argmax_prepared"]
 
 
 class Dims(C.Structure):
@@ -95,6 +96,10 @@ _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int
 _lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
 _lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
 _lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
+_lib.hdc_adc_workspace_bytes.restype = _sz
+_lib.hdc_adc_workspace_bytes.argtypes = [Dims, _i32]
+_lib.hdc_adc_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
+_lib.hdc_adc_argmax_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, Adc, _p, _p, _p, _p, _sz]
 _lib.hdc_tile_variants.restype = _i32
 _lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _p, _i32]
 _lib.hdc_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _i32]
@@ -297,6 +302,31 @@ def set_tile(kind: str, x_type: str, compute: str, F: int, K: int, variant: int)
 
 def get_tile(kind: str, x_type: str, compute: str, F: int, K: int) -> int:
     return int(_lib.hdc_get_tile(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K))
+
+
+class AdcPrepared:
+    """Class hypervectors of one (classes, perforation) as the matrix-core
+    operand of the ADC-chunked similarity; each call searches a batch of
+    query hypervectors under an ADC setting (hdc_adc_argmax_prepared)."""
+
+    def __init__(self, Cw: torch.Tensor, start: int, end: int, stride: int = 1):
+        self.K, self.perf = Cw.shape[0], Dims(start, end, stride)
+        need = int(_lib.hdc_adc_workspace_bytes(self.perf, self.K))
+        self.ws = torch.empty(max(need, 16), dtype=torch.uint8, device=Cw.device)
+        _check(_lib.hdc_adc_prepare(_stream(), _ptr(Cw), self.K, Cw.shape[1], self.perf, _ptr(self.ws),
+                                    self.ws.numel()), "hdc_adc_prepare")
+
+    def __call__(self, Q: torch.Tensor, adc, with_max=False, with_scores=False, out: torch.Tensor | None = None):
+        n = Q.shape[0]
+        if Q.shape[1] % 2:                      # the search wants an even row pitch
+            Q = torch.nn.functional.pad(Q, (0, 1))
+        lab = out if out is not None else torch.empty(n, dtype=torch.int32, device=Q.device)
+        mx = torch.empty(n, dtype=torch.int32, device=Q.device) if with_max else None
+        sc = torch.empty((n, self.K), dtype=torch.int32, device=Q.device) if with_scores else None
+        _check(_lib.hdc_adc_argmax_prepared(_stream(), _ptr(Q), n, Q.shape[1], self.K, self.perf, Adc(*adc),
+                                            _ptr(lab), _ptr(mx), _ptr(sc), _ptr(self.ws), self.ws.numel()),
+               "hdc_adc_argmax_prepared")
+        return lab, mx, sc
 
 
 def cosine_workspace_bytes(start: int, end: int, stride: int, K: int) -> int:

@@ -191,3 +191,26 @@ def test_tile_table_without_device(lib):
     assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 0
     assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 2) == 0 and lib.hdc_get_tile(SWP, UINT8, FP8, 640, 1) == 2
     assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 0) == 0
+
+
+def test_adc_prepared_validation_without_device(lib):
+    p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hdc_adc_workspace_bytes.restype = C.c_size_t
+    lib.hdc_adc_workspace_bytes.argtypes = [Dims, i32]
+    lib.hdc_adc_argmax_prepared.argtypes = [p, p, i64, i64, i32, Dims, Adc, p, p, p, p, C.c_size_t]
+    # class operand windows from the chunk-aligned word, then one int32 per chunk
+    assert lib.hdc_adc_workspace_bytes(Dims(0, 10240, 1), 26) == 20 * 8 * 1024 + 20 * 4 * 4
+    assert lib.hdc_adc_workspace_bytes(Dims(64, 4096, 2), 100) == 8 * 8 * 4 * 1024 + 8 * 4 * 4
+    assert lib.hdc_adc_workspace_bytes(Dims(200, 1000, 1), 5) == 2 * 8 * 1024 + 2 * 4 * 4
+    assert lib.hdc_adc_workspace_bytes(Dims(0, 10240, 1), 129) == 0
+    fake = C.c_void_p(1 << 20)
+    need = lib.hdc_adc_workspace_bytes(Dims(0, 128, 1), 3)
+    ok = Adc(8, 1, -127, 128)
+    assert lib.hdc_adc_argmax_prepared(None, fake, 4, 2, 3, Dims(0, 128, 1), Adc(8, 0, 0, 1), fake, None, None,
+                                       fake, need) == 1                                       # step < 1
+    assert lib.hdc_adc_argmax_prepared(None, fake, 4, 3, 3, Dims(0, 128, 1), ok, fake, None, None, fake,
+                                       need) == 1                                             # odd ldq
+    assert lib.hdc_adc_argmax_prepared(None, fake, 4, 2, 3, Dims(0, 128, 1), ok, fake, None, None, fake,
+                                       need - 1) == 3                                         # small ws
+    assert lib.hdc_adc_argmax_prepared(None, None, 0, 2, 3, Dims(0, 128, 1), ok, None, None, None, fake,
+                                       need) == 0                                             # n == 0

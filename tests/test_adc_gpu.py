@@ -65,3 +65,48 @@ def test_adc_full_size_sampled(hdc):
     lref, mref = O.argmax(ref)
     assert np.array_equal(lab[r].cpu().numpy(), lref)
     assert np.array_equal(mx[r].cpu().numpy(), mref)
+
+
+@pytest.mark.parametrize("case", CASES, ids=str)
+def test_adc_prepared_bit_exact(hdc, case):
+    """The matrix-core form against the oracle, and against the one-call
+    form, on the same cases."""
+    n, nbits, K, (s, e, k), adc = case
+    print("[case] adc prepared", case, flush=True)
+    g = np.random.default_rng(n + nbits + K)
+    W = (nbits + 63) // 64
+    Q = g.integers(0, 2 ** 63, size=(n, W), dtype=np.int64).view(np.uint64)
+    Cw = g.integers(0, 2 ** 63, size=(K, W), dtype=np.int64).view(np.uint64)
+    if K >= 3:
+        Cw[2] = Cw[0]
+    ref = O.adc_scores(Q, Cw, s, e, k, *adc)
+    lref, mref = O.argmax(ref)
+    P = hdc.AdcPrepared(torch.as_tensor(Cw.view(np.int64)).cuda(), s, e, k)
+    lab, mx, sc = P(torch.as_tensor(Q.view(np.int64)).cuda(), adc, True, True)
+    torch.cuda.synchronize()
+    assert np.array_equal(sc.cpu().numpy(), ref)
+    assert np.array_equal(lab.cpu().numpy(), lref)
+    assert np.array_equal(mx.cpu().numpy(), mref)
+
+
+def test_adc_prepared_full_size_and_settings(hdc):
+    """2^20 x 10240-bit queries, 26 classes, one prepared operand searched
+    under several ADC settings: labels and maxima equal the one-call form
+    everywhere and the oracle on sampled rows."""
+    print("[case] adc prepared 2^20 x 10240 x 26", flush=True)
+    n, D, K = 1 << 20, 10240, 26
+    g = torch.Generator(device="cuda").manual_seed(33)
+    Q = torch.randint(-(1 << 62), 1 << 62, (n, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    Cw = torch.randint(-(1 << 62), 1 << 62, (K, D // 64), dtype=torch.int64, device="cuda", generator=g)
+    P = hdc.AdcPrepared(Cw, 0, D, 1)
+    rows = np.sort(np.random.default_rng(33).choice(n, 1024, replace=False))
+    rows[-1] = n - 1
+    r = torch.as_tensor(rows).cuda()
+    for adc in [(8, 2, -3, 128), (8, 1, -127, 128), (4, 16, -127, 128)]:
+        lab, mx, _ = P(Q, adc, True)
+        lab1, mx1, _ = hdc.adc_argmax(Q, Cw, 0, D, 1, adc, True)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, lab1) and torch.equal(mx, mx1), adc
+        ref = O.adc_scores(Q[r].cpu().numpy().view(np.uint64), Cw.cpu().numpy().view(np.uint64), 0, D, 1, *adc)
+        lref, mref = O.argmax(ref)
+        assert np.array_equal(lab[r].cpu().numpy(), lref) and np.array_equal(mx[r].cpu().numpy(), mref), adc

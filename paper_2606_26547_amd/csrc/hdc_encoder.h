@@ -557,7 +557,7 @@ struct Encoder {
         const EncodeArgs &a;
         uint32_t off0[NIW];   // offset of load i in chunk 0
         int rp[NIW];          // row | piece byte offset << 8
-        uint32_t rstep, base, cbytes;
+        uint32_t rstep, base, cbytes, lastrow;
         int NC, lane, wave;
 
         __device__ __forceinline__ Loader(const EncodeArgs &a_, int NC_, int npc, int wave_, int lane_)
@@ -566,6 +566,7 @@ struct Encoder {
             rstep = (uint32_t)a.stride * (uint32_t)a.ldp;
             base = (uint32_t)a.s0 * (uint32_t)a.ldp;
             cbytes = (uint32_t)CH * rstep;
+            lastrow = base + (uint32_t)(a.nd - 1) * rstep;   // row of the last dimension
 #pragma unroll
             for (int i = 0; i < NIW; ++i) {
                 const int u = (i * kWaves + wave) * 64 + lane;
@@ -582,20 +583,18 @@ struct Encoder {
         // Load i (< NIW + NCW) of chunk c, clamped to the last chunk: the
         // projection rows, then the class fragments (wave w loads class tiles
         // (w + 4j) % NCT; duplicate tiles write the same bytes).  In the
-        // chunk holding the last dimension, rows past it re-read that row.
-        // The class table holds a whole number of chunks (zero rows past nd).
+        // chunk holding the last dimension, rows past it re-read that row
+        // (a select, not a branch: branches here would split the MFMA
+        // sequence the loads are interleaved with into separate scheduling
+        // regions).  The class table holds a whole number of chunks (zero
+        // rows past nd).
         __device__ __forceinline__ void issue(int i, int c, lds_u8 *stage, lds_u8 *lcls) const
         {
             const int cc = c < NC ? c : NC - 1;
             if (i < NIW) {
-                uint32_t off;
-                if ((cc + 1) * CH <= a.nd) {
-                    off = off0[i] + (uint32_t)cc * cbytes;
-                } else {
-                    const int last = a.nd - 1 - cc * CH;
-                    const int r = (rp[i] & 255) < last ? (rp[i] & 255) : last;
-                    off = base + (uint32_t)(cc * CH + r) * rstep + (uint32_t)(rp[i] >> 8);
-                }
+                const int last = a.nd - 1 - cc * CH;      // >= CH - 1 except in the last chunk
+                const uint32_t off = (rp[i] & 255) <= last ? off0[i] + (uint32_t)cc * cbytes
+                                                            : lastrow + (uint32_t)(rp[i] >> 8);
                 lds_dma16(a.P, off, stage + (i * kWaves + wave) * 1024);
             } else if constexpr (MODE == M_CLASSIFY) {
                 const int tile = (wave + kWaves * (i - NIW)) % NCT;   // rt * KT + kt

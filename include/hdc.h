@@ -394,9 +394,12 @@ hdc_status hdc_eval_configs(void *stream,
  *             dimension tiles per wave, or one of each; int8 features on the
  *             int8 path), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
  *             staging, two or one query tiles of 32 per wave);
- *             sweep: HDC_TILE_SWEEP_128 (work items of 128 queries) and
+ *             sweep: HDC_TILE_SWEEP_128 (work items of 128 queries),
  *             HDC_TILE_SWEEP_256 (items of 256: int8 slots take two query
- *             tiles per wave where the registers allow)
+ *             tiles per wave where the registers allow) and
+ *             HDC_TILE_SWEEP_256_DMA (items of 256, int8-feature int8 slots
+ *             on the classifier's HDC_TILE_DMA_2X2 body; int8 features,
+ *             K <= 32, F <= 640)
  * hdc_tile_variants writes up to `cap` (host array) variant ids the bucket
  * is compiled with, the built-in choice first, and returns how many there
  * are, or -1 for a shape outside the compiled kernels.  hdc_set_tile sets
@@ -418,7 +421,8 @@ enum {
     HDC_TILE_REG_QT1 = 3,
     HDC_TILE_REG_QT2 = 4,
     HDC_TILE_SWEEP_128 = 1,
-    HDC_TILE_SWEEP_256 = 2
+    HDC_TILE_SWEEP_256 = 2,
+    HDC_TILE_SWEEP_256_DMA = 3
 };
 
 int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,

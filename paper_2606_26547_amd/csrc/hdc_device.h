@@ -30,14 +30,23 @@ __device__ __forceinline__ void lds_st16(lds_u8 *p, uint4 v)
 }
 
 // Direct global -> LDS load of 16 bytes per lane: lane l's bytes at
-// base + voff land at LDS address dst + 16 * l (dst is wave-uniform).
-// Issued as inline assembly: the compiler then keeps counting only its own
-// LDS reads (it would otherwise drain every LDS read before each MFMA), and
-// the caller waits for these loads explicitly (vmcnt).
+// base + voff land at LDS address dst + 16 * l (base and dst are
+// wave-uniform; they are read from the first lane, which keeps them in
+// scalar registers also where the compiler cannot prove it, e.g. in a
+// function that is not inlined).  Issued as inline assembly: the compiler
+// then keeps counting only its own LDS reads (it would otherwise drain
+// every LDS read before each MFMA), and the caller waits for these loads
+// explicitly (vmcnt).
 __device__ __forceinline__ void lds_dma16(const void *base, uint32_t voff, const lds_u8 *dst)
 {
     const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(m), "v"(voff), "s"(base)
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    // the builtin returns int: widen each half through uint32_t (a sign
+    // extension of the low half would corrupt the high one)
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint64_t bs = ((uint64_t)hi << 32) | (uint64_t)lo;
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(m), "v"(voff), "s"(bs)
                  : "memory", "m0");
 }
 

@@ -26,7 +26,9 @@ struct SlotDesc {
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Class tiles compiled into the sweep kernel: 1 (K <= 32) or 4 (K <= 128).
-inline size_t sweep_table_bytes(int D, int K) { return (size_t)chunks(D) * sweep_kt(K) * 1024; }
+// A slot's table holds whole pairs of 32-dimension chunks (the direct-staged
+// 2x2 body reads them in pairs; the pad chunk is zero).
+inline size_t sweep_table_bytes(int D, int K) { return (size_t)table_chunks(D) * sweep_kt(K) * 1024; }
 
 struct SweepLayout {
     size_t off_desc, off_order, off_regions, region, total;
@@ -94,7 +96,8 @@ __global__ __launch_bounds__(256) void k_sweep_tables(const uint64_t *__restrict
     const int slot = blockIdx.y;
     const SlotDesc s = ((const SlotDesc *)(ws + off_desc))[slot];
     int8_t *tab = (int8_t *)(ws + off_regions + region * slot);
-    const int64_t total = (int64_t)((s.nd + kDimChunk - 1) / kDimChunk) * KT * 64;
+    // whole pairs of chunks; chunks past nd are written as zeros
+    const int64_t total = (int64_t)((s.nd + 2 * kDimChunk - 1) / (2 * kDimChunk)) * 2 * KT * 64;
     for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total && idx < per_slot;
          idx += (int64_t)gridDim.x * 256) {
         const int lane = (int)(idx & 63);
@@ -168,18 +171,48 @@ __device__ __forceinline__ void sweep_pass(EncodeArgs &a, uint8_t *smem, int64_t
 // K steps (640 features).
 constexpr bool sweep_qt2(int ct, int ks, int kt) { return ct == C_I8 && ks <= 20 && kt == 1; }
 
-// A work item of IQ * 128 queries: with IQ = 2, int8 slots take both query
-// tiles per wave in one pass where the registers allow (each projection
-// fragment staged once for 256 queries), other slots run two passes.
+// The fused classifier's direct-staged 2x2 body on one 256-query item
+// (int8 features on the int8 path).
+template <int KS, int KT>
+__device__ __forceinline__ void sweep_pass_dma(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
+                                               hdc_config_result *res)
+{
+    typedef Encoder<C_I8, 0, 2, KS, KT, M_CLASSIFY, 1, true, 2> E;
+    v16i dacc[KT][2];
+    E::run(a, smem, qblock, dacc);
+    int32_t lab[2];
+    E::finish(a, qblock, dacc, lab);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+        const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
+        const bool ok = lane < 32 && q < a.n && lab[qt] == truth[q];
+        const uint64_t m = __ballot(ok);
+        if (lane == 0 && m)
+            atomicAdd(&res->correct, (int)__popcll(m));
+    }
+}
+
+// A work item of 128 queries (IQ = 1) or 256 (IQ = 2, 3).  With IQ = 2,
+// int8 slots take both query tiles per wave in one pass where the registers
+// allow (each projection fragment staged once for 256 queries), other slots
+// run two passes; IQ = 3 runs int8-feature int8 slots on the direct-staged
+// 2x2 body instead (where it is compiled), the rest as IQ = 2.
 template <int CT, int KS, int KT, int IQ>
 __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
                                                      hdc_config_result *res)
 {
-    if constexpr (IQ == 2 && sweep_qt2(CT, KS, KT)) {
+    if constexpr (IQ == 3 && CT == C_I8 && big_tile(KS, KT)) {
+        if (a.x_type == X_INT8) {
+            sweep_pass_dma<KS, KT>(a, smem, qblock, truth, res);
+            return;
+        }
+    }
+    if constexpr (IQ >= 2 && sweep_qt2(CT, KS, KT)) {
         sweep_pass<CT, 2, KS, KT>(a, smem, qblock, truth, res);
     } else {
 #pragma unroll 1
-        for (int p = 0; p < IQ; ++p) {
+        for (int p = 0; p < (IQ == 1 ? 1 : 2); ++p) {
             if (p > 0)
                 __syncthreads();    // the previous pass's last LDS reads are done
             sweep_pass<CT, 1, KS, KT>(a, smem, qblock + (int64_t)p * 32 * kWaves, truth, res);
@@ -187,15 +220,18 @@ __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *sme
     }
 }
 
-template <int FB, int KT>
+template <int FB, int KT, int IQ>
 struct SweepLds {
     static constexpr int a = Encoder<C_I8, 0, 2, FB / 32, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int b = Encoder<C_FP8, 0, 1, FB / 64, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int c = Encoder<C_BF16, 0, 1, FB / 16, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int d = Encoder<C_I8, 0, 1, FB / 32, KT, M_CLASSIFY, 1>::LDS;
+    static constexpr int e = (IQ == 3 && big_tile(FB / 32, KT))
+                                 ? Encoder<C_I8, 0, 2, FB / 32, KT, M_CLASSIFY, 1, true, 2>::LDS : 0;
     static constexpr int ab = a > b ? a : b;
     static constexpr int cd = c > d ? c : d;
-    static constexpr int value = ab > cd ? ab : cd;
+    static constexpr int abcd = ab > cd ? ab : cd;
+    static constexpr int value = abcd > e ? abcd : e;
 };
 
 template <int FB, int KT, int IQ>
@@ -204,7 +240,7 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
                                                size_t off_desc, size_t off_order, size_t off_regions,
                                                size_t region, size_t table_bytes, int ncfg, int tiles)
 {
-    __shared__ __align__(16) uint8_t smem[SweepLds<FB, KT>::value];
+    __shared__ __align__(16) uint8_t smem[SweepLds<FB, KT, IQ>::value];
     __shared__ int item_s;
     const SlotDesc *desc = (const SlotDesc *)(ws + off_desc);
     const int32_t *order = (const int32_t *)(ws + off_order);
@@ -229,7 +265,7 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         a.nd = s.nd;
         a.ctab = (const int8_t *)(ws + off_regions + region * slot);
         a.cpop = (const int32_t *)(ws + off_regions + region * slot + table_bytes);
-        const int64_t qblock = (int64_t)tile * IQ * 32 * kWaves;
+        const int64_t qblock = (int64_t)tile * (IQ == 1 ? 1 : 2) * 32 * kWaves;
         if (s.ct == C_I8)
             sweep_item<C_I8, FB / 32, KT, IQ>(a, smem, qblock, truth, &out[slot]);
         else if (s.ct == C_FP8)
@@ -255,7 +291,8 @@ static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a
     int grid = cus * per_cu;
     if (a.max_wg > 0 && a.max_wg < grid)
         grid = a.max_wg;
-    const int tiles = (int)((a.n + IQ * 32 * kWaves - 1) / (IQ * 32 * kWaves));
+    constexpr int QI = (IQ == 1 ? 1 : 2) * 32 * kWaves;   // queries per item
+    const int tiles = (int)((a.n + QI - 1) / QI);
     hipLaunchKernelGGL((k_sweep<FB, KT, IQ>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, a.out, L.off_desc,
                        L.off_order, L.off_regions, L.region, table_bytes, a.ncfg, tiles);
     return hipGetLastError();
@@ -266,12 +303,17 @@ template <int FB>
 static hipError_t launch_sweep_fb(const EncodeArgs &base, const SweepArgs &a, const SweepLayout &L,
                                   size_t table_bytes, hipStream_t st)
 {
-    const bool big = get_tile(KK_SWEEP, a.x_type, C_I8, a.F, a.K) == SV_ITEM256;
-    if (sweep_kt(a.K) == 1)
-        return big ? launch_sweep_kernel<FB, 1, 2>(base, a, L, table_bytes, st)
-                   : launch_sweep_kernel<FB, 1, 1>(base, a, L, table_bytes, st);
-    return big ? launch_sweep_kernel<FB, 4, 2>(base, a, L, table_bytes, st)
-               : launch_sweep_kernel<FB, 4, 1>(base, a, L, table_bytes, st);
+    const int v = get_tile(KK_SWEEP, a.x_type, C_I8, a.F, a.K);
+    if (sweep_kt(a.K) == 1) {
+        if constexpr (big_tile(FB / 32, 1)) {
+            if (v == SV_ITEM256_DMA)
+                return launch_sweep_kernel<FB, 1, 3>(base, a, L, table_bytes, st);
+        }
+        return v == SV_ITEM256 ? launch_sweep_kernel<FB, 1, 2>(base, a, L, table_bytes, st)
+                               : launch_sweep_kernel<FB, 1, 1>(base, a, L, table_bytes, st);
+    }
+    return v == SV_ITEM256 ? launch_sweep_kernel<FB, 4, 2>(base, a, L, table_bytes, st)
+                           : launch_sweep_kernel<FB, 4, 1>(base, a, L, table_bytes, st);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
@@ -281,7 +323,7 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     const size_t table_bytes = sweep_table_bytes(a.D, a.K);
     hipLaunchKernelGGL(k_sweep_setup, dim3(1), dim3(1024), 0, st, a.cfgs, a.ncfg, a.D, a.n, a.ws, a.out,
                        L.off_desc, L.off_order);
-    const int64_t per_slot = chunks(a.D) * KT * 64;
+    const int64_t per_slot = table_chunks(a.D) * KT * 64;
     const unsigned gx = (unsigned)((per_slot + 255) / 256 < 1024 ? (per_slot + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_sweep_tables, dim3(gx, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L.off_desc,
                        L.off_regions, L.region, KT, per_slot);

@@ -97,6 +97,9 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
             return -1;
         v[n++] = SV_ITEM128;
         v[n++] = SV_ITEM256;
+        const int wi = sweep_width_index(F);
+        if (x_type == X_INT8 && sweep_kt(K) == 1 && big_tile(kSweepWidths[wi] / 32, 1))
+            v[n++] = SV_ITEM256_DMA;
     } else {
         if (!encoder_slot(kind, x_type, ct, F, K))
             return -1;

@@ -284,7 +284,7 @@ def level_id_encode(lev: torch.Tensor, ID: torch.Tensor, LV: torch.Tensor, D: in
 KERNEL = {"encode": 0, "classify": 1, "sweep": 2}
 TILE_NAMES = {"encode": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
               "classify": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
-              "sweep": {1: "items_128", 2: "items_256"}}
+              "sweep": {1: "items_128", 2: "items_256", 3: "items_256_dma"}}
 
 
 def tile_variants(kind: str, x_type: str, compute: str, F: int, K: int) -> list[int]:

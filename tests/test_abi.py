@@ -177,7 +177,10 @@ def test_tile_table_without_device(lib):
     assert variants(CLS, UINT8, INT8, 512, 10) == [4, 3]          # uint8 features: register staging
     assert variants(CLS, INT8, BF16, 617, 26) == [3]
     assert variants(ENC, FP32, FP32, 64, 0) == [4, 3]
-    assert variants(SWP, INT8, INT8, 617, 26) == [1, 2]
+    assert variants(SWP, INT8, INT8, 617, 26) == [1, 2, 3]
+    assert variants(SWP, UINT8, INT8, 617, 26) == [1, 2]          # direct staging needs int8 features
+    assert variants(SWP, INT8, INT8, 617, 100) == [1, 2]          # and one class tile
+    assert variants(SWP, INT8, INT8, 784, 10) == [1, 2]           # and F <= 640
     assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
     assert variants(CLS, INT8, INT8, 2000, 26) is None            # beyond the compiled widths
     assert variants(SWP, FP32, FP32, 64, 2) is None

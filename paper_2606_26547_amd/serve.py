@@ -237,6 +237,17 @@ class GpuExecutor:
         if r0.kind == "configs" and len(r0.cfgs) > MAX_JOB_CONFIGS:
             raise ValueError("configuration job of %d configurations exceeds %d" % (len(r0.cfgs), MAX_JOB_CONFIGS))
         slot = self.free.popleft() if self.free else self._new_slot()
+        try:
+            self._enqueue(b, m, slot)
+        except BaseException:
+            # nothing of this batch reached the device queue in a state
+            # that still uses the slot: hand it back before failing
+            self.free.append(slot)
+            raise
+
+    def _enqueue(self, b: Batch, m, slot):
+        torch, hdc = self.torch, self.hdc
+        r0 = b.requests[0]
         ld = m.P.shape[1]
         hxt = slot["hx"][:b.n * ld].view(b.n, ld)
         hx = hxt.numpy()
@@ -271,16 +282,30 @@ class GpuExecutor:
     def ready(self, b: Batch) -> bool:
         return b.handle[1]["ev"].query()
 
+    def release(self, b: Batch):
+        """Return a launched batch's slot after its work failed (the slot is
+        reused only once its event has completed)."""
+        if b.handle is not None:
+            slot = b.handle[1]
+            try:
+                slot["ev"].synchronize()
+            finally:
+                self.free.append(slot)
+            b.handle = None
+
     def results(self, b: Batch):
         h = b.handle
         slot = h[1]
         slot["ev"].synchronize()
-        if h[0] == "configs":
-            out = [slot["hc"].numpy()[:h[2]].copy()]
-        else:
-            res = slot["hl"].numpy()
-            out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
-        self.free.append(slot)
+        try:
+            if h[0] == "configs":
+                out = [slot["hc"].numpy()[:h[2]].copy()]
+            else:
+                res = slot["hl"].numpy()
+                out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
+        finally:
+            b.handle = None
+            self.free.append(slot)
         return out
 
 
@@ -341,12 +366,34 @@ class Server:
         self.thread = threading.Thread(target=self._loop, daemon=True)
         self.thread.start()
 
+    def validate(self, r: Request):
+        """Reject a malformed request before it is admitted: queries must be
+        an [n][F] int8 array of the model's feature width, and a
+        configuration job needs one true label per query."""
+        models = self.ex.models
+        if not 0 <= r.model < len(models):
+            raise AdmissionError("model %d does not exist" % r.model)
+        F = models[r.model].F
+        X = r.X
+        if not isinstance(X, np.ndarray) or X.dtype != np.int8 or X.ndim != 2 or X.shape[1] != F:
+            raise AdmissionError("queries must be an int8 array of shape [n][%d]" % F)
+        if X.shape[0] < 1:
+            raise AdmissionError("a request needs at least one query")
+        if r.kind == "configs":
+            if not r.cfgs or len(r.cfgs) > MAX_JOB_CONFIGS:
+                raise AdmissionError("a configuration job needs 1..%d configurations" % MAX_JOB_CONFIGS)
+            if r.truth is None or np.asarray(r.truth).shape != (X.shape[0],):
+                raise AdmissionError("a configuration job needs one true label per query")
+        elif r.kind != "infer":
+            raise AdmissionError("unknown request kind %r" % r.kind)
+
     def submit(self, r: Request) -> Future:
         with self.lock:
             r.t_arrival = r.t_arrival or time.perf_counter()
             r.rid = self.next_id
             self.next_id += 1
             try:
+                self.validate(r)
                 self.sched.submit(r)
             except AdmissionError as e:
                 r.future.set_exception(e)
@@ -370,16 +417,28 @@ class Server:
                         self.sched.done(b)
             still = []
             for b in self.running:
-                if self.ex.ready(b):
+                try:
+                    if not self.ex.ready(b):
+                        still.append(b)
+                        continue
                     res = self.ex.results(b)
-                    now = time.perf_counter()
+                except Exception as e:   # a failed batch fails its own requests only
+                    try:
+                        self.ex.release(b)
+                    except Exception:
+                        pass
                     with self.lock:
                         self.sched.done(b)
-                    for r, v in zip(b.requests, res):
-                        self.completed.append((r.rid, r.kind, r.model, r.n, now - r.t_arrival))
-                        r.future.set_result(v)
-                else:
-                    still.append(b)
+                    for r in b.requests:
+                        if not r.future.done():
+                            r.future.set_exception(e)
+                    continue
+                now = time.perf_counter()
+                with self.lock:
+                    self.sched.done(b)
+                for r, v in zip(b.requests, res):
+                    self.completed.append((r.rid, r.kind, r.model, r.n, now - r.t_arrival))
+                    r.future.set_result(v)
             self.running = still
             if not batches and still:
                 time.sleep(self.poll_s)

@@ -3,6 +3,7 @@ batching and result routing, driven by a fake executor with scripted
 latencies (no GPU)."""
 import threading
 import time
+from types import SimpleNamespace
 
 import numpy as np
 import pytest
@@ -14,7 +15,10 @@ class FakeExecutor:
     """Completes a batch `latency(batch)` seconds after launch; the 'labels'
     of a query are a deterministic function of its features."""
 
-    def __init__(self, latency=lambda b: 0.002, fail_model=None):
+    def __init__(self, latency=lambda b: 0.002, fail_model=None, fail_results_model=None):
+        self.models = [SimpleNamespace(F=16) for _ in range(3)]
+        self.fail_results_model = fail_results_model
+        self.released = 0
         self.latency = latency
         self.launched = []
         self.fail_model = fail_model
@@ -34,9 +38,14 @@ class FakeExecutor:
     def ready(self, b):
         return time.perf_counter() >= b.handle
 
+    def release(self, b):
+        self.released += 1
+
     def results(self, b):
         with self.lock:
             self.concurrent -= 1
+        if self.fail_results_model is not None and b.requests[0].model == self.fail_results_model:
+            raise RuntimeError("device error")
         if b.requests[0].kind == "configs":
             return [np.array([len(b.requests[0].cfgs)])]
         return [r.X.astype(np.int64).sum(1) % 7 for r in b.requests]
@@ -121,6 +130,38 @@ def test_config_jobs_run_alone_and_failures_are_isolated():
         bad.result(timeout=5)
     srv.close()
     assert all(len(b.requests) == 1 for b in ex.launched if b.requests[0].kind == "configs")
+
+
+def test_malformed_requests_are_rejected_at_submit():
+    ex = FakeExecutor()
+    srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n)
+    bad = [Request(model=0, X=np.zeros((4, 15), np.int8)),                      # wrong width
+           Request(model=0, X=np.zeros((4, 16), np.float32)),                   # wrong dtype
+           Request(model=7, X=np.zeros((4, 16), np.int8)),                      # no such model
+           Request(model=0, X=np.zeros((0, 16), np.int8)),                      # empty
+           Request(model=1, X=np.zeros((5, 16), np.int8), kind="configs",
+                   cfgs=[(1024, 1, 0, "int8")], truth=np.zeros(4)),             # truth length
+           Request(model=1, X=np.zeros((5, 16), np.int8), kind="configs", cfgs=[], truth=np.zeros(5))]
+    futs = [srv.submit(r) for r in bad]
+    for f in futs:
+        with pytest.raises(AdmissionError):
+            f.result(timeout=5)
+    good = srv.submit(req(0, 8))
+    assert good.result(timeout=5).shape == (8,)
+    srv.close()
+    assert len(ex.launched) == 1 and srv.sched.used == 0
+
+
+def test_failed_completion_fails_its_requests_and_the_loop_goes_on():
+    ex = FakeExecutor(fail_results_model=1)
+    srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n)
+    bad = srv.submit(req(1, 8))
+    with pytest.raises(RuntimeError):
+        bad.result(timeout=5)
+    good = srv.submit(req(0, 8))                        # the loop thread is still alive
+    assert good.result(timeout=5).shape == (8,)
+    srv.close()
+    assert ex.released == 1 and srv.sched.used == 0
 
 
 def test_tight_budget_still_completes_everything():

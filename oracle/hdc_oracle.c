@@ -66,6 +66,16 @@ double or_round_e4m3(double v)
     return round_to_format(v, 4, -6, 448.0, 1);
 }
 
+/* FP8_SPLIT: x = h + l with h = 16 * floor(x / 16) and l = x - h, each
+ * part rounded to E4M3 on its own, then added back. */
+static double split_e4m3(double x)
+{
+    assert(x == floor(x) && x >= -128.0 && x <= 255.0);
+    double h = 16.0 * floor(x / 16.0);
+    double l = x - h;
+    return or_round_e4m3(h) + or_round_e4m3(l);
+}
+
 static double raw_feature(const void *X, int x_type, int64_t ldx, int64_t i, int32_t f)
 {
     switch (x_type) {
@@ -83,6 +93,8 @@ double or_feature(const void *X, int x_type, int64_t ldx, int64_t i, int32_t f, 
         return or_round_bf16(v);
     if (compute == OR_FP8_E4M3)
         return or_round_e4m3(v);
+    if (compute == OR_FP8_SPLIT)
+        return split_e4m3(v);
     return v;
 }
 
@@ -139,13 +151,45 @@ static int xacc_sign(xacc *a)
     return 0;
 }
 
+/* The exact sum rounded once to the nearest double (ties to even): the
+ * magnitude's top 96 bits plus a sticky bit for everything below them. */
 static double xacc_value(xacc *a)
 {
-    xacc_normalize(a);
-    double s = 0.0;
-    for (int j = XDIG - 1; j >= 0; j--)
-        s += ldexp((double)a->dig[j], 32 * j - 149);
-    return s;
+    xacc m = *a;
+    xacc_normalize(&m);
+    int neg = m.dig[XDIG - 1] < 0;
+    if (neg) {
+        for (int j = 0; j < XDIG; j++)
+            m.dig[j] = -m.dig[j];
+        xacc_normalize(&m);
+    }
+    int t = XDIG - 1;
+    while (t >= 0 && m.dig[t] == 0)
+        t--;
+    if (t < 0)
+        return 0.0;
+    assert(m.dig[t] > 0 && m.dig[t] < 4294967296LL);
+    unsigned __int128 v = 0;
+    for (int j = t; j >= t - 2; j--)
+        v = (v << 32) | (unsigned __int128)(j >= 0 ? (uint64_t)m.dig[j] : 0);
+    int sticky = 0;
+    for (int j = t - 3; j >= 0; j--)
+        sticky |= m.dig[j] != 0;
+    int e0 = 32 * (t - 2) - 149;            /* exponent of bit 0 of v */
+    int nb = 0;
+    for (unsigned __int128 u = v; u; u >>= 1)
+        nb++;
+    if (nb > 53) {
+        int sh = nb - 53;
+        unsigned __int128 rem = v & (((unsigned __int128)1 << sh) - 1);
+        unsigned __int128 half = (unsigned __int128)1 << (sh - 1);
+        v >>= sh;
+        e0 += sh;
+        if (rem > half || (rem == half && (sticky || (v & 1))))
+            v++;
+    }
+    double r = ldexp((double)(uint64_t)v, e0);
+    return neg ? -r : r;
 }
 
 /* Integer features under an element type map to integer values (bfloat16
@@ -158,7 +202,8 @@ static int int_feature_table(int x_type, int compute, int32_t tab[256])
     for (int b = 0; b < 256; b++) {
         double raw = x_type == OR_INT8 ? (double)(int8_t)b : (double)b;
         double v = compute == OR_BF16 ? or_round_bf16(raw)
-                 : compute == OR_FP8_E4M3 ? or_round_e4m3(raw) : raw;
+                 : compute == OR_FP8_E4M3 ? or_round_e4m3(raw)
+                 : compute == OR_FP8_SPLIT ? split_e4m3(raw) : raw;
         if (v != floor(v))
             return 0;
         tab[b] = (int32_t)v;
@@ -224,10 +269,11 @@ void or_project(const void *X, int x_type, int64_t n, int32_t F, int64_t ldx,
     int use_tab = int_feature_table(x_type, compute, tab);
 #pragma omp parallel for num_threads(or_threads(threads)) schedule(dynamic, 8)
     for (int64_t i = 0; i < n; i++) {
-        double s = 0.0;
+        xacc s;
+        memset(&s, 0, sizeof s);
         for (int32_t f = 0; f < F; f++)
-            s += fabs(or_feature(X, x_type, ldx, i, f, compute));
-        absum[i] = s;
+            xacc_add(&s, fabs(or_feature(X, x_type, ldx, i, f, compute)));
+        absum[i] = xacc_value(&s);
         for (int32_t j = 0; j < ns; j++) {
             int64_t d = start + (int64_t)j * stride;
             project_one(X, x_type, ldx, i, F, P + d * ldp, compute,

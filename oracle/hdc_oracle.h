@@ -42,7 +42,7 @@ extern "C" {
 #endif
 
 /* element types (same numbering as the feature types the tests pass in) */
-enum { OR_INT8 = 0, OR_UINT8 = 1, OR_BF16 = 2, OR_FP8_E4M3 = 3, OR_FP32 = 4 };
+enum { OR_INT8 = 0, OR_UINT8 = 1, OR_BF16 = 2, OR_FP8_E4M3 = 3, OR_FP32 = 4, OR_FP8_SPLIT = 5 };
 
 /* Round a real value to bfloat16: round to nearest, ties to even, on 8
  * significant bits, binary32 exponent range (subnormals below 2^-126),
@@ -56,7 +56,11 @@ double or_round_e4m3(double v);
 
 /* Value of feature f of row i as the encoder sees it under element type
  * `compute`: the exact feature value (compute = INT8 or FP32), or that value
- * rounded to bfloat16 / E4M3. */
+ * rounded to bfloat16 / E4M3.  FP8_SPLIT (integer features only) writes the
+ * integer x as a high part h = 16 * floor(x / 16) plus a low part
+ * l = x - h in [0, 16), rounds each part to E4M3 on its own and returns
+ * their sum: the reduced element type applied to two halves of the
+ * feature (Sec. 4.2, "Element Type Representation"). */
 double or_feature(const void *X, int x_type, int64_t ldx, int64_t i, int32_t f, int compute);
 
 /* Number of dimensions in S(start, end, stride). */
@@ -73,8 +77,9 @@ void or_encode(const void *X, int x_type, int64_t n, int32_t F, int64_t ldx,
                int32_t start, int32_t end, int32_t stride,
                uint64_t *H, int64_t ldh, int threads);
 
-/* The projections themselves, y[i][j] as double (exactly rounded), plus
- * absum[i] = sum_f |x'_{if}|, for floating-point tolerance bands. */
+/* The projections themselves, y[i][j] as double, plus absum[i] =
+ * sum_f |x'_{if}|, for floating-point tolerance bands.  Both are the exact
+ * sums rounded once to the nearest double (ties to even). */
 void or_project(const void *X, int x_type, int64_t n, int32_t F, int64_t ldx,
                 const int8_t *P, int32_t D, int64_t ldp, int compute,
                 int32_t start, int32_t end, int32_t stride,

@@ -21,8 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hdc_oracle.c")
 LIB = os.path.join(HERE, "libhdc_oracle.so")
 
-INT8, UINT8, BF16, FP8_E4M3, FP32 = 0, 1, 2, 3, 4
-DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32}
+INT8, UINT8, BF16, FP8_E4M3, FP32, FP8_SPLIT = 0, 1, 2, 3, 4, 5
+DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32, "fp8split": FP8_SPLIT}
 
 
 def build(verbose: bool = False) -> str:

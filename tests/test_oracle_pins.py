@@ -227,6 +227,76 @@ def test_fp32_sign_is_exact():
     assert not O.encode(X2, np.array([[1, -1], [-1, 1]], np.int8), "fp32").any()
 
 
+def _conv_lib(x, ct):
+    """Reference element-type conversion by torch's casts (round to nearest
+    even; E4M3FN values here stay below its 448 limit)."""
+    import torch
+    t = torch.tensor(np.asarray(x, dtype=np.float32))
+    if ct == "bf16":
+        t = t.to(torch.bfloat16)
+    elif ct == "fp8":
+        t = t.to(torch.float8_e4m3fn)
+    return t.to(torch.float64).numpy()
+
+
+def test_project_values_are_exact_sums_rounded_once():
+    """or_project: y and sum|x'| against rational arithmetic (fractions),
+    each rounded once to double, with the element-type conversion done by a
+    library cast; rows chosen so that plain float64 summation is wrong."""
+    from fractions import Fraction
+    g = np.random.default_rng(21)
+    P = (1 - 2 * g.integers(0, 2, size=(24, 64))).astype(np.int8)
+    X = (g.standard_normal((6, 64)) * 3).astype(np.float32)
+    X[0, :3] = [1e30, 1.0, -1e30]                   # cancellation
+    X[1, :4] = [3e7, 1.0, -3e7, 0.5]
+    X[2] = 0.1
+    X[3, :] = 0.0                                    # y = 0, absum = 0
+    X[4, 1:] = 0.0
+    X[4, 0] = 5e-45                                  # subnormal binary32
+    for ct in ("fp32", "bf16", "fp8"):
+        Xc = _conv_lib(np.clip(X, -440, 440) if ct == "fp8" else X, ct)
+        Xin = np.clip(X, -440, 440).astype(np.float32) if ct == "fp8" else X
+        Y, absum = O.project(Xin, P, ct)
+        for i in range(X.shape[0]):
+            xs = [Fraction(float(v)) for v in Xc[i]]
+            assert absum[i] == float(sum(abs(v) for v in xs)), (ct, i)
+            for j in range(P.shape[0]):
+                y = sum(v * int(c) for v, c in zip(xs, P[j]))
+                assert Y[i, j] == float(y), (ct, i, j)
+    # perforated dimension sets pick the rows S_j in order
+    Ys, _ = O.project(X, P, "fp32", 3, 24, 5)
+    Yf, _ = O.project(X, P, "fp32")
+    assert np.array_equal(Ys, Yf[:, 3:24:5])
+
+
+def test_fp8_split_is_the_exact_encoding():
+    """The split E4M3 element type: x = 16*floor(x/16) + (x mod 16) with both
+    parts exact in E4M3 (4 significant bits: multiples of 16 up to 240 and
+    -128, and 0..15), so its projection is the integer one for every int8
+    and uint8 value, and its signs are the exact int8 encoding's."""
+    for v in list(range(-128, 128)) + list(range(256)):
+        h = 16 * (v // 16)
+        lo = v - h
+        assert O.round_e4m3(h) == h and O.round_e4m3(lo) == lo and 0 <= lo < 16
+    # every feature value through the projection: a one-feature row per value
+    vals_i8 = np.arange(-128, 128, dtype=np.int8).reshape(-1, 1)
+    vals_u8 = np.arange(0, 256, dtype=np.uint8).reshape(-1, 1)
+    Pm = np.array([[1], [-1]], dtype=np.int8)
+    for vals in (vals_i8, vals_u8):
+        Y, _ = O.project(vals, Pm, "fp8split")
+        assert np.array_equal(Y, vals.astype(np.float64) * np.array([[1.0, -1.0]]))
+        # direct E4M3 rounds values above 16 (the rung the split replaces)
+        Yd, _ = O.project(vals, Pm, "fp8")
+        assert not np.array_equal(Yd, Y)
+    g = np.random.default_rng(5)
+    for x_type, F in (("int8", 617), ("uint8", 784)):
+        X, P = _small_case(40, F, 300, x_type, 17)
+        y = X.astype(np.int64) @ P.astype(np.int64).T
+        assert np.array_equal(unpack(O.encode(X, P, "fp8split"), 300), np.where(y < 0, -1, 1))
+        assert np.array_equal(O.encode(X, P, "fp8split", 2, 300, 3), O.encode(X, P, "int8", 2, 300, 3))
+    del g
+
+
 def test_fp32_encode_matches_float64_outside_band():
     X, P = _small_case(50, 64, 2048, "fp32", 13)
     y = X.astype(np.float64) @ P.astype(np.float64).T

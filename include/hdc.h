@@ -42,7 +42,9 @@
  *   row-major [D][ldp] int8 (row d holds the F weights of dimension d, i.e.
  *   P = B^T for the paper's random-projection matrix B; Sec. 2.2 Listing
  *   1's hypermatrix<D, F>).  ldp >= F rounded up to 64, a multiple of 16,
- *   P 16-byte aligned; columns [0, F) must hold +1 or -1.
+ *   P 16-byte aligned; columns [0, F) must hold +1 or -1.  D * ldp must be
+ *   below 2^32 bytes (the kernels address P with 32-bit offsets); a larger
+ *   projection gives HDC_ERR_UNSUPPORTED.
  */
 #ifndef HDC_H
 #define HDC_H
@@ -69,16 +71,24 @@ typedef enum {
  *                                        correction, also exact)
  *   HDC_INT8 / HDC_UINT8 -> HDC_BF16     bf16 MFMA, fp32 accumulation
  *   HDC_INT8 / HDC_UINT8 -> HDC_FP8_E4M3 OCP E4M3 MFMA, fp32 accumulation
+ *   HDC_INT8 / HDC_UINT8 -> HDC_FP8_E4M3_SPLIT
+ *                                        each feature x written as
+ *                                        16*floor(x/16) + (x mod 16), both
+ *                                        parts exact in E4M3; two E4M3 MFMAs
+ *                                        into fp32 sums below 2^24: exact,
+ *                                        the same bits as HDC_INT8
  *   HDC_FP32 -> HDC_FP32 / HDC_BF16 / HDC_FP8_E4M3   (F <= 256)
  * The reduced types round each feature to the compute type (round to nearest
  * even) and multiply by the exactly representable +-1 weights (Sec. 4.2
- * "Element Type Representation"). */
+ * "Element Type Representation").  HDC_FP8_E4M3_SPLIT is a compute type
+ * only (never a feature type) and is not a sweep configuration dtype. */
 typedef enum {
     HDC_INT8 = 0,
     HDC_UINT8 = 1,
     HDC_BF16 = 2,
     HDC_FP8_E4M3 = 3,
-    HDC_FP32 = 4
+    HDC_FP32 = 4,
+    HDC_FP8_E4M3_SPLIT = 5
 } hdc_dtype;
 
 typedef struct {
@@ -163,7 +173,9 @@ hdc_status hdc_retrain_epoch(void *stream,
  * Listing 1: hamming_distance, red_perf, arg_min; Sec. 4.2).
  *     dist[i][k] = #{ d in S(perf) : bit d of Q row i != bit d of C row k }
  * The count is used as-is (not rescaled).  argmin[i] is the lowest k with
- * the smallest distance.  Q and C both hold >= perf.end valid bits.
+ * the smallest distance.
+ *   nbits    valid bits of each Q and C row (hypervector length); requires
+ *            perf.end <= nbits, ldq and ldc >= ceil(nbits / 64)
  *   Q        [n][ldq] uint64,  C [K][ldc] uint64
  *   argmin   [n] int32 output
  *   min_dist [n] int32 output, may be NULL
@@ -173,7 +185,7 @@ hdc_status hdc_retrain_epoch(void *stream,
 hdc_status hdc_hamming_argmin(void *stream,
                               const uint64_t *Q, int64_t n, int64_t ldq,
                               const uint64_t *C, int32_t K, int64_t ldc,
-                              hdc_dims perf,
+                              int32_t nbits, hdc_dims perf,
                               int32_t *argmin, int32_t *min_dist, int32_t *dists);
 
 /* ---------------------------------------------------------------------
@@ -293,9 +305,12 @@ hdc_status hdc_adc_argmax_prepared(void *stream,
                                    const void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
- * hdc_classify -- the fused inference path: encode each query over the
- * dimensions S(dims) under `compute`, compare bit j of the query with bit
- * S_j of each (full-D) class hypervector, argmin.  Equal, bit for bit, to
+ * hdc_classify -- the fused inference path of Sec. 2.2 Listing 1 (matmul,
+ * then hamming_distance under red_perf, then arg_min) in one kernel, with
+ * the binarisation of Sec. 4.2 "Automatic Binarization" between them:
+ * encode each query over the dimensions S(dims) under `compute`, compare
+ * bit j of the query with bit S_j of each (full-D) class hypervector,
+ * argmin.  Equal, bit for bit, to
  * hdc_encode(dims) followed by hdc_hamming_argmin over the gathered class
  * bits, without writing the query hypervectors anywhere.
  *   C       [K][ldc] uint64 class hypervectors over all D dimensions

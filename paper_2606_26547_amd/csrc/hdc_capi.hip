@@ -10,6 +10,7 @@ hipError_t launch_encode_i8(const EncodeArgs &a, int mode, Tile tile, hipStream_
 hipError_t launch_encode_fp8(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
 hipError_t launch_encode_bf16(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
 hipError_t launch_encode_f32(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
+hipError_t launch_encode_fp8s(const EncodeArgs &a, int mode, Tile tile, hipStream_t st);
 
 hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st)
 {
@@ -18,6 +19,7 @@ hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, 
     case C_FP8: return launch_encode_fp8(a, mode, tile, st);
     case C_BF16: return launch_encode_bf16(a, mode, tile, st);
     case C_F32: return launch_encode_f32(a, mode, tile, st);
+    case C_FP8S: return launch_encode_fp8s(a, mode, tile, st);
     }
     return hipErrorInvalidValue;
 }
@@ -49,6 +51,7 @@ int compute_of(hdc_dtype x, hdc_dtype c)
         if (c == HDC_INT8) return C_I8;
         if (c == HDC_BF16) return C_BF16;
         if (c == HDC_FP8_E4M3) return C_FP8;
+        if (c == HDC_FP8_E4M3_SPLIT) return C_FP8S;
         return -1;
     }
     if (x == HDC_FP32) {
@@ -87,6 +90,10 @@ hdc_status check_encode_operands(const void *X, hdc_dtype x_type, int64_t n, int
         return HDC_ERR_INVALID;
     if (!P || ldp < round_up(F, 64) || ldp % 16 || !aligned(P, 16))
         return HDC_ERR_INVALID;
+    // the encoders address P with 32-bit byte offsets (the direct-to-LDS
+    // loads take a 32-bit voffset): every row must start below 2^32 - ldp
+    if ((uint64_t)D * (uint64_t)ldp > (uint64_t)UINT32_MAX - (uint64_t)ldp)
+        return HDC_ERR_UNSUPPORTED;
     if (n > 0 && (!X || ldx < round_up(F, 64) || ldx % 16 || !aligned(X, 16)))
         return HDC_ERR_INVALID;
     return HDC_OK;
@@ -173,16 +180,16 @@ hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits,
 }
 
 hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C,
-                              int32_t K, int64_t ldc, hdc_dims perf, int32_t *argmin, int32_t *min_dist,
-                              int32_t *dists)
+                              int32_t K, int64_t ldc, int32_t nbits, hdc_dims perf, int32_t *argmin,
+                              int32_t *min_dist, int32_t *dists)
 {
-    if (n < 0 || K <= 0)
+    if (n < 0 || K <= 0 || nbits <= 0)
+        return HDC_ERR_INVALID;
+    if (perf.stride < 1 || perf.start < 0 || perf.end <= perf.start || perf.end > nbits)
         return HDC_ERR_INVALID;
     if (K > kMaxK || perf.end > 65536)
         return HDC_ERR_UNSUPPORTED;
-    if (perf.stride < 1 || perf.start < 0 || perf.end <= perf.start)
-        return HDC_ERR_INVALID;
-    const int64_t W = (perf.end + 63) / 64;
+    const int64_t W = ((int64_t)nbits + 63) / 64;
     if (!C || ldc < W)
         return HDC_ERR_INVALID;
     if (n == 0)

@@ -59,26 +59,47 @@ __device__ __forceinline__ void lds_dma16(const void *base, uint32_t voff, const
 // column l % 32.
 // ---------------------------------------------------------------------------
 template <int CT> struct Tr;
+// frag is the A operand (projection rows, from LDS), xfrag the B operand
+// (query features, kept in registers); they differ for the split E4M3
+// type, whose B operand is a pair: the high parts in elements 0..7 and the
+// low parts in 8..15.
 template <> struct Tr<C_I8> {
     static constexpr int KSTEP = 32, DW = 4, ESZ = 1;
     typedef v4i frag;
+    typedef v4i xfrag;
     typedef v16i acc;
 };
 template <> struct Tr<C_FP8> {
     static constexpr int KSTEP = 64, DW = 8, ESZ = 1;
     typedef v8i frag;
+    typedef v8i xfrag;
+    typedef v16f acc;
+};
+template <> struct Tr<C_FP8S> {
+    static constexpr int KSTEP = 64, DW = 8, ESZ = 1;
+    typedef v8i frag;
+    typedef v16i xfrag;
     typedef v16f acc;
 };
 template <> struct Tr<C_BF16> {
     static constexpr int KSTEP = 16, DW = 4, ESZ = 2;
     typedef v4i frag;           // 8 bf16 reinterpreted
+    typedef v4i xfrag;
     typedef v16f acc;
 };
 template <> struct Tr<C_F32> {
     static constexpr int KSTEP = 2, DW = 1, ESZ = 4;
     typedef float frag;
+    typedef float xfrag;
     typedef v16f acc;
 };
+
+// Halves of a split E4M3 B operand.
+__device__ __forceinline__ v8i split_hi(const v16i &x) { return __builtin_shufflevector(x, x, 0, 1, 2, 3, 4, 5, 6, 7); }
+__device__ __forceinline__ v8i split_lo(const v16i &x)
+{
+    return __builtin_shufflevector(x, x, 8, 9, 10, 11, 12, 13, 14, 15);
+}
 
 __device__ __forceinline__ void mma(v16i &c, const v4i &a, const v4i &b)
 {
@@ -134,6 +155,19 @@ __device__ __forceinline__ float byte_value(uint32_t w, int e, bool is_signed)
 {
     uint32_t b = (w >> (8 * e)) & 0xffu;
     return is_signed ? (float)(int)(int8_t)b : (float)b;
+}
+
+// Four integer features (bytes of w, signed or unsigned) split into E4M3
+// parts: *hi gets 16 * floor(x / 16) (the byte with its low nibble cleared,
+// read with the feature's sign: a multiple of 16 in [-128, 240]), *lo gets
+// x mod 16 (the low nibble, 0..15).  Both are exact in E4M3 (four
+// significant bits), so the conversions do not round.
+__device__ __forceinline__ void fp8_split4(uint32_t w, bool is_signed, uint32_t *hi, uint32_t *lo)
+{
+    const uint32_t h = w & 0xF0F0F0F0u, l = w & 0x0F0F0F0Fu;
+    *hi = fp8x4(byte_value(h, 0, is_signed), byte_value(h, 1, is_signed), byte_value(h, 2, is_signed),
+                byte_value(h, 3, is_signed));
+    *lo = fp8x4((float)(l & 0xffu), (float)((l >> 8) & 0xffu), (float)((l >> 16) & 0xffu), (float)(l >> 24));
 }
 
 // Keep the bytes of w whose feature index (k0 + byte) is below F.

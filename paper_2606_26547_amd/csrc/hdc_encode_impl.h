@@ -104,7 +104,7 @@ static hipError_t launch_encode_ct(const EncodeArgs &a, int mode, Tile tile, hip
     constexpr int KSTEP = Tr<CT>::KSTEP;
     const int F = a.F;
     if (a.x_type == X_FP32) {
-        if constexpr (CT == C_I8) {
+        if constexpr (CT == C_I8 || CT == C_FP8S) {
             return hipErrorInvalidValue;
         } else {
             if (F <= 64) return launch_bucket<CT, 1, 64 / KSTEP>(a, mode, tile, st);

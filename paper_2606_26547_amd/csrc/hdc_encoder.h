@@ -25,6 +25,7 @@ template <int CT, int XF, int QT, int KS, int KT, int MODE, int WV = 0, bool DMA
 struct Encoder {
     typedef Tr<CT> T;
     typedef typename T::frag frag;
+    typedef typename T::xfrag xfrag;
     typedef typename T::acc acc_t;
     static constexpr int KSTEP = T::KSTEP;
     static constexpr int KB = KSTEP * T::ESZ;              // LDS bytes per K-step per row
@@ -61,7 +62,7 @@ struct Encoder {
     static constexpr int QPB = QPW * kWaves;               // queries per workgroup
 
     // ---------------------------------------------------------------- X
-    static __device__ __forceinline__ frag load_frag(const EncodeArgs &a, int64_t q, int s, int g)
+    static __device__ __forceinline__ xfrag load_frag(const EncodeArgs &a, int64_t q, int s, int g)
     {
         const int k0 = s * KSTEP + g * (KSTEP / 2);
         if constexpr (XF == 0) {
@@ -89,6 +90,19 @@ struct Encoder {
                                       byte_value(x, 2, sgn), byte_value(x, 3, sgn));
                 }
                 return r;
+            } else if constexpr (CT == C_FP8S) {
+                uint4 w0 = *(const uint4 *)(row + k0);
+                uint4 w1 = *(const uint4 *)(row + k0 + 16);
+                uint32_t d[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                v16i r;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    uint32_t hi, lo;
+                    fp8_split4(keep_bytes(d[e], k0 + 4 * e, a.F), sgn, &hi, &lo);
+                    r[e] = (int)hi;
+                    r[8 + e] = (int)lo;
+                }
+                return r;
             } else {   // C_BF16
                 uint2 w = *(const uint2 *)(row + k0);
                 uint32_t d[2] = {keep_bytes(w.x, k0, a.F), keep_bytes(w.y, k0 + 4, a.F)};
@@ -101,6 +115,7 @@ struct Encoder {
                 return r;
             }
         } else {
+            static_assert(CT != C_FP8S, "the split E4M3 type is for integer features");
             const float *row = (const float *)a.X + q * a.ldx;
             auto val = [&](int k) { return k < a.F ? row[k] : 0.0f; };
             if constexpr (CT == C_F32) {
@@ -130,7 +145,7 @@ struct Encoder {
         }
     }
 
-    static __device__ __forceinline__ void load_x(frag (&xr)[QT][KS], const EncodeArgs &a,
+    static __device__ __forceinline__ void load_x(xfrag (&xr)[QT][KS], const EncodeArgs &a,
                                                   int64_t qbase, int lane, int ks_used)
     {
         // Branch-free: out-of-range rows / steps load an in-bounds address
@@ -144,9 +159,9 @@ struct Encoder {
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const bool v = qv && s < ks_used;
-                frag f = load_frag(a, qc, v ? s : 0, g);
+                xfrag f = load_frag(a, qc, v ? s : 0, g);
                 if (!v)
-                    f = frag{};
+                    f = xfrag{};
                 xr[qt][s] = f;
             }
         }
@@ -210,7 +225,7 @@ struct Encoder {
             }
             if constexpr (CT == C_I8) {
                 lds_st16(rowl + 16 * j, valid ? pr[m] : make_uint4(0, 0, 0, 0));
-            } else if constexpr (CT == C_FP8) {
+            } else if constexpr (CT == C_FP8 || CT == C_FP8S) {
                 uint4 o;
                 uint32_t *op = (uint32_t *)&o;
 #pragma unroll
@@ -269,7 +284,9 @@ struct Encoder {
     // features (sums below 2^24).  Register-staged kernels compiled for two
     // waves per SIMD have no room for the second set and rely on the other
     // wave instead; two query tiles are two chains already.
-    static constexpr int KC = (QT == 1 && (WAVES == 1 || DMA) && KS >= 2) ? 2 : 1;
+    // The split E4M3 type always has two: its high parts accumulate in the
+    // first, its low parts in the second (|sums| < 2^24, exact).
+    static constexpr int KC = CT == C_FP8S ? 2 : (QT == 1 && (WAVES == 1 || DMA) && KS >= 2) ? 2 : 1;
     typedef acc_t Parts[QT][KC];             // accumulators of one row tile
     static constexpr int kPhases = 4 * QT;   // epilogue phases (see Epilogue)
 
@@ -288,7 +305,7 @@ struct Encoder {
     // (the previous row tile's epilogue, the next chunk's loads) issues
     // between the MFMAs, while the matrix core is busy.
     template <class Hook>
-    static __device__ __forceinline__ void tile_mma(Parts &part, const frag (&xr)[QT][KS], const lds_u8 *lp,
+    static __device__ __forceinline__ void tile_mma(Parts &part, const xfrag (&xr)[QT][KS], const lds_u8 *lp,
                                                     const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
     {
         const int g = lane >> 5, row = lane & 31;
@@ -322,9 +339,18 @@ struct Encoder {
             const frag cur = f[s % PD];
             if (s + PD < KS)
                 f[s % PD] = *(const HDC_LDS frag *)(base + (s + PD) * KB);
+            if constexpr (CT == C_FP8S) {
 #pragma unroll
-            for (int qt = 0; qt < QT; ++qt)
-                mma(part[qt][s % KC], cur, xr[qt][s]);
+                for (int qt = 0; qt < QT; ++qt)
+                    mma(part[qt][0], cur, split_hi(xr[qt][s]));
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt)
+                    mma(part[qt][1], cur, split_lo(xr[qt][s]));
+            } else {
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt)
+                    mma(part[qt][s % KC], cur, xr[qt][s]);
+            }
             hook.at(s);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -357,7 +383,7 @@ struct Encoder {
                 const int ph = p - 4 * qt;
                 const acc_t &y = part[qt][0];
                 if (ph == 0) {
-                    if constexpr (CT == C_FP8) {
+                    if constexpr (CT == C_FP8 || CT == C_FP8S) {
                         // The 16-pass E4M3 MFMA's accumulator was observed to
                         // be read one wait state early by the compiler-inserted
                         // hazard padding; extra wait states keep the read clear.
@@ -474,7 +500,7 @@ struct Encoder {
         const int NC = (a.nd + kDimChunk - 1) / kDimChunk;
         const bool colsum = CT == C_I8 && XF == 0 && a.x_type == X_UINT8;
 
-        frag xr[QT][KS];
+        xfrag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
@@ -651,7 +677,7 @@ struct Encoder {
         // of the encode epilogue are not counted: waiting for more is safe)
         constexpr int G = NLOADS;
 
-        frag xr[QT][KS];
+        xfrag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)

@@ -8,8 +8,11 @@
 
 namespace hdc {
 
-// Encoding compute type of a kernel instantiation.
-enum Compute : int { C_I8 = 0, C_BF16 = 1, C_FP8 = 2, C_F32 = 3 };
+// Encoding compute type of a kernel instantiation.  C_FP8S is E4M3 on
+// integer features split into a multiple of 16 and a remainder in [0, 16)
+// (both exact in E4M3), two MFMAs per projection fragment.
+enum Compute : int { C_I8 = 0, C_BF16 = 1, C_FP8 = 2, C_F32 = 3, C_FP8S = 4 };
+constexpr int kComputeTypes = 5;
 
 // Feature storage type.
 enum XType : int { X_INT8 = 0, X_UINT8 = 1, X_FP32 = 2 };
@@ -87,7 +90,7 @@ constexpr bool big_tile(int ks, int kt) { return ks <= 20 && kt <= 2; }
 // Two query tiles per wave fit beside the accumulators (register staging).
 constexpr bool qt2_fits(int ct, int ks) { return (ct == C_I8 && ks <= 16) || (ct == C_F32 && ks <= 64); }
 // K step (features per MFMA) of a compute type.
-constexpr int kstep_of(int ct) { return ct == C_I8 ? 32 : ct == C_FP8 ? 64 : ct == C_BF16 ? 16 : 2; }
+constexpr int kstep_of(int ct) { return ct == C_I8 ? 32 : (ct == C_FP8 || ct == C_FP8S) ? 64 : ct == C_BF16 ? 16 : 2; }
 
 // Compiled feature widths of the encoder (integer features / fp32
 // features); a launch uses the smallest width >= F.

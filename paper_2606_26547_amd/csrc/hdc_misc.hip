@@ -306,6 +306,11 @@ __global__ __launch_bounds__(256) void k_convert(const void *__restrict__ X, int
     }
     if (compute == C_FP8)
         v = __builtin_amdgcn_cvt_f32_fp8((int)fp8x4(v, 0.f, 0.f, 0.f), 0);
+    else if (compute == C_FP8S) {   // integer features: the two E4M3 parts, added back
+        uint32_t hi, lo;
+        fp8_split4(((const uint8_t *)X)[i * ldx + f], x_type == X_INT8, &hi, &lo);
+        v = __builtin_amdgcn_cvt_f32_fp8((int)hi, 0) + __builtin_amdgcn_cvt_f32_fp8((int)lo, 0);
+    }
     else if (compute == C_BF16)
         v = __uint_as_float(bf16x2(v, 0.f) << 16);
     out[idx] = v;

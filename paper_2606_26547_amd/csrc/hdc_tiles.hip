@@ -16,7 +16,7 @@ constexpr int kNW = kNI > kNF ? kNI : kNF;
 constexpr int kNS = sizeof(kSweepWidths) / sizeof(kSweepWidths[0]);
 
 // [kind encode/classify][compute][feature kind int/fp32][width][class tiles 1/2/4]
-std::atomic<int> g_enc[2][4][2][kNW][3];
+std::atomic<int> g_enc[2][kComputeTypes][2][kNW][3];
 // [width][class tiles 1/4]
 std::atomic<int> g_sweep[kNS][2];
 
@@ -48,7 +48,7 @@ int encoder_variants(int ct, int x_type, int width, int kt, int *out)
 
 std::atomic<int> *encoder_slot(int kind, int x_type, int ct, int F, int K)
 {
-    if ((kind != KK_ENCODE && kind != KK_CLASSIFY) || ct < 0 || ct > 3)
+    if ((kind != KK_ENCODE && kind != KK_CLASSIFY) || ct < 0 || ct >= kComputeTypes)
         return nullptr;
     const int wi = width_index(x_type, F);
     if (wi < 0 || K < 1 || K > kMaxK)

@@ -27,8 +27,8 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-INT8, UINT8, BF16, FP8_E4M3, FP32 = 0, 1, 2, 3, 4
-DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32}
+INT8, UINT8, BF16, FP8_E4M3, FP32, FP8_SPLIT = 0, 1, 2, 3, 4, 5
+DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32, "fp8split": FP8_SPLIT}
 STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
@@ -74,7 +74,7 @@ _lib.hdc_encode.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C
 _lib.hdc_bundle_workspace_bytes.restype = _sz
 _lib.hdc_bundle_workspace_bytes.argtypes = [_i32, _i32]
 _lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
-_lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, _p, _p, _p]
+_lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, _i32, Dims, _p, _p, _p]
 _lib.hdc_hamming_workspace_bytes.restype = _sz
 _lib.hdc_hamming_workspace_bytes.argtypes = [Dims, _i32]
 _lib.hdc_hamming_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
@@ -195,12 +195,16 @@ def bundle(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.
 
 
 def hamming_argmin(Q: torch.Tensor, Cw: torch.Tensor, start: int, end: int, stride: int = 1,
-                   with_min=False, with_dists=False):
+                   with_min=False, with_dists=False, nbits: int | None = None):
+    """hdc_hamming_argmin; nbits (the hypervector length) defaults to the
+    longest the row pitches of Q and Cw hold."""
     n, K = Q.shape[0], Cw.shape[0]
+    if nbits is None:
+        nbits = 64 * min(Q.shape[1], Cw.shape[1])
     lab = torch.empty(n, dtype=torch.int32, device=Q.device)
     mn = torch.empty(n, dtype=torch.int32, device=Q.device) if with_min else None
     dists = torch.empty((n, K), dtype=torch.int32, device=Q.device) if with_dists else None
-    _check(_lib.hdc_hamming_argmin(_stream(), _ptr(Q), n, Q.shape[1], _ptr(Cw), K, Cw.shape[1],
+    _check(_lib.hdc_hamming_argmin(_stream(), _ptr(Q), n, Q.shape[1], _ptr(Cw), K, Cw.shape[1], nbits,
                                    Dims(start, end, stride), _ptr(lab), _ptr(mn), _ptr(dists)),
            "hdc_hamming_argmin")
     return lab, mn, dists

@@ -61,6 +61,31 @@ def test_validation_without_device(lib):
     assert lib.hdc_encode(None, fake, 0, 1, 2000, 2048, fake, 64, 2048, 0, Dims(0, 64, 1), fake, 1) == 2
     # n == 0 is a no-op
     assert lib.hdc_encode(None, None, 0, 0, 8, 64, fake, 64, 64, 0, Dims(0, 64, 1), None, 1) == 0
+    # the split E4M3 compute type (5) takes integer features only
+    assert lib.hdc_encode(None, None, 0, 0, 8, 64, fake, 64, 64, 5, Dims(0, 64, 1), None, 1) == 0
+    assert lib.hdc_encode(None, None, 1, 0, 8, 64, fake, 64, 64, 5, Dims(0, 64, 1), None, 1) == 0
+    assert lib.hdc_encode(None, fake, 4, 1, 8, 64, fake, 64, 64, 5, Dims(0, 64, 1), fake, 1) == 2
+    assert lib.hdc_encode(None, fake, 5, 1, 8, 64, fake, 64, 64, 5, Dims(0, 64, 1), fake, 1) == 1
+    # a projection of 2^32 bytes or more is refused (32-bit row offsets):
+    # encode, classify and the configuration sweep share the check
+    big_d = (1 << 32) // 1024
+    assert lib.hdc_encode(None, fake, 0, 1, 1000, 1024, fake, big_d, 1024, 0, Dims(0, 64, 1), fake, 1) == 2
+    assert lib.hdc_encode(None, fake, 0, 1, 1000, 1024, fake, big_d - 2, 1024, 0, Dims(0, 64, 1), None, 1) == 1
+    lib.hdc_classify.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, p, i32, i64, p, p, p,
+                                 C.c_size_t]
+    assert lib.hdc_classify(None, fake, 0, 1, 1000, 1024, fake, big_d, 1024, 0, Dims(0, 64, 1), fake, 3, 1, fake,
+                            None, fake, 1 << 20) == 2
+    lib.hdc_eval_configs.argtypes = [p, p, C.c_int, i64, i32, i64, p, p, i32, i64, p, i32, i64, p, i32, p, p,
+                                     C.c_size_t, i32]
+    assert lib.hdc_eval_configs(None, fake, 0, 1, 1000, 1024, fake, fake, big_d, 1024, fake, 3, big_d // 64, fake,
+                                1, fake, fake, 1 << 30, 0) == 2
+    # hdc_hamming_argmin: nbits bounds the perforation set and the pitches
+    lib.hdc_hamming_argmin.argtypes = [p, p, i64, i64, p, i32, i64, i32, Dims, p, p, p]
+    assert lib.hdc_hamming_argmin(None, fake, 4, 2, fake, 3, 2, 0, Dims(0, 64, 1), fake, None, None) == 1
+    assert lib.hdc_hamming_argmin(None, fake, 4, 2, fake, 3, 2, 100, Dims(0, 101, 1), fake, None, None) == 1
+    assert lib.hdc_hamming_argmin(None, fake, 4, 1, fake, 3, 2, 100, Dims(0, 64, 1), fake, None, None) == 1
+    assert lib.hdc_hamming_argmin(None, fake, 4, 2, fake, 3, 1, 100, Dims(0, 64, 1), fake, None, None) == 1
+    assert lib.hdc_hamming_argmin(None, None, 0, 2, fake, 3, 2, 100, Dims(0, 64, 1), None, None, None) == 0
     lib.hdc_classify_workspace_bytes.restype = C.c_size_t
     assert lib.hdc_classify_workspace_bytes(10240, 26) == 320 * 1024 + 512
     assert lib.hdc_classify_workspace_bytes(10240, 200) == 0

@@ -52,11 +52,86 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile choices, no tuning launches")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--full-out", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
+                    help="where the full result record is written (the last stdout line is a summary of it)")
     return ap.parse_args()
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _r(v, nd=4):
+    """Round floats for the summary line (3-4 significant digits)."""
+    if isinstance(v, float):
+        return float("%.*g" % (nd, v))
+    if isinstance(v, dict):
+        return {k: _r(x, nd) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_r(x, nd) for x in v]
+    return v
+
+
+def _pick(d, *keys):
+    return {k: d[k] for k in keys if isinstance(d, dict) and k in d}
+
+
+def compact(out: dict) -> dict:
+    """The one-line summary printed last: the contract fields, the headline
+    roofline and CPU baseline, and a few figures of every other section (the
+    full record goes to a file).  Stays well under 4 KB."""
+    c = _pick(out, "metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "accuracy_plain", "p50_ms", "p99_ms")
+    c["config"] = _pick(out.get("config", {}), "workload", "F", "K", "D", "batch", "parallelism")
+    if "roofline" in out:
+        c["roofline"] = _pick(out["roofline"], "bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                              "ms_per_launch")
+    if "cpu_baseline" in out:
+        c["cpu_baseline"] = _pick(out["cpu_baseline"], "value", "unit", "cores", "kind", "sample", "cpu_model",
+                                  "tuned_value", "single_thread_value")
+    if "tuned" in out:
+        t = out["tuned"]
+        c["tuned"] = dict(_pick(t, "config", "value", "ms_per_step", "accuracy", "speedup_vs_plain"),
+                          p99_ms=out.get("latency", {}).get("tuned", {}).get("p99_ms"))
+    extras = {}
+    if "latency" in out:
+        extras["latency_1559"] = {k: _pick(v, "p50_ms", "p99_ms") for k, v in out["latency"].items()}
+    if "train" in out:
+        extras["train_ms"] = out["train"]["ms"]
+    for key in ("sweep", "bundle", "plain_fp32"):
+        if key in out:
+            sec = out[key]
+            extras[key] = dict(_pick(sec, "ms", "slots", "queries_per_s", "accuracy", "GB_s"),
+                               **({"frac": sec["roofline"]["frac"], "bound": sec["roofline"]["bound"]}
+                                  if "roofline" in sec else {}))
+    if "hamming_unfused" in out:
+        extras["hamming_mfma_GB_s"] = {k.split()[0] + k.split()[1]: v["mfma"]["GB_s"]
+                                       for k, v in out["hamming_unfused"].items()}
+    if "ladder" in out:
+        extras["ladder"] = {wl: {t: _pick(v, "flip_rate", "accuracy") for t, v in r.items()
+                                 if isinstance(v, dict) and "flip_rate" in v}
+                            for wl, r in out["ladder"].items()}
+    if "serving" in out:
+        sv = out["serving"]
+        extras["serving"] = {m: _pick(sv[m], "p50_ms", "p99_ms", "queries_per_s")
+                             for m in ("plain", "tuned") if m in sv}
+    for key in ("cosine", "adc", "retrain"):
+        if key in out and "roofline" in out[key]:
+            extras[key + "_frac"] = out[key]["roofline"]["frac"]
+    if extras:
+        c["extras"] = extras
+    c["full_record"] = out.get("full_record")
+    return _r(c)
 
 
 def measured_traffic(key: str, batch: int, tile: str):
@@ -197,13 +272,24 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)
-        sweep_ms = (time.perf_counter() - t) * 1e3
+        sweep_wall_ms = (time.perf_counter() - t) * 1e3
+        # device time of the launch (slot setup, class operands, persistent
+        # kernel) with events on the launch stream
+        _, sweep_ms, _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, slots), 5, 1)
+        # algorithmic encode work of the 256 slots: 2 F |S| per query
+        sweep_ops = sum(2.0 * F * hdc.dims_count(s_, d_, k_) * Xsd.shape[0] for (d_, k_, s_, _) in slots)
         grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid)
         best, plain_r = tuner.select_tuned(
             grid_res, (D, 1, 0, "int8"), 1.0,
             timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw))
         out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
-                        "ms": sweep_ms, "one_launch": True}
+                        "ms": sweep_ms, "wall_ms": sweep_wall_ms, "one_launch": True,
+                        "roofline": {"bound": "mfma", "achieved": sweep_ops / (sweep_ms / 1e3) / 1e12,
+                                     "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s",
+                                     "frac": sweep_ops / (sweep_ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS,
+                                     "ops_per_launch": sweep_ops,
+                                     "note": "sum over slots of 2 F |S| x queries (int8 peak for every "
+                                             "slot dtype; bf16 slots run at half that rate)"}}
         d, k, s, tdt = best.cfg
         tuned = hdc.Prepared(Cw, D, tdt, s, d, k)
         tl = torch.empty(N, dtype=torch.int32, device=dev)
@@ -251,7 +337,7 @@ def main():
             row = {"queries": nq}
             for kind, fn in (("mfma", lambda: hp(Q, out=lab_h)),
                              ("popcount", lambda: hdc.lib().hdc_hamming_argmin(
-                                 hdc._stream(), hdc._ptr(Q), nq, W, hdc._ptr(Ch), Kh, W, hdc.Dims(0, nbits, 1),
+                                 hdc._stream(), hdc._ptr(Q), nq, W, hdc._ptr(Ch), Kh, W, nbits, hdc.Dims(0, nbits, 1),
                                  hdc._ptr(lab_p), None, None))):
                 _, ms_hk, _ = event_loop(fn, 10, 2)
                 gbs = nq * W * 8 / (ms_hk / 1e3) / 1e9
@@ -289,6 +375,7 @@ def main():
         dt = time.perf_counter() - t
         agree = float((lab_cpu == labels[:n_cpu].cpu().numpy()).mean())
         out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "queries/s", "cores": O.threads(), "kind": "oracle",
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                                "sample": "first %d queries of the batch, plain config (exact int encode + "
                                          "bit-by-bit Hamming + argmin), %.1fs" % (n_cpu, dt),
                                "labels_agree_with_gpu": agree}
@@ -309,7 +396,15 @@ def main():
         if not args.no_extras:
             out["cpu_baseline"]["rows"] = oracle_rows(O, np, ds, F, K, D)
 
-    print(json.dumps(out), flush=True)
+    out["full_record"] = args.full_out
+    try:
+        os.makedirs(os.path.dirname(args.full_out), exist_ok=True)
+        with open(args.full_out, "w") as f:
+            json.dump(out, f, indent=1)
+    except OSError as e:
+        log("could not write the full record to %s: %s" % (args.full_out, e))
+        out["full_record"] = None
+    print(json.dumps(compact(out)), flush=True)
 
 
 def oracle_rows(O, np, ds, F, K, D):

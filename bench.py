@@ -645,7 +645,7 @@ def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F,
     yte = torch.as_tensor(ds.y_test).to(dev)
     Hx = hdc.encode(Xte, F, Pd, D, "int8")
     sp = {}
-    for t in ("int8", "bf16", "fp8"):
+    for t in ("int8", "bf16", "fp8", "fp8split"):
         H = hdc.encode(Xte, F, Pd, D, t)
         lab = hdc.classify(Xte, F, Pd, D, Cw, t)
         prep = hdc.Prepared(Cw, D, t)
@@ -667,7 +667,7 @@ def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F,
     Ci, _ = hdc.bundle(Hi, Di, yi_tr, Ki)
     Hx = hdc.encode(Xi_te, Fi, Pi, Di, "int8")
     im = {}
-    for t in ("int8", "bf16", "fp8"):
+    for t in ("int8", "bf16", "fp8", "fp8split"):
         H = hdc.encode(Xi_te, Fi, Pi, Di, t)
         lab = hdc.classify(Xi_te, Fi, Pi, Di, Ci, t)
         prep = hdc.Prepared(Ci, Di, t)
@@ -683,7 +683,7 @@ def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F,
     im["tuned"] = {"cfg": list(best.cfg), "accuracy": best.accuracy, "accuracy_plain": plain.accuracy}
     res["image"] = im
     log("ladder image: %s; tuned %s" % ({t: (round(v["flip_rate"], 5), round(v["accuracy"], 4)) for t, v in im.items()
-                                        if t in ("int8", "bf16", "fp8")}, best.cfg))
+                                        if t in ("int8", "bf16", "fp8", "fp8split")}, best.cfg))
     return res
 
 

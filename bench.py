@@ -183,7 +183,7 @@ def main():
     Xsd = hdc.pad_cols(Xs, dev)
     ysd = torch.as_tensor(ys).to(dev)
     Xte = hdc.pad_cols(ds.X_test, dev)
-    ws_b = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(D, K), dtype=torch.uint8, device=dev)
+    ws_b = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(Xtr.shape[0], D, K), dtype=torch.uint8, device=dev)
     Htr = torch.zeros((Xtr.shape[0], hdc.words(D)), dtype=torch.int64, device=dev)
 
     def train():
@@ -264,8 +264,12 @@ def main():
     if not args.no_extras:
         # -------------------------------------------------------- training
         ms_train, _, _ = event_loop(train, 5, 1)
-        out["train"] = {"ms": ms_train, "n_train": int(Xtr.shape[0]),
-                        "note": "encode of the training set + majority bundle"}
+        _, ms_bundle_tr, _ = event_loop(lambda: hdc.bundle(Htr, D, ytr, K, ws_b), 20, 3)
+        out["train"] = {"ms": ms_train, "n_train": int(Xtr.shape[0]), "bundle_ms": ms_bundle_tr,
+                        "note": "encode of the training set + majority bundle (bundle_ms: the bundle alone, "
+                                "device time)"}
+        # -------------------------------------------------------- bundling at HBM scale
+        out["bundle"] = bundle_bench(dev, hdc, torch, event_loop)
         # -------------------------------------------------------- sweep + tuned selection
         grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
         tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)                  # warm-up launch
@@ -405,6 +409,24 @@ def main():
         log("could not write the full record to %s: %s" % (args.full_out, e))
         out["full_record"] = None
     print(json.dumps(compact(out)), flush=True)
+
+
+def bundle_bench(dev, hdc, torch, event_loop, n=1 << 20, nbits=10240, K=26):
+    """Majority bundling of 2^20 random 10240-bit rows (1.34 GB) into 26
+    classes, random labels: HBM-bound (every row read once)."""
+    W = nbits // 64
+    H = torch.randint(-(1 << 62), 1 << 62, (n, W), dtype=torch.int64, device=dev)
+    y = torch.randint(0, K, (n,), dtype=torch.int32, device=dev)
+    ws = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(n, nbits, K), dtype=torch.uint8, device=dev)
+    _, ms, _ = event_loop(lambda: hdc.bundle(H, nbits, y, K, ws), 10, 2)
+    nbytes = n * W * 8 + n * 4 + K * W * 8        # rows + labels read, class words written
+    gbs = nbytes / (ms / 1e3) / 1e9
+    log("bundle 2^20 x %d bits: %.3f ms, %.0f GB/s" % (nbits, ms, gbs))
+    del H
+    return {"rows": n, "nbits": nbits, "K": K, "ms": ms, "GB_s": gbs,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes,
+                         "note": "algorithmic bytes: every row and label read once, class words written"}}
 
 
 def oracle_rows(O, np, ds, F, K, D):

@@ -122,14 +122,19 @@ hdc_status hdc_encode(void *stream,
  * aggregated into one class hypervector), as the per-dimension majority:
  *     n_k = #{i : labels[i] == k},  cnt[k][d] = #{i in class k : bit d set}
  *     C bit d of class k = (2 * cnt[k][d] > n_k)
- * so a tie gives +1 and an empty class is all +1.  Exact and deterministic.
- *   H       [n][ldh] uint64 hypervectors of nbits elements each
+ * so a tie gives +1 and an empty class is all +1.  Exact and deterministic
+ * (integer counts; the order rows are visited does not matter).
+ *   H       [n][ldh] uint64 hypervectors of nbits elements each, 8-byte
+ *           aligned
  *   labels  [n] int32 in [0, K) (precondition; out-of-range rows are skipped)
  *   C       [K][ldc] uint64 output, ldc >= ceil(nbits/64)
  *   counts  [K] int32 output n_k, may be NULL
- *   ws      >= hdc_bundle_workspace_bytes(nbits, K) bytes
+ *   ws      >= hdc_bundle_workspace_bytes(n, nbits, K) bytes, 256-byte
+ *           aligned (the class sums, a row index list grouped by class and
+ *           its offsets)
+ * Supports K <= 128 and n < 2^30.
  * ------------------------------------------------------------------- */
-size_t hdc_bundle_workspace_bytes(int32_t nbits, int32_t K);
+size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K);
 hdc_status hdc_bundle(void *stream,
                       const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
                       const int32_t *labels, int32_t K,
@@ -151,21 +156,28 @@ hdc_status hdc_bundle(void *stream,
  * each row gets from the model at the start of the epoch (e.g. from
  * hdc_hamming_argmin over all nbits).  Integer updates: the result does not
  * depend on the order rows are visited.
- *   H       [n][ldh] uint64 training hypervectors (nbits valid bits)
- *   labels  [n] int32 in [0, K)   pred [n] int32 in [0, K)
+ *   H       [n][ldh] uint64 training hypervectors (nbits valid bits),
+ *           8-byte aligned
+ *   labels  [n] int32 in [0, K)   pred [n] int32 in [0, K) (rows with a
+ *           label or prediction outside [0, K) are skipped)
  *   acc     [K][nbits] int32, written (class_acc) / updated (epoch)
  *   C       [K][ldc] uint64 output, ldc >= ceil(nbits / 64)
  *   n_wrong device int32 output (rows with pred != label), may be NULL
- * Supports K <= 128.  No workspace.
+ *   ws      >= hdc_retrain_workspace_bytes(n, nbits, K) bytes, 256-byte
+ *           aligned (one size serves both calls)
+ * Supports K <= 128 and n < 2^30.
  * ------------------------------------------------------------------- */
+size_t hdc_retrain_workspace_bytes(int64_t n, int32_t nbits, int32_t K);
 hdc_status hdc_class_acc(void *stream,
                          const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
                          const int32_t *labels, int32_t K,
-                         int32_t *acc, uint64_t *C, int64_t ldc);
+                         int32_t *acc, uint64_t *C, int64_t ldc,
+                         void *ws, size_t ws_bytes);
 hdc_status hdc_retrain_epoch(void *stream,
                              const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
                              const int32_t *labels, const int32_t *pred, int32_t K,
-                             int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong);
+                             int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong,
+                             void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
  * hdc_hamming_argmin -- Hamming distance of each query hypervector to every

@@ -155,11 +155,11 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
     return from_hip(launch_encode(a, ct, M_ENCODE, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
 }
 
-size_t hdc_bundle_workspace_bytes(int32_t nbits, int32_t K)
+size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K)
 {
-    if (nbits <= 0 || K <= 0)
+    if (n < 0 || nbits <= 0 || K <= 0 || K > kMaxK || !group_count_fits(n))
         return 0;
-    return (size_t)4 * K * ((size_t)nbits + 1);
+    return group_count_ws_bytes(0, n, nbits, K);
 }
 
 hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
@@ -168,15 +168,15 @@ hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits,
 {
     if (n < 0 || nbits <= 0 || K <= 0)
         return HDC_ERR_INVALID;
-    if (K > kMaxK)
+    if (K > kMaxK || !group_count_fits(n))
         return HDC_ERR_UNSUPPORTED;
     const int64_t W = (nbits + 63) / 64;
-    if (!C || ldc < W || (n > 0 && (!H || !labels || ldh < W)))
+    if (!C || ldc < W || (n > 0 && (!H || !labels || ldh < W || !aligned(H, 8))))
         return HDC_ERR_INVALID;
-    if (!ws || ws_bytes < hdc_bundle_workspace_bytes(nbits, K) || !aligned(ws, 4))
+    if (!ws || ws_bytes < hdc_bundle_workspace_bytes(n, nbits, K) || !aligned(ws, 256))
         return HDC_ERR_WORKSPACE;
-    return from_hip(launch_bundle(H, n, nbits, ldh, labels, K, C, ldc, counts, (int32_t *)ws,
-                                  (hipStream_t)stream));
+    return from_hip(launch_group_count(0, H, n, nbits, ldh, labels, nullptr, K, nullptr, C, ldc, counts, nullptr, ws,
+                                       (hipStream_t)stream));
 }
 
 hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C,
@@ -201,39 +201,51 @@ hdc_status hdc_hamming_argmin(void *stream, const uint64_t *Q, int64_t n, int64_
 }
 
 static hdc_status check_retrain(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh, const int32_t *labels,
-                                int32_t K, const int32_t *acc, const uint64_t *C, int64_t ldc)
+                                int32_t K, const int32_t *acc, const uint64_t *C, int64_t ldc, const void *ws,
+                                size_t ws_bytes)
 {
     if (n < 0 || nbits <= 0 || K <= 0)
         return HDC_ERR_INVALID;
-    if (K > kMaxK)
+    if (K > kMaxK || !group_count_fits(n))
         return HDC_ERR_UNSUPPORTED;
     const int64_t W = (nbits + 63) / 64;
-    if (!acc || !C || ldc < W || (n > 0 && (!H || !labels || ldh < W)))
+    if (!acc || !aligned(acc, 4) || !C || ldc < W || (n > 0 && (!H || !labels || ldh < W || !aligned(H, 8))))
         return HDC_ERR_INVALID;
+    if (!ws || ws_bytes < hdc_retrain_workspace_bytes(n, nbits, K) || !aligned(ws, 256))
+        return HDC_ERR_WORKSPACE;
     return HDC_OK;
 }
 
-hdc_status hdc_class_acc(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
-                         const int32_t *labels, int32_t K, int32_t *acc, uint64_t *C, int64_t ldc)
+size_t hdc_retrain_workspace_bytes(int64_t n, int32_t nbits, int32_t K)
 {
-    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc);
+    if (n < 0 || nbits <= 0 || K <= 0 || K > kMaxK || !group_count_fits(n))
+        return 0;
+    const size_t a = group_count_ws_bytes(1, n, nbits, K), b = group_count_ws_bytes(2, n, nbits, K);
+    return a > b ? a : b;
+}
+
+hdc_status hdc_class_acc(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                         const int32_t *labels, int32_t K, int32_t *acc, uint64_t *C, int64_t ldc, void *ws,
+                         size_t ws_bytes)
+{
+    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc, ws, ws_bytes);
     if (s != HDC_OK)
         return s;
-    return from_hip(launch_retrain(H, n, nbits, ldh, labels, nullptr, K, acc, C, ldc, nullptr,
-                                   (hipStream_t)stream));
+    return from_hip(launch_group_count(1, H, n, nbits, ldh, labels, nullptr, K, acc, C, ldc, nullptr, nullptr, ws,
+                                       (hipStream_t)stream));
 }
 
 hdc_status hdc_retrain_epoch(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
                              const int32_t *labels, const int32_t *pred, int32_t K, int32_t *acc, uint64_t *C,
-                             int64_t ldc, int32_t *n_wrong)
+                             int64_t ldc, int32_t *n_wrong, void *ws, size_t ws_bytes)
 {
-    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc);
+    const hdc_status s = check_retrain(H, n, nbits, ldh, labels, K, acc, C, ldc, ws, ws_bytes);
     if (s != HDC_OK)
         return s;
     if (n > 0 && !pred)
         return HDC_ERR_INVALID;
-    return from_hip(launch_retrain(H, n, nbits, ldh, labels, pred, K, acc, C, ldc, n_wrong,
-                                   (hipStream_t)stream));
+    return from_hip(launch_group_count(2, H, n, nbits, ldh, labels, pred, K, acc, C, ldc, nullptr, n_wrong, ws,
+                                       (hipStream_t)stream));
 }
 
 hdc_status hdc_adc_argmax(void *stream, const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int32_t K,

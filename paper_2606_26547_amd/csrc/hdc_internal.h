@@ -129,12 +129,13 @@ hipError_t launch_cos_prepared(const uint64_t *Q, int64_t n, int64_t ldq, int K,
 hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K,
                           int64_t ldc, int start, int end, int stride, int32_t *argmin,
                           int32_t *min_dist, int32_t *dists, hipStream_t st);
-hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
-                         int K, uint64_t *C, int64_t ldc, int32_t *counts, int32_t *ws_cnt,
-                         hipStream_t st);
-hipError_t launch_retrain(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
-                          const int32_t *pred, int K, int32_t *acc, uint64_t *C, int64_t ldc, int32_t *n_wrong,
-                          hipStream_t st);
+// Bundling and retraining (hdc_bundle.hip): mode 0 bundle (accumulator in
+// the workspace), 1 class accumulators, 2 one retraining epoch.
+bool group_count_fits(int64_t n);
+size_t group_count_ws_bytes(int mode, int64_t n, int nbits, int K);
+hipError_t launch_group_count(int mode, const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
+                              const int32_t *pred, int K, int32_t *acc, uint64_t *C, int64_t ldc, int32_t *counts,
+                              int32_t *n_wrong, void *ws, hipStream_t st);
 hipError_t launch_adc_argmax(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
                              int start, int end, int stride, int res, int step, int floor_, int ceil_,
                              int32_t *label, int32_t *max_score, int32_t *scores, hipStream_t st);

@@ -199,93 +199,6 @@ hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint6
 }
 
 // ---------------------------------------------------------------------------
-// Majority bundling.  Pass 1 counts, per (class, dimension), the members
-// whose bit is set, with one workgroup per (word column, row block) and
-// integer atomics (order-free, hence deterministic); pass 2 thresholds.
-// ws holds cnt[K][nbits] then nk[K] (int32), zeroed first.
-// ---------------------------------------------------------------------------
-constexpr int kBundleRows = 2048;
-
-__global__ __launch_bounds__(256) void k_fill_i32(int32_t *__restrict__ p, int64_t count, int32_t v)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
-        p[i] = v;
-}
-
-__global__ __launch_bounds__(256) void k_bundle_count(const uint64_t *__restrict__ H, int64_t n, int nbits,
-                                                      int64_t ldh, const int32_t *__restrict__ labels, int K,
-                                                      int W, int32_t *__restrict__ gcnt, int32_t *__restrict__ gnk)
-{
-    __shared__ int lcnt[kMaxK * 64];
-    __shared__ int lnk[kMaxK];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int w = blockIdx.x % W;
-    const int64_t r0 = (int64_t)(blockIdx.x / W) * kBundleRows;
-    for (int i = t; i < K * 64; i += 256)
-        lcnt[i] = 0;
-    if (t < K)
-        lnk[t] = 0;
-    __syncthreads();
-    const int64_t r1 = r0 + kBundleRows < n ? r0 + kBundleRows : n;
-    for (int64_t i = r0 + wave; i < r1; i += kWaves) {
-        const int k = labels[i];
-        if (k < 0 || k >= K)
-            continue;
-        const uint64_t x = H[i * ldh + w];
-        if ((x >> lane) & 1ull)
-            atomicAdd(&lcnt[k * 64 + lane], 1);
-        if (w == 0 && lane == 0)
-            atomicAdd(&lnk[k], 1);
-    }
-    __syncthreads();
-    for (int i = t; i < K * 64; i += 256) {
-        const int k = i >> 6, j = i & 63;
-        const int d = w * 64 + j;
-        if (d < nbits && lcnt[i])
-            atomicAdd(&gcnt[(int64_t)k * nbits + d], lcnt[i]);
-    }
-    if (w == 0 && t < K && lnk[t])
-        atomicAdd(&gnk[t], lnk[t]);
-}
-
-__global__ __launch_bounds__(256) void k_bundle_final(const int32_t *__restrict__ gcnt,
-                                                      const int32_t *__restrict__ gnk, int K, int nbits, int W,
-                                                      uint64_t *__restrict__ C, int64_t ldc,
-                                                      int32_t *__restrict__ counts)
-{
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)K * W)
-        return;
-    const int k = (int)(idx / W), w = (int)(idx % W);
-    const int nk = gnk[k];
-    uint64_t word = 0;
-    for (int j = 0; j < 64; ++j) {
-        const int d = w * 64 + j;
-        if (d < nbits && 2 * gcnt[(int64_t)k * nbits + d] > nk)
-            word |= 1ull << j;
-    }
-    C[(int64_t)k * ldc + w] = word;
-    if (w == 0 && counts)
-        counts[k] = nk;
-}
-
-hipError_t launch_bundle(const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels, int K,
-                         uint64_t *C, int64_t ldc, int32_t *counts, int32_t *ws, hipStream_t st)
-{
-    const int W = (nbits + 63) / 64;
-    const int64_t cells = (int64_t)K * nbits + K;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((cells + 255) / 256 < 4096 ? (cells + 255) / 256 : 4096)),
-                       dim3(256), 0, st, ws, cells, 0);
-    const int64_t rb = (n + kBundleRows - 1) / kBundleRows;
-    if (rb > 0)
-        hipLaunchKernelGGL(k_bundle_count, dim3((unsigned)(rb * W)), dim3(256), 0, st, H, n, nbits, ldh, labels,
-                           K, W, ws, ws + (int64_t)K * nbits);
-    hipLaunchKernelGGL(k_bundle_final, dim3((unsigned)(((int64_t)K * W + 255) / 256)), dim3(256), 0, st, ws,
-                       ws + (int64_t)K * nbits, K, nbits, W, C, ldc, counts);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Feature conversion diagnostic: the value of each feature as the encoder's
 // X loader converts it (same helpers).
 // ---------------------------------------------------------------------------

@@ -36,7 +36,8 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
-           "hdc_convert_features", "hdc_class_acc", "hdc_retrain_epoch", "hdc_adc_argmax",
+           "hdc_convert_features", "hdc_retrain_workspace_bytes", "hdc_class_acc", "hdc_retrain_epoch",
+           "hdc_adc_argmax",
            "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared",
            "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode",
            "hdc_tile_variants", "hdc_set_tile", "hdc_get_tile",
@@ -72,7 +73,7 @@ _lib.hdc_dims_count.restype = _i32
 _lib.hdc_dims_count.argtypes = [Dims]
 _lib.hdc_encode.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i64]
 _lib.hdc_bundle_workspace_bytes.restype = _sz
-_lib.hdc_bundle_workspace_bytes.argtypes = [_i32, _i32]
+_lib.hdc_bundle_workspace_bytes.argtypes = [_i64, _i32, _i32]
 _lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
 _lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, _i32, Dims, _p, _p, _p]
 _lib.hdc_hamming_workspace_bytes.restype = _sz
@@ -94,8 +95,10 @@ _lib.hdc_device_clock_hz.restype = C.c_double
 _lib.hdc_device_clock_hz.argtypes = []
 _lib.hdc_convert_features.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, C.c_int, _p]
 _lib.hdc_adc_argmax.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, Dims, Adc, _p, _p, _p]
-_lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64]
-_lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p]
+_lib.hdc_retrain_workspace_bytes.restype = _sz
+_lib.hdc_retrain_workspace_bytes.argtypes = [_i64, _i32, _i32]
+_lib.hdc_class_acc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _p, _i64, _p, _sz]
+_lib.hdc_retrain_epoch.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _p, _i64, _p, _p, _sz]
 _lib.hdc_adc_workspace_bytes.restype = _sz
 _lib.hdc_adc_workspace_bytes.argtypes = [Dims, _i32]
 _lib.hdc_adc_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
@@ -186,7 +189,7 @@ def bundle(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.
     W = words(nbits)
     Cw = torch.zeros((K, W), dtype=torch.int64, device=H.device)
     counts = torch.zeros(K, dtype=torch.int32, device=H.device)
-    need = int(_lib.hdc_bundle_workspace_bytes(nbits, K))
+    need = int(_lib.hdc_bundle_workspace_bytes(H.shape[0], nbits, K))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=H.device)
     _check(_lib.hdc_bundle(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(Cw),
@@ -429,20 +432,31 @@ def adc_argmax(Q: torch.Tensor, Cw: torch.Tensor, start: int, end: int, stride: 
     return lab, mx, sc
 
 
-def class_acc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int):
+def retrain_workspace(n: int, nbits: int, K: int, device) -> torch.Tensor:
+    """A workspace for hdc_class_acc / hdc_retrain_epoch on n rows."""
+    need = int(_lib.hdc_retrain_workspace_bytes(n, nbits, K))
+    return torch.empty(max(need, 16), dtype=torch.uint8, device=device)
+
+
+def class_acc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.Tensor | None = None):
     """hdc_class_acc: (acc[K][nbits] int32, C[K][words] int64) from training rows."""
     acc = torch.empty((K, nbits), dtype=torch.int32, device=H.device)
     Cw = torch.empty((K, words(nbits)), dtype=torch.int64, device=H.device)
+    if ws is None or ws.numel() < int(_lib.hdc_retrain_workspace_bytes(H.shape[0], nbits, K)):
+        ws = retrain_workspace(H.shape[0], nbits, K, H.device)
     _check(_lib.hdc_class_acc(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(acc),
-                              _ptr(Cw), Cw.shape[1]), "hdc_class_acc")
+                              _ptr(Cw), Cw.shape[1], _ptr(ws), ws.numel()), "hdc_class_acc")
     return acc, Cw
 
 
 def retrain_epoch(H: torch.Tensor, nbits: int, labels: torch.Tensor, pred: torch.Tensor, acc: torch.Tensor,
-                  Cw: torch.Tensor, n_wrong: torch.Tensor | None = None):
+                  Cw: torch.Tensor, n_wrong: torch.Tensor | None = None, ws: torch.Tensor | None = None):
     """hdc_retrain_epoch: updates acc and Cw in place; n_wrong (device int32[1]) if given."""
+    K = acc.shape[0]
+    if ws is None or ws.numel() < int(_lib.hdc_retrain_workspace_bytes(H.shape[0], nbits, K)):
+        ws = retrain_workspace(H.shape[0], nbits, K, H.device)
     _check(_lib.hdc_retrain_epoch(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), _ptr(pred),
-                                  acc.shape[0], _ptr(acc), _ptr(Cw), Cw.shape[1], _ptr(n_wrong)),
+                                  K, _ptr(acc), _ptr(Cw), Cw.shape[1], _ptr(n_wrong), _ptr(ws), ws.numel()),
            "hdc_retrain_epoch")
 
 

@@ -98,19 +98,52 @@ def test_validation_without_device(lib):
     assert lib.hdc_hamming_workspace_bytes(Dims(0, 10240, 1), 129) == 0
     assert lib.hdc_hamming_workspace_bytes(Dims(0, 70000, 1), 26) == 0
     lib.hdc_bundle_workspace_bytes.restype = C.c_size_t
-    assert lib.hdc_bundle_workspace_bytes(10240, 26) == 4 * 26 * 10241
+    lib.hdc_bundle_workspace_bytes.argtypes = [C.c_int64, i32, i32]
+    # class sums [K][nbits], per-block group sizes (one block up to 8192
+    # rows, then one per 4096), group cursors, group and segment offsets, the
+    # row list: each part padded to 256 bytes
+    pad = lambda b: (b + 255) // 256 * 256
+    assert lib.hdc_bundle_workspace_bytes(6238, 10240, 26) == \
+        pad(4 * 26 * 10240) + pad(4 * 26) + pad(4 * 26) + 2 * pad(4 * 27) + pad(4 * 6238)
+    assert lib.hdc_bundle_workspace_bytes(20000, 10240, 26) == \
+        pad(4 * 26 * 10240) + pad(4 * 5 * 26) + pad(4 * 26) + 2 * pad(4 * 27) + pad(4 * 20000)
+    assert lib.hdc_bundle_workspace_bytes(6238, 10240, 129) == 0
+    assert lib.hdc_bundle_workspace_bytes(1 << 30, 10240, 26) == 0
+    lib.hdc_retrain_workspace_bytes.restype = C.c_size_t
+    lib.hdc_retrain_workspace_bytes.argtypes = [C.c_int64, i32, i32]
+    # (class, sign) groups and up to two list entries per row; no class sums
+    assert lib.hdc_retrain_workspace_bytes(6238, 10240, 26) == 2 * pad(4 * 52) + 2 * pad(4 * 53) + pad(4 * 2 * 6238)
+
+
+def test_bundle_validation_without_device(lib):
+    p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.hdc_bundle.argtypes = [p, p, i64, i32, i64, p, i32, p, i64, p, p, sz]
+    fake, ws, big = C.c_void_p(1 << 20), C.c_void_p(1 << 24), 1 << 30
+    assert lib.hdc_bundle(None, fake, 4, 0, 1, fake, 3, fake, 1, None, ws, big) == 1          # nbits <= 0
+    assert lib.hdc_bundle(None, fake, 4, 64, 1, fake, 200, fake, 1, None, ws, big) == 2       # K > 128
+    assert lib.hdc_bundle(None, fake, 4, 130, 2, fake, 3, fake, 3, None, ws, big) == 1        # ldh < words
+    assert lib.hdc_bundle(None, fake, 4, 130, 3, fake, 3, fake, 2, None, ws, big) == 1        # ldc < words
+    assert lib.hdc_bundle(None, None, 4, 64, 1, fake, 3, fake, 1, None, ws, big) == 1         # no H
+    assert lib.hdc_bundle(None, fake, 4, 64, 1, fake, 3, fake, 1, None, ws, 16) == 3          # workspace
+    assert lib.hdc_bundle(None, fake, 4, 64, 1, fake, 3, fake, 1, None, C.c_void_p((1 << 24) + 8), big) == 3
+    assert lib.hdc_bundle(None, fake, 1 << 30, 64, 1, fake, 3, fake, 1, None, ws, big) == 2   # n >= 2^30
 
 
 def test_retrain_validation_without_device(lib):
     p, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
-    lib.hdc_class_acc.argtypes = [p, p, i64, i32, i64, p, i32, p, p, i64]
-    lib.hdc_retrain_epoch.argtypes = [p, p, i64, i32, i64, p, p, i32, p, p, i64, p]
+    sz = C.c_size_t
+    lib.hdc_class_acc.argtypes = [p, p, i64, i32, i64, p, i32, p, p, i64, p, sz]
+    lib.hdc_retrain_epoch.argtypes = [p, p, i64, i32, i64, p, p, i32, p, p, i64, p, p, sz]
     fake = C.c_void_p(1 << 20)
-    assert lib.hdc_class_acc(None, fake, 4, 0, 1, fake, 3, fake, fake, 1) == 1        # nbits <= 0
-    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 200, fake, fake, 1) == 2     # K > 128
-    assert lib.hdc_class_acc(None, fake, 4, 130, 2, fake, 3, fake, fake, 3) == 1      # ldh < words
-    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, None, fake, 1) == 1       # no acc
-    assert lib.hdc_retrain_epoch(None, fake, 4, 64, 1, fake, None, 3, fake, fake, 1, None) == 1   # no pred
+    ws, big = C.c_void_p(1 << 24), 1 << 30
+    assert lib.hdc_class_acc(None, fake, 4, 0, 1, fake, 3, fake, fake, 1, ws, big) == 1        # nbits <= 0
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 200, fake, fake, 1, ws, big) == 2     # K > 128
+    assert lib.hdc_class_acc(None, fake, 4, 130, 2, fake, 3, fake, fake, 3, ws, big) == 1      # ldh < words
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, None, fake, 1, ws, big) == 1       # no acc
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, fake, fake, 1, ws, 64) == 3        # workspace
+    assert lib.hdc_class_acc(None, fake, 4, 64, 1, fake, 3, fake, fake, 1, C.c_void_p((1 << 24) + 4), big) == 3
+    assert lib.hdc_class_acc(None, fake, 1 << 30, 64, 1, fake, 3, fake, fake, 1, ws, big) == 2  # n >= 2^30
+    assert lib.hdc_retrain_epoch(None, fake, 4, 64, 1, fake, None, 3, fake, fake, 1, None, ws, big) == 1  # pred
 
 
 class Adc(C.Structure):

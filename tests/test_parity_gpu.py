@@ -89,25 +89,55 @@ def test_encode_fp32_features_band(hdc, ct):
     assert flips <= 1e-3
 
 
-BUNDLE_CASES = [(1, 64, 1), (100, 100, 3), (6238, 2048, 26), (5000, 1000, 128), (300, 10240, 10)]
+# (n, nbits, K, row pitch in words or None): single-workgroup grouping up
+# to 16384 rows, multi-block above; one or two dwords per lane (8192 bits:
+# two); classes spanning several count segments (the large-n, small-K cases)
+BUNDLE_CASES = [(1, 64, 1, None), (1, 1, 1, None), (100, 100, 3, None), (6238, 2048, 26, None),
+                (5000, 1000, 128, None), (300, 10240, 10, None), (777, 130, 3, 5), (16385, 8192, 26, None),
+                (40000, 10240, 3, 161), (70001, 2048, 100, None), (0, 640, 4, None)]
 
 
 @pytest.mark.parametrize("case", BUNDLE_CASES, ids=str)
 def test_bundle_bit_exact(hdc, case):
-    n, nbits, K = case
+    n, nbits, K, ld = case
     say("bundle", case)
     g = np.random.default_rng(n + nbits)
     W = (nbits + 63) // 64
+    ld = ld or W
     bits = g.integers(0, 2, size=(n, W * 64), dtype=np.uint8)
     bits[:, nbits:] = 0
-    H = np.packbits(bits, axis=1, bitorder="little").view(np.uint64).reshape(n, W)
+    H = np.zeros((n, ld), dtype=np.uint64)
+    H[:, :W] = np.packbits(bits, axis=1, bitorder="little").view(np.uint64).reshape(n, W)
     y = g.integers(0, K, size=n).astype(np.int32)
     if K > 2:
         y[y == 1] = 0                      # class 1 empty
-    Cref, cref = O.bundle(H, y, K, nbits)
+    if n > 10:
+        y[3], y[7] = -1, K                 # rows outside [0, K) are skipped
+    keep = (y >= 0) & (y < K)              # (a precondition of the oracle)
+    Cref, cref = O.bundle(H[keep], y[keep], K, nbits)
     Cw, counts = hdc.bundle(dev(H.view(np.int64)), nbits, dev(y), K)
     torch.cuda.synchronize()
     assert np.array_equal(words_np(Cw), Cref)
+    assert np.array_equal(counts.cpu().numpy(), cref)
+
+
+def test_bundle_full_size_sampled(hdc):
+    """2^20 rows of 10240 bits, 26 classes (the bundling benchmark's shape):
+    the class words of 12 sampled word columns against the oracle's bundle of
+    those columns alone (bundling commutes with a gather of dimensions), and
+    the class sizes in full."""
+    n, nbits, K = 1 << 20, 10240, 26
+    say("bundle full size", n, nbits, K)
+    W = nbits // 64
+    Hn = np.random.default_rng(5).integers(-(1 << 63), (1 << 63) - 1, size=(n, W), dtype=np.int64)
+    Hd = dev(Hn)
+    y = np.random.default_rng(5).integers(0, K, size=n).astype(np.int32)
+    Cw, counts = hdc.bundle(Hd, nbits, dev(y), K)
+    torch.cuda.synchronize()
+    cols = np.sort(np.random.default_rng(6).choice(W, size=12, replace=False))
+    Hs = Hn[:, cols].view(np.uint64)
+    Cref, cref = O.bundle(Hs, y, K, 64 * len(cols))
+    assert np.array_equal(words_np(Cw)[:, cols], Cref)
     assert np.array_equal(counts.cpu().numpy(), cref)
 
 

@@ -22,7 +22,8 @@ def say(*a):
 
 
 @pytest.mark.parametrize("case", [(2000, 617, 2048, 26, 3), (6238, 617, 10240, 26, 2), (500, 96, 1000, 100, 2),
-                                  (300, 64, 64, 2, 4)], ids=str)
+                                  (300, 64, 64, 2, 4), (20000, 617, 4096, 26, 2), (9000, 128, 1984, 3, 2)],
+                         ids=str)
 def test_fit_matches_oracle(hdc, case):
     from paper_2606_26547_amd import train
     n, F, D, K, E = case

@@ -142,6 +142,27 @@ hdc_status hdc_bundle(void *stream,
                       void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------
+ * hdc_bundle_noalloc -- hdc_bundle for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments without the workspace, the same
+ * results bit for bit.  Scratch is a fixed array inside the library, one
+ * copy per device (held until the process ends; its address is looked up
+ * on the first call on a device, with that device current), of
+ * hdc_bundle_noalloc_limit_bytes() bytes (32 MiB): a call whose
+ * hdc_bundle_workspace_bytes(n, nbits, K) exceeds that returns
+ * HDC_ERR_UNSUPPORTED before any device work.  The call allocates nothing
+ * and clears what must start at zero itself.  Every call on a device
+ * shares that device's array: calls that may overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * The work runs on the device current at the call.
+ * ------------------------------------------------------------------- */
+size_t hdc_bundle_noalloc_limit_bytes(void);
+hdc_status hdc_bundle_noalloc(void *stream,
+                              const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                              const int32_t *labels, int32_t K,
+                              uint64_t *C, int64_t ldc, int32_t *counts);
+
+/* ---------------------------------------------------------------------
  * hdc_class_acc / hdc_retrain_epoch -- retraining (Sec. 5: the apps'
  * TRAIN_ITERATIONS knob, whose iterations the tuner cuts; the update rule
  * itself is not stated in the paper, the one implemented is the usual

@@ -28,6 +28,8 @@
 //      workgroup adds sign * (rows - 2*count) into acc with one integer
 //      atomic per dimension;
 //   3. binarise acc into the class words (one ballot per 64 dimensions).
+#include <mutex>
+
 #include "hdc_device.h"
 
 namespace hdc {
@@ -509,6 +511,40 @@ Layout layout(int mode, int64_t n, int nbits, int K)
 }
 
 }  // namespace
+
+// Scratch for callers that cannot allocate (hdc_bundle_noalloc): one array
+// per device, held until the process ends.  Host code never uses the
+// array's name as an address: the device address of each GPU's copy comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];
+}  // namespace
+
+hipError_t noalloc_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kScratchDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 // Row indices and list offsets are int32; a retraining list holds up to 2n
 // entries.

@@ -162,9 +162,8 @@ size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K)
     return group_count_ws_bytes(0, n, nbits, K);
 }
 
-hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
-                      const int32_t *labels, int32_t K, uint64_t *C, int64_t ldc, int32_t *counts, void *ws,
-                      size_t ws_bytes)
+static hdc_status check_bundle(const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh, const int32_t *labels,
+                               int32_t K, const uint64_t *C, int64_t ldc)
 {
     if (n < 0 || nbits <= 0 || K <= 0)
         return HDC_ERR_INVALID;
@@ -173,8 +172,36 @@ hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits,
     const int64_t W = (nbits + 63) / 64;
     if (!C || ldc < W || (n > 0 && (!H || !labels || ldh < W || !aligned(H, 8))))
         return HDC_ERR_INVALID;
+    return HDC_OK;
+}
+
+hdc_status hdc_bundle(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                      const int32_t *labels, int32_t K, uint64_t *C, int64_t ldc, int32_t *counts, void *ws,
+                      size_t ws_bytes)
+{
+    const hdc_status s = check_bundle(H, n, nbits, ldh, labels, K, C, ldc);
+    if (s != HDC_OK)
+        return s;
     if (!ws || ws_bytes < hdc_bundle_workspace_bytes(n, nbits, K) || !aligned(ws, 256))
         return HDC_ERR_WORKSPACE;
+    return from_hip(launch_group_count(0, H, n, nbits, ldh, labels, nullptr, K, nullptr, C, ldc, counts, nullptr, ws,
+                                       (hipStream_t)stream));
+}
+
+size_t hdc_bundle_noalloc_limit_bytes(void) { return kNoAllocScratchBytes; }
+
+hdc_status hdc_bundle_noalloc(void *stream, const uint64_t *H, int64_t n, int32_t nbits, int64_t ldh,
+                              const int32_t *labels, int32_t K, uint64_t *C, int64_t ldc, int32_t *counts)
+{
+    const hdc_status s = check_bundle(H, n, nbits, ldh, labels, K, C, ldc);
+    if (s != HDC_OK)
+        return s;
+    if (hdc_bundle_workspace_bytes(n, nbits, K) > kNoAllocScratchBytes)
+        return HDC_ERR_UNSUPPORTED;
+    void *ws = nullptr;
+    const hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess)
+        return HDC_ERR_DEVICE;
     return from_hip(launch_group_count(0, H, n, nbits, ldh, labels, nullptr, K, nullptr, C, ldc, counts, nullptr, ws,
                                        (hipStream_t)stream));
 }

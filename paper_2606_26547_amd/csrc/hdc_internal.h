@@ -133,6 +133,11 @@ hipError_t launch_hamming(const uint64_t *Q, int64_t n, int64_t ldq, const uint6
 // the workspace), 1 class accumulators, 2 one retraining epoch.
 bool group_count_fits(int64_t n);
 size_t group_count_ws_bytes(int mode, int64_t n, int nbits, int K);
+// The no-allocation bundling entry point's device scratch (hdc_bundle.hip):
+// its size, and its address on the current device (looked up on the first
+// call per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+hipError_t noalloc_scratch(void **out);
 hipError_t launch_group_count(int mode, const uint64_t *H, int64_t n, int nbits, int64_t ldh, const int32_t *labels,
                               const int32_t *pred, int K, int32_t *acc, uint64_t *C, int64_t ldc, int32_t *counts,
                               int32_t *n_wrong, void *ws, hipStream_t st);

@@ -32,7 +32,7 @@ DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP
 STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
-           "hdc_bundle", "hdc_hamming_argmin", "hdc_hamming_workspace_bytes", "hdc_hamming_prepare",
+           "hdc_bundle", "hdc_bundle_noalloc_limit_bytes", "hdc_bundle_noalloc", "hdc_hamming_argmin", "hdc_hamming_workspace_bytes", "hdc_hamming_prepare",
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
@@ -75,6 +75,9 @@ _lib.hdc_encode.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C
 _lib.hdc_bundle_workspace_bytes.restype = _sz
 _lib.hdc_bundle_workspace_bytes.argtypes = [_i64, _i32, _i32]
 _lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
+_lib.hdc_bundle_noalloc_limit_bytes.restype = _sz
+_lib.hdc_bundle_noalloc_limit_bytes.argtypes = []
+_lib.hdc_bundle_noalloc.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p]
 _lib.hdc_hamming_argmin.argtypes = [_p, _p, _i64, _i64, _p, _i32, _i64, _i32, Dims, _p, _p, _p]
 _lib.hdc_hamming_workspace_bytes.restype = _sz
 _lib.hdc_hamming_workspace_bytes.argtypes = [Dims, _i32]
@@ -194,6 +197,20 @@ def bundle(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=H.device)
     _check(_lib.hdc_bundle(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(Cw),
                            Cw.shape[1], _ptr(counts), _ptr(ws), ws.numel()), "hdc_bundle")
+    return Cw, counts
+
+
+def bundle_noalloc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, Cw: torch.Tensor | None = None,
+                   counts: torch.Tensor | None = None):
+    """hdc_bundle_noalloc: hdc_bundle on the library's own per-device
+    scratch (no workspace); fills Cw [K][words(nbits)] and counts [K] (the
+    tensors are allocated here when not given)."""
+    if Cw is None:
+        Cw = torch.zeros((K, words(nbits)), dtype=torch.int64, device=H.device)
+    if counts is None:
+        counts = torch.zeros(K, dtype=torch.int32, device=H.device)
+    _check(_lib.hdc_bundle_noalloc(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(Cw),
+                                   Cw.shape[1], _ptr(counts)), "hdc_bundle_noalloc")
     return Cw, counts
 
 

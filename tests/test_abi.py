@@ -127,6 +127,16 @@ def test_bundle_validation_without_device(lib):
     assert lib.hdc_bundle(None, fake, 4, 64, 1, fake, 3, fake, 1, None, ws, 16) == 3          # workspace
     assert lib.hdc_bundle(None, fake, 4, 64, 1, fake, 3, fake, 1, None, C.c_void_p((1 << 24) + 8), big) == 3
     assert lib.hdc_bundle(None, fake, 1 << 30, 64, 1, fake, 3, fake, 1, None, ws, big) == 2   # n >= 2^30
+    # the no-allocation form: the same checks, and a size beyond its fixed
+    # scratch is refused before any device work
+    lib.hdc_bundle_noalloc.argtypes = [p, p, i64, i32, i64, p, i32, p, i64, p]
+    lib.hdc_bundle_noalloc_limit_bytes.restype = sz
+    assert lib.hdc_bundle_noalloc_limit_bytes() == 32 << 20
+    assert lib.hdc_bundle_noalloc(None, fake, 4, 0, 1, fake, 3, fake, 1, None) == 1           # nbits <= 0
+    assert lib.hdc_bundle_noalloc(None, fake, 4, 64, 1, fake, 200, fake, 1, None) == 2        # K > 128
+    assert lib.hdc_bundle_noalloc(None, None, 4, 64, 1, fake, 3, fake, 1, None) == 1          # no H
+    assert lib.hdc_bundle_noalloc(None, fake, 1 << 24, 64, 1, fake, 3, fake, 1, None) == 2    # beyond 32 MiB
+    assert lib.hdc_bundle_noalloc(None, fake, 4, 65536, 1024, fake, 128, fake, 1024, None) == 2  # class sums
 
 
 def test_retrain_validation_without_device(lib):

@@ -110,6 +110,8 @@ int32_t hdc_dims_count(hdc_dims dims);
  * the |S| selected dimensions are computed; they are packed densely, so a
  * row holds ceil(|S|/64) words.
  *   H   [n][ldh] uint64, ldh >= ceil(|S|/64); words past that are untouched.
+ * A batch too small to fill the device spreads the dimensions over several
+ * workgroups per query block (each writes whole words of its own).
  * ------------------------------------------------------------------- */
 hdc_status hdc_encode(void *stream,
                       const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
@@ -350,26 +352,37 @@ hdc_status hdc_adc_argmax_prepared(void *stream,
  *           (as written by hdc_bundle with nbits = D)
  *   labels  [n] int32 output;  dists [n][K] int32 output, may be NULL
  *   ws      >= hdc_classify_workspace_bytes(hdc_dims_count(dims), K)
+ *   scratch optional (may be NULL), 4-byte aligned: with
+ *           hdc_classify_scratch_bytes(n, hdc_dims_count(dims), K) bytes a
+ *           batch too small to fill the device spreads its dimensions over
+ *           several workgroups per query block, which add their integer
+ *           partial sums there before a small argmin kernel (a smaller
+ *           scratch allows fewer splits; NULL or 0 bytes, none).  The
+ *           results are the same either way.  Calls sharing a scratch
+ *           must not overlap.
  * Supports K <= 128, F <= 1024.
  * ------------------------------------------------------------------- */
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K);
+size_t hdc_classify_scratch_bytes(int64_t n, int32_t n_dims, int32_t K);
 hdc_status hdc_classify(void *stream,
                         const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                         const int8_t *P, int32_t D, int64_t ldp,
                         hdc_dtype compute, hdc_dims dims,
                         const uint64_t *C, int32_t K, int64_t ldc,
                         int32_t *labels, int32_t *dists,
-                        void *ws, size_t ws_bytes);
+                        void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes);
 
 /* ---------------------------------------------------------------------
  * hdc_classify_prepare / hdc_classify_prepared -- hdc_classify split in
- * two, for resident models: _prepare gathers the class hypervectors over
- * S(dims) into the workspace once (the class operand of the fused kernel and
- * the per-class count of -1 elements); _prepared then classifies any number
- * of query batches with that workspace, launching only the fused kernel.
- * The result is identical to hdc_classify.  `ws` must stay untouched
- * between the two calls and be sized by hdc_classify_workspace_bytes();
- * K and dims must be the same in both calls.
+ * two, for resident models (Sec. 2.2 Listing 1; Sec. 4.2): _prepare
+ * gathers the class hypervectors over S(dims) into the workspace once (the
+ * class operand of the fused kernel and the per-class count of -1
+ * elements); _prepared then classifies any number of query batches with
+ * that workspace, launching only the fused kernel (plus the argmin kernel
+ * of a dimension-split launch, see `scratch` above).  The result is
+ * identical to hdc_classify.  `ws` must stay untouched between the two
+ * calls and be sized by hdc_classify_workspace_bytes(); K and dims must be
+ * the same in both calls.
  * ------------------------------------------------------------------- */
 hdc_status hdc_classify_prepare(void *stream,
                                 const uint64_t *C, int32_t K, int64_t ldc, hdc_dims dims,
@@ -379,7 +392,7 @@ hdc_status hdc_classify_prepared(void *stream,
                                  const int8_t *P, int32_t D, int64_t ldp,
                                  hdc_dtype compute, hdc_dims dims, int32_t K,
                                  int32_t *labels, int32_t *dists,
-                                 const void *ws, size_t ws_bytes);
+                                 const void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes);
 
 /* ---------------------------------------------------------------------
  * hdc_eval_configs -- one persistent launch that evaluates many

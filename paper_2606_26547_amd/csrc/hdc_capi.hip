@@ -151,6 +151,7 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
     EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
     a.H32 = (uint32_t *)H;
     a.ldh32 = 2 * ldh;
+    a.max_split = 1 << 30;   // the splits write disjoint words: no scratch
     const int v = get_tile(KK_ENCODE, xt, ct, F, 1);
     return from_hip(launch_encode(a, ct, M_ENCODE, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
 }
@@ -559,9 +560,20 @@ hdc_status hdc_classify_prepare(void *stream, const uint64_t *C, int32_t K, int6
     return from_hip(launch_class_table(C, K, ldc, dims.start, dims.stride, nd, tab, cpop, (hipStream_t)stream));
 }
 
+size_t hdc_classify_scratch_bytes(int64_t n, int32_t n_dims, int32_t K)
+{
+    if (n <= 0 || n_dims <= 0 || K <= 0 || K > kMaxK)
+        return 0;
+    // the most splits any variant takes (the largest query blocks, two
+    // resident workgroups per CU)
+    const int Z = split_count((n + kQpbMax - 1) / kQpbMax, n_dims, 1 << 30, kSplitTargetMax);
+    return Z > 1 ? (size_t)4 * Z * K * n : 0;
+}
+
 hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                                  const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
-                                 int32_t K, int32_t *labels, int32_t *dists, const void *ws, size_t ws_bytes)
+                                 int32_t K, int32_t *labels, int32_t *dists, const void *ws, size_t ws_bytes,
+                                 void *scratch, size_t scratch_bytes)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
@@ -576,6 +588,8 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
     const int32_t nd = dims_count(dims);
     if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K) || !aligned(ws, 16))
         return HDC_ERR_WORKSPACE;
+    if (scratch && !aligned(scratch, 4))
+        return HDC_ERR_WORKSPACE;
     if (n == 0)
         return HDC_OK;
     EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
@@ -584,6 +598,12 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
     a.K = K;
     a.labels = labels;
     a.dists = dists;
+    // dimension splits: as many as the scratch holds partial class sums for
+    if (scratch) {
+        const int64_t cap = (int64_t)(scratch_bytes / ((size_t)4 * K * n));
+        a.max_split = (int32_t)(cap < (1 << 30) ? cap : (1 << 30));
+        a.part = (int32_t *)scratch;
+    }
     const int v = get_tile(KK_CLASSIFY, xt, ct, F, K);
     return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
 }
@@ -591,7 +611,7 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
 hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                         const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
                         const uint64_t *C, int32_t K, int64_t ldc, int32_t *labels, int32_t *dists, void *ws,
-                        size_t ws_bytes)
+                        size_t ws_bytes, void *scratch, size_t scratch_bytes)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
@@ -613,7 +633,7 @@ hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n
     if (s != HDC_OK)
         return s;
     return hdc_classify_prepared(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, K, labels, dists, ws,
-                                 ws_bytes);
+                                 ws_bytes, scratch, scratch_bytes);
 }
 
 size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)

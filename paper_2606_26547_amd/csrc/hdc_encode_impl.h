@@ -7,6 +7,12 @@
 
 namespace hdc {
 
+// Grid (query block, dimension split).  Split z of Z takes the whole
+// 64-dimension words [z * per, (z + 1) * per) of the dimension list: its
+// projection rows, its half-words of the packed output and its part of the
+// class operand.  In classify mode every split adds its own part of the
+// class sums, so a split launch writes them to part[z][n][K] and
+// k_split_argmin finishes.
 template <int CT, int XF, int QT, int KS, int KT, int MODE, bool DMA, int RT>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT>::WAVES)))
@@ -15,12 +21,42 @@ void k_encode(EncodeArgs a)
     typedef Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT> E;
     __shared__ __align__(16) uint8_t smem[E::LDS];
     const int64_t qblock = (int64_t)blockIdx.x * E::QPB;
+    const int Z = gridDim.y, z = blockIdx.y;
+    if (Z > 1) {
+        const int per = split_units(a.nd, Z);
+        const int d0 = 64 * z * per;                    // first dimension (list index) of the split
+        const int nd = a.nd - d0 < 64 * per ? a.nd - d0 : 64 * per;
+        a.s0 += d0 * a.stride;
+        a.nd = nd;
+        if constexpr (MODE == M_ENCODE)
+            a.H32 += d0 / 32;
+        else
+            a.ctab += (int64_t)(d0 / 32) * KT * 1024;
+    }
     v16i dacc[KT][QT];
     E::run(a, smem, qblock, dacc);
     if constexpr (MODE == M_CLASSIFY) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (Z > 1) {
+            const int g = lane >> 5;
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt) {
+                const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
+                if (q >= a.n)
+                    continue;
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int k = kt * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+                        if (k < a.K)
+                            a.part[((int64_t)z * a.n + q) * a.K + k] = dacc[kt][qt][v];
+                    }
+            }
+            return;
+        }
         int32_t lab[QT];
         E::finish(a, qblock, dacc, lab);
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt) {
             const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
@@ -30,13 +66,59 @@ void k_encode(EncodeArgs a)
     }
 }
 
+// Distances and argmin of a split classify launch: one wave per query,
+// lane k (and k + 64) sums class k's partials over the splits, dist_k =
+// popc_k - sum; the first smallest distance wins, as in Encoder::finish.
+static __global__ __launch_bounds__(256) void k_split_argmin(EncodeArgs a, int Z)
+{
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= a.n)
+        return;
+    int bd = 0x7fffffff, bk = 0;
+    for (int k0 = 0; k0 < a.K; k0 += 64) {
+        const int k = k0 + lane;
+        const bool kv = k < a.K;
+        int s = 0;
+        if (kv) {
+            const int32_t *p = a.part + q * a.K + k;
+            const int64_t zs = a.n * a.K;
+#pragma unroll 8
+            for (int z = 0; z < Z; ++z)
+                s += p[z * zs];
+        }
+        const int d = kv ? a.cpop[k] - s : 0x7fffffff;
+        if (kv && a.dists)
+            a.dists[q * a.K + k] = d;
+        if (d < bd) {
+            bd = d;
+            bk = k;
+        }
+    }
+    // first minimum across the lanes (lower class index on ties)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int od = __shfl_xor(bd, o), ok = __shfl_xor(bk, o);
+        if (od < bd || (od == bd && ok < bk)) {
+            bd = od;
+            bk = ok;
+        }
+    }
+    if (lane == 0)
+        a.labels[q] = bk;
+}
+
 template <int CT, int XF, int QT, int KS, int KT, int MODE, bool DMA = false, int RT = 1>
 static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
 {
     typedef Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT> E;
     const int64_t blocks = (a.n + E::QPB - 1) / E::QPB;
-    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE, DMA, RT>), dim3((unsigned)blocks), dim3(256), 0, st,
-                       a);
+    // resident workgroups: one per CU per wave per SIMD the kernel is built for
+    const int Z = split_count(blocks, a.nd, a.max_split, 256 * E::WAVES);
+    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE, DMA, RT>), dim3((unsigned)blocks, (unsigned)Z), dim3(256),
+                       0, st, a);
+    if (MODE == M_CLASSIFY && Z > 1)
+        hipLaunchKernelGGL(k_split_argmin, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, st, a, Z);
     return hipGetLastError();
 }
 

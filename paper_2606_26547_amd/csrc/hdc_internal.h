@@ -37,7 +37,37 @@ struct EncodeArgs {
     int32_t K;
     int32_t *labels;       // [n]
     int32_t *dists;        // [n][K] or null
+    // dimension splits: a launch whose query blocks cannot fill the device
+    // spreads the dimension list over gridDim.y workgroups per query block
+    // (at most max_split; 0 or 1 = none).  Classify partials go to
+    // part[split][K][n] (int32), then a small kernel takes the argmin.
+    int32_t max_split;
+    int32_t *part;
 };
+
+// Dimension splits of an encoder launch with `blocks` query blocks over nd
+// dimensions: as many as keep blocks * splits within `target` workgroups
+// (the device's resident workgroups for the kernel: one round, no tail),
+// each split at least kSplitMinUnits whole 64-dimension words, at most `cap`
+// (1 = no split).  The kernel maps split z of Z to words [z*per, (z+1)*per)
+// with per = split_units(nd, Z) = ceil(words / Z); the count returned is
+// ceil(words / per), so that no split is empty.
+constexpr int kSplitMinUnits = 4;
+constexpr int kQpbMax = 256;        // most queries per encoder workgroup (any variant)
+constexpr int kSplitTargetMax = 512;   // two resident workgroups per CU at most
+__host__ __device__ inline int split_count(int64_t blocks, int nd, int cap, int target)
+{
+    const int units = (nd + 63) / 64;
+    if (blocks <= 0 || 2 * blocks > target || units < 2 * kSplitMinUnits || cap < 2)
+        return 1;
+    int64_t z = target / blocks;
+    const int zmax = units / kSplitMinUnits;
+    z = z < zmax ? z : zmax;
+    z = z < cap ? z : cap;
+    const int per = (int)((units + z - 1) / z);
+    return (units + per - 1) / per;
+}
+__host__ __device__ inline int split_units(int nd, int Z) { return ((nd + 63) / 64 + Z - 1) / Z; }
 
 // Mode of the encode kernel.
 enum Mode : int { M_ENCODE = 0, M_CLASSIFY = 1 };

@@ -33,7 +33,7 @@ STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_E
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
            "hdc_bundle", "hdc_bundle_noalloc_limit_bytes", "hdc_bundle_noalloc", "hdc_hamming_argmin", "hdc_hamming_workspace_bytes", "hdc_hamming_prepare",
-           "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify",
+           "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify_scratch_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
            "hdc_eval_configs_workspace_bytes", "hdc_eval_configs", "hdc_device_clock_hz",
            "hdc_convert_features", "hdc_retrain_workspace_bytes", "hdc_class_acc", "hdc_retrain_epoch",
@@ -85,11 +85,13 @@ _lib.hdc_hamming_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_hamming_argmin_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, _p, _p, _p, _p, _sz]
 _lib.hdc_classify_workspace_bytes.restype = _sz
 _lib.hdc_classify_workspace_bytes.argtypes = [_i32, _i32]
+_lib.hdc_classify_scratch_bytes.restype = _sz
+_lib.hdc_classify_scratch_bytes.argtypes = [_i64, _i32, _i32]
 _lib.hdc_classify.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i32,
-                              _i64, _p, _p, _p, _sz]
+                              _i64, _p, _p, _p, _sz, _p, _sz]
 _lib.hdc_classify_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_classify_prepared.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _i32,
-                                       _p, _p, _p, _sz]
+                                       _p, _p, _p, _sz, _p, _sz]
 _lib.hdc_eval_configs_workspace_bytes.restype = _sz
 _lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32]
 _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
@@ -388,10 +390,22 @@ def classify_workspace_bytes(n_dims: int, K: int) -> int:
     return int(_lib.hdc_classify_workspace_bytes(n_dims, K))
 
 
+def classify_scratch(n: int, nd: int, K: int, device, have: torch.Tensor | None = None):
+    """Scratch for the dimension-split classify of n queries (None when the
+    batch fills the device by itself); `have` is reused when large enough."""
+    need = int(_lib.hdc_classify_scratch_bytes(n, nd, K))
+    if need == 0:
+        return None
+    if have is not None and have.numel() >= need:
+        return have
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
 def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, compute="int8", start=0,
              d_trunc=None, stride=1, with_dists=False, ws: torch.Tensor | None = None,
-             labels: torch.Tensor | None = None):
-    """hdc_classify: fused encode + Hamming + argmin under one configuration."""
+             labels: torch.Tensor | None = None, split: bool = True):
+    """hdc_classify: fused encode + Hamming + argmin under one configuration
+    (split=False: no dimension splits for small batches)."""
     d_trunc = D if d_trunc is None else d_trunc
     n, K = X.shape[0], Cw.shape[0]
     nd = dims_count(start, d_trunc, stride)
@@ -401,15 +415,19 @@ def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor,
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=X.device)
     dists = torch.empty((n, K), dtype=torch.int32, device=X.device) if with_dists else None
+    sc = classify_scratch(n, nd, K, X.device) if split else None
     _check(_lib.hdc_classify(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
                              DTYPE[compute], Dims(start, d_trunc, stride), _ptr(Cw), K, Cw.shape[1],
-                             _ptr(labels), _ptr(dists), _ptr(ws), ws.numel()), "hdc_classify")
+                             _ptr(labels), _ptr(dists), _ptr(ws), ws.numel(), _ptr(sc),
+                             sc.numel() if sc is not None else 0), "hdc_classify")
     return (labels, dists) if with_dists else labels
 
 
 class Prepared:
     """Class operand of one (model, configuration) kept on the device, so that
-    repeated classification launches only the fused kernel."""
+    repeated classification launches only the fused kernel.  Holds the
+    dimension-split scratch of the largest small batch seen (calls through
+    one Prepared object are ordered on the stream they are issued on)."""
 
     def __init__(self, Cw: torch.Tensor, D: int, compute="int8", start=0, d_trunc=None, stride=1):
         self.D, self.K = D, Cw.shape[0]
@@ -419,20 +437,27 @@ class Prepared:
         self.nd = dims_count(start, self.d_trunc, stride)
         need = classify_workspace_bytes(self.nd, self.K)
         self.ws = torch.empty(max(need, 16), dtype=torch.uint8, device=Cw.device)
+        self.scratch = None
         _check(_lib.hdc_classify_prepare(_stream(), _ptr(Cw), self.K, Cw.shape[1],
                                          Dims(start, self.d_trunc, stride), _ptr(self.ws), self.ws.numel()),
                "hdc_classify_prepare")
 
     def __call__(self, X: torch.Tensor, F: int, P: torch.Tensor, labels: torch.Tensor | None = None,
-                 with_dists=False):
+                 with_dists=False, split: bool = True):
         n = X.shape[0]
         if labels is None:
             labels = torch.empty(n, dtype=torch.int32, device=X.device)
         dists = torch.empty((n, self.K), dtype=torch.int32, device=X.device) if with_dists else None
+        sc = None
+        if split:
+            sc = classify_scratch(n, self.nd, self.K, X.device, self.scratch)
+            if sc is not None:
+                self.scratch = sc
         _check(_lib.hdc_classify_prepared(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), self.D,
                                           P.shape[1], DTYPE[self.compute],
                                           Dims(self.start, self.d_trunc, self.stride), self.K, _ptr(labels),
-                                          _ptr(dists), _ptr(self.ws), self.ws.numel()),
+                                          _ptr(dists), _ptr(self.ws), self.ws.numel(), _ptr(sc),
+                                          sc.numel() if sc is not None else 0),
                "hdc_classify_prepared")
         return (labels, dists) if with_dists else labels
 

@@ -72,9 +72,23 @@ def test_validation_without_device(lib):
     assert lib.hdc_encode(None, fake, 0, 1, 1000, 1024, fake, big_d, 1024, 0, Dims(0, 64, 1), fake, 1) == 2
     assert lib.hdc_encode(None, fake, 0, 1, 1000, 1024, fake, big_d - 2, 1024, 0, Dims(0, 64, 1), None, 1) == 1
     lib.hdc_classify.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, p, i32, i64, p, p, p,
-                                 C.c_size_t]
+                                 C.c_size_t, p, C.c_size_t]
     assert lib.hdc_classify(None, fake, 0, 1, 1000, 1024, fake, big_d, 1024, 0, Dims(0, 64, 1), fake, 3, 1, fake,
-                            None, fake, 1 << 20) == 2
+                            None, fake, 1 << 20, None, 0) == 2
+    # a misaligned dimension-split scratch is refused
+    lib.hdc_classify_prepared.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, i32, p, p, p,
+                                          C.c_size_t, p, C.c_size_t]
+    assert lib.hdc_classify_prepared(None, fake, 0, 1, 64, 64, fake, 64, 64, 0, Dims(0, 64, 1), 3, fake, None,
+                                     fake, 1 << 20, C.c_void_p((1 << 20) + 2), 1 << 20) == 3
+    # scratch sizes: a batch that fills the device by its query blocks alone
+    # needs none; 1559 queries of 10240 dimensions split the dimensions into
+    # 40 parts of four words (the most the words allow), each holding K
+    # partial sums per query
+    lib.hdc_classify_scratch_bytes.restype = C.c_size_t
+    lib.hdc_classify_scratch_bytes.argtypes = [i64, i32, i32]
+    assert lib.hdc_classify_scratch_bytes(1 << 18, 10240, 26) == 0
+    assert lib.hdc_classify_scratch_bytes(1559, 10240, 26) == 4 * 40 * 26 * 1559
+    assert lib.hdc_classify_scratch_bytes(1559, 448, 26) == 0          # too few words to split
     lib.hdc_eval_configs.argtypes = [p, p, C.c_int, i64, i32, i64, p, p, i32, i64, p, i32, i64, p, i32, p, p,
                                      C.c_size_t, i32]
     assert lib.hdc_eval_configs(None, fake, 0, 1, 1000, 1024, fake, fake, big_d, 1024, fake, 3, big_d // 64, fake,

@@ -186,8 +186,10 @@ def main():
     ws_b = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(Xtr.shape[0], D, K), dtype=torch.uint8, device=dev)
     Htr = torch.zeros((Xtr.shape[0], hdc.words(D)), dtype=torch.int64, device=dev)
 
+    tiles_in_use = {"encode": 0}
+
     def train():
-        hdc.encode(Xtr, F, Pd, D, "int8", out=Htr)
+        hdc.encode(Xtr, F, Pd, D, "int8", out=Htr, tile=tiles_in_use["encode"])
         return hdc.bundle(Htr, D, ytr, K, ws_b)
 
     Cw, _ = train()
@@ -217,14 +219,17 @@ def main():
                    AT.Shape("sweep", F, K, D, dg.C4["n_queries"], cfgs=slots)]
     t0 = time.time()
     tiles = AT.autotune(tile_shapes) if not args.no_autotune else []
-    cls_tile = hdc.TILE_NAMES["classify"][hdc.get_tile("classify", "int8", "int8", F, K) or
-                                          hdc.tile_variants("classify", "int8", "int8", F, K)[0]]
+    table = AT.TileTable.from_choices(tiles)
+    cls_tile_id = table.get("classify", "int8", "int8", F, K)
+    tiles_in_use["encode"] = table.get("encode", "int8", "int8", F, 1)
+    sweep_tile = table.get("sweep", "int8", "int8", F, K)
+    cls_tile = hdc.TILE_NAMES["classify"][cls_tile_id or hdc.tile_variants("classify", "int8", "int8", F, K)[0]]
     log("tiles (%.1fs): %s" % (time.time() - t0, {c.shape.kind: (c.chosen_name, {k: round(v, 3) for k, v in
                                                                                  c.variants.items()})
                                                   for c in tiles}))
 
     # ------------------------------------------------------------ plain steps
-    plain = hdc.Prepared(Cw, D, "int8")
+    plain = hdc.Prepared(Cw, D, "int8", tile=cls_tile_id)
     labels = torch.empty(N, dtype=torch.int32, device=dev)
     ms_step, ms_kernel, _ = event_loop(lambda: plain(Xqd, F, Pd, labels), args.steps, args.warmup)
     acc_plain = float((labels == yqd).float().mean().item())
@@ -272,20 +277,25 @@ def main():
         out["bundle"] = bundle_bench(dev, hdc, torch, event_loop)
         # -------------------------------------------------------- sweep + tuned selection
         grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
-        tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)                  # warm-up launch
+        tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots, tile=sweep_tile)   # warm-up launch
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots)
+        res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots, tile=sweep_tile)
         sweep_wall_ms = (time.perf_counter() - t) * 1e3
-        # device time of the launch (slot setup, class operands, persistent
-        # kernel) with events on the launch stream
-        _, sweep_ms, _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, slots), 5, 1)
+        # device time of the launch (configurations up, slot setup, class
+        # operands, persistent kernel, results down into pinned memory) with
+        # events on the launch stream
+        sweep_out = torch.empty(16 * len(slots), dtype=torch.uint8, pin_memory=True)
+        ws_sw = torch.empty(hdc.lib().hdc_eval_configs_workspace_bytes(len(slots), D, K), dtype=torch.uint8,
+                            device=dev)
+        _, sweep_ms, _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, slots, ws=ws_sw,
+                                                             tile=sweep_tile, out=sweep_out), 5, 1)
         # algorithmic encode work of the 256 slots: 2 F |S| per query
         sweep_ops = sum(2.0 * F * hdc.dims_count(s_, d_, k_) * Xsd.shape[0] for (d_, k_, s_, _) in slots)
-        grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid)
+        grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid, tile=sweep_tile)
         best, plain_r = tuner.select_tuned(
             grid_res, (D, 1, 0, "int8"), 1.0,
-            timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw))
+            timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw, tile=cls_tile_id))
         out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
                         "ms": sweep_ms, "wall_ms": sweep_wall_ms, "one_launch": True,
                         "roofline": {"bound": "mfma", "achieved": sweep_ops / (sweep_ms / 1e3) / 1e12,
@@ -295,7 +305,7 @@ def main():
                                      "note": "sum over slots of 2 F |S| x queries (int8 peak for every "
                                              "slot dtype; bf16 slots run at half that rate)"}}
         d, k, s, tdt = best.cfg
-        tuned = hdc.Prepared(Cw, D, tdt, s, d, k)
+        tuned = hdc.Prepared(Cw, D, tdt, s, d, k, tile=cls_tile_id if tdt == "int8" else 0)
         tl = torch.empty(N, dtype=torch.int32, device=dev)
         ms_t, ms_tk, _ = event_loop(lambda: tuned(Xqd, F, Pd, tl), args.steps, args.warmup)
         acc_t = float((tl == yqd).float().mean().item())

@@ -118,6 +118,14 @@ hdc_status hdc_encode(void *stream,
                       const int8_t *P, int32_t D, int64_t ldp,
                       hdc_dtype compute, hdc_dims dims,
                       uint64_t *H, int64_t ldh);
+/* hdc_encode with the kernel shape named (a tile variant of the encode
+ * bucket, see hdc_tile_variants; 0 = the built-in rule, as hdc_encode);
+ * a variant the bucket is not compiled with gives HDC_ERR_UNSUPPORTED. */
+hdc_status hdc_encode_tiled(void *stream,
+                            const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                            const int8_t *P, int32_t D, int64_t ldp,
+                            hdc_dtype compute, hdc_dims dims,
+                            uint64_t *H, int64_t ldh, int32_t tile);
 
 /* ---------------------------------------------------------------------
  * hdc_bundle -- class bundling (Sec. 2.1: same-class hypervectors are
@@ -360,6 +368,9 @@ hdc_status hdc_adc_argmax_prepared(void *stream,
  *           scratch allows fewer splits; NULL or 0 bytes, none).  The
  *           results are the same either way.  Calls sharing a scratch
  *           must not overlap.
+ *   tile    the kernel shape: a tile variant of the classify bucket (see
+ *           hdc_tile_variants) or 0 for the built-in rule; a variant the
+ *           bucket is not compiled with gives HDC_ERR_UNSUPPORTED
  * Supports K <= 128, F <= 1024.
  * ------------------------------------------------------------------- */
 size_t hdc_classify_workspace_bytes(int32_t n_dims, int32_t K);
@@ -370,7 +381,7 @@ hdc_status hdc_classify(void *stream,
                         hdc_dtype compute, hdc_dims dims,
                         const uint64_t *C, int32_t K, int64_t ldc,
                         int32_t *labels, int32_t *dists,
-                        void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes);
+                        void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes, int32_t tile);
 
 /* ---------------------------------------------------------------------
  * hdc_classify_prepare / hdc_classify_prepared -- hdc_classify split in
@@ -392,7 +403,8 @@ hdc_status hdc_classify_prepared(void *stream,
                                  const int8_t *P, int32_t D, int64_t ldp,
                                  hdc_dtype compute, hdc_dims dims, int32_t K,
                                  int32_t *labels, int32_t *dists,
-                                 const void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes);
+                                 const void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes,
+                                 int32_t tile);
 
 /* ---------------------------------------------------------------------
  * hdc_eval_configs -- one persistent launch that evaluates many
@@ -401,16 +413,26 @@ hdc_status hdc_classify_prepared(void *stream,
  * back its quality of service and time (Sec. 3, Sec. 4.1).  For every
  * configuration c, the queries are classified exactly as hdc_classify with
  * dims {cfg.start, cfg.d_trunc, cfg.stride} and compute = cfg.dtype, and
- *     out[c].correct = #{i : label_i == truth[i]}
- *     out[c].ticks   = sum over c's work items of device wall-clock ticks
- * (ticks / hdc_device_clock_hz() seconds of device time; several items run
- * concurrently, so this is busy time, not elapsed time).  A configuration
- * with an unsupported dtype or an empty / out-of-range dimension set does no
- * work and reports n = 0.  Work is scheduled longest configuration first.
+ *     out[c].correct   = #{i : label_i == truth[i]}
+ *     out[c].n         = n (0 for a configuration that does no work)
+ *     out[c].device_us = device wall-clock time summed over c's work items
+ * (several items run concurrently, so this is busy time, not elapsed time).
+ * A configuration with an unsupported dtype or an empty / out-of-range
+ * dimension set does no work and reports n = 0.  Work is scheduled longest
+ * configuration first.
  *   X      integer features only (HDC_INT8 / HDC_UINT8); F <= 1024
- *   truth  [n] int32 true labels
- *   cfgs   [ncfg] hdc_config, device memory; ncfg <= 4096
- *   out    [ncfg] hdc_config_result, device memory, overwritten
+ *   truth  [n] int32 true labels (device)
+ *   cfgs   [ncfg] hdc_config, HOST memory, read before the call returns;
+ *          ncfg <= 4096.  tile_id: the work-item shape of that
+ *          configuration, a sweep variant of the (x_type, F, K) bucket
+ *          (HDC_TILE_SWEEP_*; see hdc_tile_variants) or 0 for the built-in
+ *          one (items of 256 queries); a variant the bucket is not compiled
+ *          with, or a negative id, gives HDC_ERR_UNSUPPORTED before any
+ *          device work
+ *   out    [ncfg] hdc_config_result, HOST memory, overwritten; valid once
+ *          the stream has passed the call (into page-locked memory the copy
+ *          is asynchronous; into pageable memory the call returns only
+ *          after the results have arrived)
  *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, D, K), 256-byte aligned
  *   max_workgroups  0: as many workgroups as fit on the device at once;
  *          otherwise at most this many (a configuration job that shares
@@ -420,12 +442,13 @@ hdc_status hdc_classify_prepared(void *stream,
 typedef struct {
     int32_t d_trunc, stride, start;
     int32_t dtype;          /* hdc_dtype compute type */
+    int32_t tile_id;        /* HDC_TILE_SWEEP_* or 0 */
 } hdc_config;
 
 typedef struct {
     int32_t correct;
     int32_t n;
-    uint64_t ticks;
+    double device_us;
 } hdc_config_result;
 
 size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
@@ -439,14 +462,15 @@ hdc_status hdc_eval_configs(void *stream,
                             void *ws, size_t ws_bytes, int32_t max_workgroups);
 
 /* ---------------------------------------------------------------------
- * Tile table -- the kernel shape each launch uses, for an autotuner that
- * times the variants of a shape on the device and keeps the fastest (the
- * sweep of approximation configurations, and the encoder and classifier,
- * run with tiles picked this way).  A bucket is (kind, x_type, compute,
- * the compiled feature width the launch uses for F, the class tiles of K:
- * 1, 2 or 4 for K <= 32, 64, 128; the sweep compiles 1 or 4).  Every
- * variant of a bucket computes identical results; only the time differs.
- *   kind      HDC_KERNEL_ENCODE (hdc_encode), HDC_KERNEL_CLASSIFY
+ * Tile variants -- the kernel shapes each launch can take, for an autotuner
+ * that times the variants of a shape on the device and then names the
+ * fastest in each call (hdc_encode_tiled, hdc_classify(_prepared), the
+ * tile_id of each hdc_eval_configs configuration).  The library holds no
+ * mutable tile state.  A bucket is (kind, x_type, compute, the compiled
+ * feature width the launch uses for F, the class tiles of K: 1, 2 or 4 for
+ * K <= 32, 64, 128; the sweep compiles 1 or 4).  Every variant of a bucket
+ * computes identical results; only the time differs.
+ *   kind      HDC_KERNEL_ENCODE (hdc_encode_tiled), HDC_KERNEL_CLASSIFY
  *             (hdc_classify, hdc_classify_prepared), HDC_KERNEL_SWEEP
  *             (hdc_eval_configs; compute is ignored, x_type is the
  *             feature type of the job)
@@ -455,20 +479,15 @@ hdc_status hdc_eval_configs(void *stream,
  *             dimension tiles per wave, or one of each; int8 features on the
  *             int8 path), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
  *             staging, two or one query tiles of 32 per wave);
- *             sweep: HDC_TILE_SWEEP_128 (work items of 128 queries),
- *             HDC_TILE_SWEEP_256 (items of 256: int8 slots take two query
- *             tiles per wave where the registers allow) and
- *             HDC_TILE_SWEEP_256_DMA (items of 256, int8-feature int8 slots
- *             on the classifier's HDC_TILE_DMA_2X2 body; int8 features,
- *             K <= 32, F <= 640)
+ *             sweep: HDC_TILE_SWEEP_256 (work items of 256 queries: int8
+ *             configurations take two query tiles per wave where the
+ *             registers allow), HDC_TILE_SWEEP_128 (items of 128) and
+ *             HDC_TILE_SWEEP_256_DMA (items of 256, int8-feature int8
+ *             configurations on the classifier's HDC_TILE_DMA_2X2 body;
+ *             int8 features, K <= 32, F <= 640)
  * hdc_tile_variants writes up to `cap` (host array) variant ids the bucket
  * is compiled with, the built-in choice first, and returns how many there
- * are, or -1 for a shape outside the compiled kernels.  hdc_set_tile sets
- * the bucket's variant, 0 restoring the built-in choice; a variant the
- * bucket does not have gives HDC_ERR_UNSUPPORTED, a shape outside the
- * compiled kernels HDC_ERR_INVALID.  The table is process-wide and read at
- * each launch (no stream ordering: set it before enqueuing the launches it
- * is meant for).  hdc_get_tile returns the bucket's variant, or -1.
+ * are, or -1 for a shape outside the compiled kernels.
  * ------------------------------------------------------------------- */
 typedef enum {
     HDC_KERNEL_ENCODE = 0,
@@ -488,11 +507,9 @@ enum {
 
 int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
                           int32_t *variants, int32_t cap);
-hdc_status hdc_set_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
-                        int32_t variant);
-int32_t hdc_get_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K);
 
-/* Frequency in Hz of the device wall clock that hdc_eval_configs reads. */
+/* Frequency in Hz of the device wall clock (the one hdc_eval_configs times
+ * work items with). */
 double hdc_device_clock_hz(void);
 
 /* ---------------------------------------------------------------------

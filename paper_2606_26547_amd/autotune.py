@@ -1,8 +1,8 @@
 """Tile autotuner: times every compiled tile variant of the kernels a
 workload launches, on the device, and keeps the fastest per bucket.
 
-A bucket is what one entry of the library's tile table covers: (kind,
-feature type, compute type, compiled feature width, class tiles).  For each
+A bucket is what one set of compiled variants covers: (kind, feature type,
+compute type, compiled feature width, class tiles).  For each
 shape, ``tune`` builds seeded synthetic operands of that shape (features,
 +-1 projection rows, class hypervectors, for the sweep a configuration
 list), runs every variant after a warm-up, checks that its result equals
@@ -10,9 +10,11 @@ the built-in variant's (every variant computes the same labels, encodings
 or counts; a variant that differs is an error, not a candidate) and takes
 the mean device time over ``reps`` launches.  A variant replaces the
 built-in one only when it is faster by more than ``margin``.  ``autotune``
-tunes a list of shapes and installs the choices with hdc_set_tile;
-``save`` / ``load`` keep the table as JSON together with the device name,
-and ``load`` refuses a table measured on another device.
+tunes a list of shapes; a ``TileTable`` holds the choices (read-only once
+built) and the caller passes the chosen variant with each launch (the
+library keeps no tile state).  ``save`` / ``load`` keep the table as JSON
+together with the device name, and ``load`` refuses a table measured on
+another device.
 """
 from __future__ import annotations
 
@@ -79,47 +81,48 @@ def _operands(sh: Shape, seed: int):
 
 
 def tune(sh: Shape, reps: int = 5, margin: float = 0.03, seed: int = 1) -> Choice:
-    """Time every variant of the bucket of ``sh`` and install the fastest."""
+    """Time every variant of the bucket of ``sh``; the choice is returned."""
     variants = hdc.tile_variants(sh.kind, sh.x_type, sh.compute, sh.F, sh.K)
     names = hdc.TILE_NAMES[sh.kind]
     X, P, C = _operands(sh, seed)
     if sh.kind == "classify":
         prep = hdc.Prepared(C, sh.D, sh.compute)
         lab = torch.empty(sh.n, dtype=torch.int32, device="cuda")
-        run = lambda: prep(X, sh.F, P, lab)                                      # noqa: E731
+
+        def run(v):
+            prep.tile = v
+            prep(X, sh.F, P, lab)
         result = lambda: lab.clone()                                             # noqa: E731
     elif sh.kind == "encode":
         H = torch.empty((sh.n, (sh.D + 63) // 64), dtype=torch.int64, device="cuda")
-        run = lambda: hdc.encode(X, sh.F, P, sh.D, sh.compute, out=H)            # noqa: E731
+        run = lambda v: hdc.encode(X, sh.F, P, sh.D, sh.compute, out=H, tile=v)  # noqa: E731
         result = lambda: H.clone()                                               # noqa: E731
     else:
         truth = torch.randint(0, sh.K, (sh.n,), dtype=torch.int32, device="cuda")
         ws = torch.empty(int(hdc.lib().hdc_eval_configs_workspace_bytes(len(sh.cfgs), sh.D, sh.K)),
                          dtype=torch.uint8, device="cuda")
-        box = {}
+        out = torch.empty(16 * len(sh.cfgs), dtype=torch.uint8, pin_memory=True)
+        cfgs = [tuple(c[:4]) for c in sh.cfgs]
 
-        def run():
-            box["c"] = hdc.eval_configs(X, sh.F, truth, P, sh.D, C, sh.cfgs, ws=ws)[0]
-        result = lambda: box["c"].clone()                                        # noqa: E731
+        def run(v):
+            hdc.eval_configs(X, sh.F, truth, P, sh.D, C, cfgs, ws=ws, tile=v, out=out)
+        result = lambda: torch.as_tensor(hdc.result_view(out, len(cfgs))["correct"].copy())  # noqa: E731
     ch = Choice(shape=sh)
     ref = None
     times = {}
     for v in variants:
-        hdc.set_tile(sh.kind, sh.x_type, sh.compute, sh.F, sh.K, v)
-        run()
+        run(v)
         torch.cuda.synchronize()
-        out = result()
+        res = result()
         if ref is None:
-            ref = out
-        elif not torch.equal(out, ref):
-            hdc.set_tile(sh.kind, sh.x_type, sh.compute, sh.F, sh.K, 0)
+            ref = res
+        elif not torch.equal(res, ref):
             raise RuntimeError("tile variant %s of %s gives a different result" % (names[v], sh))
-        times[v] = _events(run, reps)
+        times[v] = _events(lambda: run(v), reps)
     best = min(times, key=times.get)
     default = variants[0]
     if times[best] > times[default] * (1 - margin):
         best = default
-    hdc.set_tile(sh.kind, sh.x_type, sh.compute, sh.F, sh.K, best)
     ch.variants = {names[v]: times[v] for v in variants}
     ch.chosen, ch.chosen_name, ch.default_name = best, names[best], names[default]
     return ch
@@ -127,6 +130,26 @@ def tune(sh: Shape, reps: int = 5, margin: float = 0.03, seed: int = 1) -> Choic
 
 def autotune(shapes: list[Shape], reps: int = 5, margin: float = 0.03) -> list[Choice]:
     return [tune(sh, reps, margin) for sh in shapes]
+
+
+class TileTable:
+    """Chosen variants keyed by (kind, x_type, compute, F, K); 0 (the
+    built-in rule) for a shape that was not tuned.  Built once, then only
+    read: the caller passes ``get(...)`` with each launch."""
+
+    def __init__(self, entries: dict | None = None):
+        self._t = dict(entries or {})
+
+    @classmethod
+    def from_choices(cls, choices: list[Choice]) -> "TileTable":
+        return cls({(c.shape.kind, c.shape.x_type, c.shape.compute, c.shape.F, c.shape.K): c.chosen
+                    for c in choices})
+
+    def get(self, kind: str, x_type: str, compute: str, F: int, K: int) -> int:
+        return self._t.get((kind, x_type, compute, F, K), 0)
+
+    def __len__(self):
+        return len(self._t)
 
 
 def to_json(choices: list[Choice]) -> dict:
@@ -140,18 +163,11 @@ def save(choices: list[Choice], path: str):
         json.dump(to_json(choices), f, indent=1)
 
 
-def load(path: str) -> int:
-    """Install a saved table; returns the number of entries applied."""
+def load(path: str) -> TileTable:
+    """A saved table (refused when it was measured on another device)."""
     with open(path) as f:
         t = json.load(f)
     if t.get("device") != torch.cuda.get_device_name(0):
         raise ValueError("tile table measured on %r, this device is %r" % (t.get("device"),
                                                                              torch.cuda.get_device_name(0)))
-    for e in t["entries"]:
-        hdc.set_tile(e["kind"], e["x_type"], e["compute"], e["F"], e["K"], e["variant"])
-    return len(t["entries"])
-
-
-def reset(shapes: list[Shape]):
-    for sh in shapes:
-        hdc.set_tile(sh.kind, sh.x_type, sh.compute, sh.F, sh.K, 0)
+    return TileTable({(e["kind"], e["x_type"], e["compute"], e["F"], e["K"]): e["variant"] for e in t["entries"]})

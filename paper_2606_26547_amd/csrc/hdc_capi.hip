@@ -135,9 +135,9 @@ const char *hdc_status_string(hdc_status s)
 
 int32_t hdc_dims_count(hdc_dims dims) { return dims_count(dims); }
 
-hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
-                      const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims, uint64_t *H,
-                      int64_t ldh)
+hdc_status hdc_encode_tiled(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                            const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims, uint64_t *H,
+                            int64_t ldh, int32_t tile)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
@@ -146,14 +146,22 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
     const int32_t nd = dims_count(dims);
     if (n > 0 && (!H || ldh < (nd + 63) / 64 || !aligned(H, 8)))
         return HDC_ERR_INVALID;
+    if (tile < 0 || !tile_compiled(KK_ENCODE, xt, ct, F, 1, tile))
+        return HDC_ERR_UNSUPPORTED;
     if (n == 0)
         return HDC_OK;
     EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
     a.H32 = (uint32_t *)H;
     a.ldh32 = 2 * ldh;
     a.max_split = 1 << 30;   // the splits write disjoint words: no scratch
-    const int v = get_tile(KK_ENCODE, xt, ct, F, 1);
-    return from_hip(launch_encode(a, ct, M_ENCODE, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
+    return from_hip(launch_encode(a, ct, M_ENCODE, Tile{tile}, (hipStream_t)stream));
+}
+
+hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
+                      const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims, uint64_t *H,
+                      int64_t ldh)
+{
+    return hdc_encode_tiled(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, H, ldh, 0);
 }
 
 size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K)
@@ -473,24 +481,6 @@ int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, 
     return n;
 }
 
-hdc_status hdc_set_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,
-                        int32_t variant)
-{
-    int xt, ct;
-    const int32_t Kk = kind == HDC_KERNEL_ENCODE ? 1 : K;
-    if (!tile_key(kind, x_type, compute, &xt, &ct) || F <= 0 || get_tile((int)kind, xt, ct, F, Kk) < 0)
-        return HDC_ERR_INVALID;
-    return set_tile((int)kind, xt, ct, F, Kk, variant) ? HDC_OK : HDC_ERR_UNSUPPORTED;
-}
-
-int32_t hdc_get_tile(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K)
-{
-    int xt, ct;
-    if (!tile_key(kind, x_type, compute, &xt, &ct) || F <= 0)
-        return -1;
-    return get_tile((int)kind, xt, ct, F, kind == HDC_KERNEL_ENCODE ? 1 : K);
-}
-
 size_t hdc_adc_workspace_bytes(hdc_dims perf, int32_t K)
 {
     if (check_perf(perf, K) != HDC_OK)
@@ -573,7 +563,7 @@ size_t hdc_classify_scratch_bytes(int64_t n, int32_t n_dims, int32_t K)
 hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                                  const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
                                  int32_t K, int32_t *labels, int32_t *dists, const void *ws, size_t ws_bytes,
-                                 void *scratch, size_t scratch_bytes)
+                                 void *scratch, size_t scratch_bytes, int32_t tile)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
@@ -590,6 +580,8 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
         return HDC_ERR_WORKSPACE;
     if (scratch && !aligned(scratch, 4))
         return HDC_ERR_WORKSPACE;
+    if (tile < 0 || !tile_compiled(KK_CLASSIFY, xt, ct, F, K, tile))
+        return HDC_ERR_UNSUPPORTED;
     if (n == 0)
         return HDC_OK;
     EncodeArgs a = make_args(X, xt, n, F, ldx, P, ldp, dims);
@@ -604,14 +596,13 @@ hdc_status hdc_classify_prepared(void *stream, const void *X, hdc_dtype x_type, 
         a.max_split = (int32_t)(cap < (1 << 30) ? cap : (1 << 30));
         a.part = (int32_t *)scratch;
     }
-    const int v = get_tile(KK_CLASSIFY, xt, ct, F, K);
-    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{v > 0 ? v : 0}, (hipStream_t)stream));
+    return from_hip(launch_encode(a, ct, M_CLASSIFY, Tile{tile}, (hipStream_t)stream));
 }
 
 hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                         const int8_t *P, int32_t D, int64_t ldp, hdc_dtype compute, hdc_dims dims,
                         const uint64_t *C, int32_t K, int64_t ldc, int32_t *labels, int32_t *dists, void *ws,
-                        size_t ws_bytes, void *scratch, size_t scratch_bytes)
+                        size_t ws_bytes, void *scratch, size_t scratch_bytes, int32_t tile)
 {
     int ct, xt;
     hdc_status s = check_encode_operands(X, x_type, n, F, ldx, P, D, ldp, compute, dims, &ct, &xt);
@@ -623,7 +614,7 @@ hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n
         return HDC_ERR_INVALID;
     if (n == 0) {
         const int32_t nd = dims_count(dims);
-        if (K > kMaxK)
+        if (K > kMaxK || tile < 0 || !tile_compiled(KK_CLASSIFY, xt, ct, F, K, tile))
             return HDC_ERR_UNSUPPORTED;
         if (!ws || ws_bytes < hdc_classify_workspace_bytes(nd, K))
             return HDC_ERR_WORKSPACE;
@@ -633,7 +624,7 @@ hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n
     if (s != HDC_OK)
         return s;
     return hdc_classify_prepared(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, K, labels, dists, ws,
-                                 ws_bytes, scratch, scratch_bytes);
+                                 ws_bytes, scratch, scratch_bytes, tile);
 }
 
 size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
@@ -654,14 +645,20 @@ hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64
         return s;
     if (K <= 0 || ncfg <= 0 || max_workgroups < 0)
         return HDC_ERR_INVALID;
-    if (K > kMaxK || ncfg > kMaxConfigs)
+    if (K > kMaxK || ncfg > kMaxConfigs || xt == X_FP32)
         return HDC_ERR_UNSUPPORTED;
     if (!C || ldc < (D + 63) / 64 || !cfgs || !out || (n > 0 && !truth))
         return HDC_ERR_INVALID;
+    for (int32_t i = 0; i < ncfg; ++i)
+        if (cfgs[i].tile_id < 0 || !tile_compiled(KK_SWEEP, xt, C_I8, F, K, cfgs[i].tile_id))
+            return HDC_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < hdc_eval_configs_workspace_bytes(ncfg, D, K) || !aligned(ws, 256))
         return HDC_ERR_WORKSPACE;
-    if (n == 0)
+    if (n == 0) {
+        for (int32_t i = 0; i < ncfg; ++i)
+            out[i] = hdc_config_result{0, 0, 0.0};
         return HDC_OK;
+    }
     SweepArgs a;
     a.X = X;
     a.x_type = xt;

@@ -106,10 +106,10 @@ inline size_t class_table_bytes(int nd, int K) { return (size_t)table_chunks(nd)
 // features on the int8 path), or register staging with one or two query
 // tiles per wave.
 enum TileVariant : int { TV_AUTO = 0, TV_DMA_2X2 = 1, TV_DMA_1X1 = 2, TV_REG_QT1 = 3, TV_REG_QT2 = 4 };
-// Tile variants of the configuration sweep: work items of 128 queries (one
-// query tile per wave) or of 256 (int8 slots with two query tiles per wave
-// where the registers allow, other slots in two passes), or of 256 with
-// int8-feature int8 slots on the direct-staged 2x2 body.
+// Tile variants of the configuration sweep (per configuration): work items of
+// 128 queries (one query tile per wave) or of 256 (int8 slots with two query
+// tiles per wave where the registers allow, other slots in two passes), or of
+// 256 with int8-feature int8 slots on the direct-staged 2x2 body.
 enum SweepVariant : int { SV_AUTO = 0, SV_ITEM128 = 1, SV_ITEM256 = 2, SV_ITEM256_DMA = 3 };
 enum KernelKind : int { KK_ENCODE = 0, KK_CLASSIFY = 1, KK_SWEEP = 2 };
 
@@ -134,10 +134,10 @@ int sweep_width_index(int F);
 inline int encoder_kt(int mode, int K) { return mode == M_ENCODE ? 1 : class_tiles(K); }
 inline int sweep_kt(int K) { return K <= 32 ? 1 : 4; }
 
-// Process-wide tile table (written by hdc_set_tile, read at every launch).
+// Tile variants a bucket is compiled with (the built-in one first; -1 for a
+// shape outside the compiled kernels), and whether a launch may name one.
 int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap);
-int get_tile(int kind, int x_type, int ct, int F, int K);
-bool set_tile(int kind, int x_type, int ct, int F, int K, int variant);
+bool tile_compiled(int kind, int x_type, int ct, int F, int K, int variant);
 
 hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, hipStream_t st);
 hipError_t launch_class_table(const uint64_t *C, int K, int64_t ldc, int s0, int stride, int nd,
@@ -204,9 +204,9 @@ struct SweepArgs {
     const uint64_t *C;
     int32_t K;
     int64_t ldc;
-    const hdc_config *cfgs;   // device
+    const hdc_config *cfgs;   // host
     int32_t ncfg;
-    hdc_config_result *out;   // device
+    hdc_config_result *out;   // host
     uint8_t *ws;
     size_t ws_bytes;
     int32_t max_wg;           // 0: fill the device

@@ -3,14 +3,18 @@
 // system: run each candidate, read back its accuracy and time).
 //
 // Workspace layout (all offsets 256-byte aligned):
-//   [0]            queue counter (uint32) and item count
-//   [256]          slot descriptors, ncfg x SlotDesc
+//   [0]            queue counter (uint32)
+//   [256]          the configurations as passed (copied from the host)
+//   [..]           slot descriptors, ncfg x SlotDesc
 //   [..]           slot order (longest first), ncfg x int32
+//   [..]           first work item of each slot in that order, ncfg + 1 x int32
+//   [..]           per-slot results as counted (correct, n, device ticks)
+//   [..]           per-slot results as returned (correct, n, device_us)
 //   [..]           per-slot class operand regions of fixed size
 //                  (chunks(D) * KT KiB table + 128 int32 popcounts)
-// Work item i = (slot order[i / tiles], query tile i % tiles); a workgroup
-// takes items from the queue until it is exhausted, so every workgroup
-// reaches the exit whatever the grid size.
+// Work item i belongs to the slot whose item range holds it (a binary search
+// over the item offsets); a workgroup takes items from the queue until it is
+// exhausted, so every workgroup reaches the exit whatever the grid size.
 #include <string.h>
 
 #include "hdc_encoder.h"
@@ -19,9 +23,16 @@ namespace hdc {
 
 struct SlotDesc {
     int32_t s0, stride, nd, ct;   // ct < 0: invalid configuration (no work)
+    int32_t iq;                   // work items: 1 = 128 queries, 2 = 256, 3 = 256 on the direct-staged body
+    int32_t tiles;                // work items of the slot
     int64_t cost;
 };
 
+// Per-slot counters of the persistent kernel.
+struct SlotCount {
+    int32_t correct, n;
+    uint64_t ticks;
+};
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -31,12 +42,16 @@ inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 inline size_t sweep_table_bytes(int D, int K) { return (size_t)table_chunks(D) * sweep_kt(K) * 1024; }
 
 struct SweepLayout {
-    size_t off_desc, off_order, off_regions, region, total;
+    size_t off_cfg, off_desc, off_order, off_items, off_count, off_res, off_regions, region, total;
     SweepLayout(int ncfg, int D, int K)
     {
-        off_desc = 256;
+        off_cfg = 256;
+        off_desc = align256(off_cfg + (size_t)ncfg * sizeof(hdc_config));
         off_order = align256(off_desc + (size_t)ncfg * sizeof(SlotDesc));
-        off_regions = align256(off_order + (size_t)ncfg * 4);
+        off_items = align256(off_order + (size_t)ncfg * 4);
+        off_count = align256(off_items + (size_t)(ncfg + 1) * 4);
+        off_res = align256(off_count + (size_t)ncfg * sizeof(SlotCount));
+        off_regions = align256(off_res + (size_t)ncfg * sizeof(hdc_config_result));
         region = align256(sweep_table_bytes(D, K) + 128 * 4);
         total = off_regions + region * (size_t)ncfg;
     }
@@ -49,15 +64,43 @@ size_t sweep_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
     return SweepLayout(ncfg, D, K).total;
 }
 
-// Validate configurations, zero the results and order the slots by
-// decreasing cost (dimensions x compute cost); ties keep slot order.
-__global__ __launch_bounds__(1024) void k_sweep_setup(const hdc_config *__restrict__ cfgs, int ncfg, int D,
-                                                      int64_t n, uint8_t *__restrict__ ws,
-                                                      hdc_config_result *__restrict__ out, size_t off_desc,
-                                                      size_t off_order)
+// Exclusive prefix sums over the block of one value per thread (at most 16
+// waves); `wt` is LDS of 16 ints; returns the block total in *total.
+__device__ __forceinline__ int block_exscan(int v, int *wt, int *total)
 {
-    SlotDesc *desc = (SlotDesc *)(ws + off_desc);
-    int32_t *order = (int32_t *)(ws + off_order);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(s, o);
+        if (lane >= o)
+            s += u;
+    }
+    if (lane == 63)
+        wt[wave] = s;
+    __syncthreads();
+    int base = 0, all = 0;
+    for (int w = 0; w < nw; ++w) {
+        base += w < wave ? wt[w] : 0;
+        all += wt[w];
+    }
+    __syncthreads();
+    *total = all;
+    return base + s - v;
+}
+
+// Validate configurations, zero the counters, order the slots by decreasing
+// cost (dimensions x compute cost; ties keep slot order) and lay out their
+// work items in that order.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_sweep_setup(int ncfg, int D, int64_t n, int x_type, int K,
+                                                      uint8_t *__restrict__ ws, SweepLayout L)
+{
+    __shared__ int wt[16];
+    const hdc_config *cfgs = (const hdc_config *)(ws + L.off_cfg);
+    SlotDesc *desc = (SlotDesc *)(ws + L.off_desc);
+    int32_t *order = (int32_t *)(ws + L.off_order);
+    int32_t *items = (int32_t *)(ws + L.off_items);
+    SlotCount *cnt = (SlotCount *)(ws + L.off_count);
     for (int i = threadIdx.x; i < ncfg; i += blockDim.x) {
         const hdc_config c = cfgs[i];
         SlotDesc s;
@@ -69,10 +112,13 @@ __global__ __launch_bounds__(1024) void k_sweep_setup(const hdc_config *__restri
             s.ct = -1;
         s.nd = ok ? (c.d_trunc - c.start + c.stride - 1) / c.stride : 0;
         s.cost = (int64_t)s.nd * (s.ct == C_BF16 ? 2 : 1);
+        // built-in work items: 256 queries
+        s.iq = c.tile_id == SV_ITEM128 ? 1 : c.tile_id == SV_ITEM256_DMA ? 3 : 2;
+        s.tiles = ok ? (int32_t)((n + (s.iq == 1 ? 127 : 255)) / (s.iq == 1 ? 128 : 256)) : 0;
         desc[i] = s;
-        out[i].correct = 0;
-        out[i].n = ok ? (int32_t)n : 0;
-        out[i].ticks = 0;
+        cnt[i].correct = 0;
+        cnt[i].n = ok ? (int32_t)n : 0;
+        cnt[i].ticks = 0;
     }
     if (threadIdx.x == 0)
         ((uint32_t *)ws)[0] = 0u;
@@ -86,16 +132,46 @@ __global__ __launch_bounds__(1024) void k_sweep_setup(const hdc_config *__restri
         }
         order[rank] = i;
     }
+    __syncthreads();
+    // first item of each rank: thread t covers ranks [t * per, (t + 1) * per)
+    const int per = (ncfg + blockDim.x - 1) / blockDim.x;
+    const int r0 = threadIdx.x * per;
+    int local = 0;
+    for (int r = r0; r < r0 + per && r < ncfg; ++r)
+        local += desc[order[r]].tiles;
+    int total;
+    int run = block_exscan(local, wt, &total);
+    for (int r = r0; r < r0 + per && r < ncfg; ++r) {
+        items[r] = run;
+        run += desc[order[r]].tiles;
+    }
+    if (threadIdx.x == 0)
+        items[ncfg] = total;
+}
+
+// Per-slot results in the returned form: device time in microseconds.
+__global__ __launch_bounds__(256) void k_sweep_results(int ncfg, const uint8_t *__restrict__ ws, SweepLayout L,
+                                                       double us_per_tick)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= ncfg)
+        return;
+    const SlotCount c = ((const SlotCount *)(ws + L.off_count))[i];
+    hdc_config_result r;
+    r.correct = c.correct;
+    r.n = c.n;
+    r.device_us = (double)c.ticks * us_per_tick;
+    ((hdc_config_result *)(ws + L.off_res))[i] = r;
 }
 
 // Class operand tables of every slot (same layout as hdc_classify's).
 __global__ __launch_bounds__(256) void k_sweep_tables(const uint64_t *__restrict__ C, int K, int64_t ldc,
-                                                      uint8_t *__restrict__ ws, size_t off_desc,
-                                                      size_t off_regions, size_t region, int KT, int64_t per_slot)
+                                                      uint8_t *__restrict__ ws, SweepLayout L, int KT,
+                                                      int64_t per_slot)
 {
     const int slot = blockIdx.y;
-    const SlotDesc s = ((const SlotDesc *)(ws + off_desc))[slot];
-    int8_t *tab = (int8_t *)(ws + off_regions + region * slot);
+    const SlotDesc s = ((const SlotDesc *)(ws + L.off_desc))[slot];
+    int8_t *tab = (int8_t *)(ws + L.off_regions + L.region * slot);
     // whole pairs of chunks; chunks past nd are written as zeros
     const int64_t total = (int64_t)((s.nd + 2 * kDimChunk - 1) / (2 * kDimChunk)) * 2 * KT * 64;
     for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total && idx < per_slot;
@@ -121,13 +197,12 @@ __global__ __launch_bounds__(256) void k_sweep_tables(const uint64_t *__restrict
 }
 
 __global__ __launch_bounds__(256) void k_sweep_popc(const uint64_t *__restrict__ C, int K, int64_t ldc,
-                                                    uint8_t *__restrict__ ws, size_t off_desc, size_t off_regions,
-                                                    size_t region, size_t table_bytes)
+                                                    uint8_t *__restrict__ ws, SweepLayout L, size_t table_bytes)
 {
     __shared__ int part[256];
     const int slot = blockIdx.y, k = blockIdx.x;
-    const SlotDesc s = ((const SlotDesc *)(ws + off_desc))[slot];
-    int32_t *popc = (int32_t *)(ws + off_regions + region * slot + table_bytes);
+    const SlotDesc s = ((const SlotDesc *)(ws + L.off_desc))[slot];
+    int32_t *popc = (int32_t *)(ws + L.off_regions + L.region * slot + table_bytes);
     int acc = 0;
     if (k < K)
         for (int64_t dl = threadIdx.x; dl < s.nd; dl += 256) {
@@ -149,7 +224,7 @@ __global__ __launch_bounds__(256) void k_sweep_popc(const uint64_t *__restrict__
 // adding the correct labels to the slot's count.
 template <int CT, int QT, int KS, int KT>
 __device__ __forceinline__ void sweep_pass(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
-                                           hdc_config_result *res)
+                                           SlotCount *res)
 {
     typedef Encoder<CT, 0, QT, KS, KT, M_CLASSIFY, 1> E;
     v16i dacc[KT][QT];
@@ -175,7 +250,7 @@ constexpr bool sweep_qt2(int ct, int ks, int kt) { return ct == C_I8 && ks <= 20
 // (int8 features on the int8 path).
 template <int KS, int KT>
 __device__ __forceinline__ void sweep_pass_dma(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
-                                               hdc_config_result *res)
+                                               SlotCount *res)
 {
     typedef Encoder<C_I8, 0, 2, KS, KT, M_CLASSIFY, 1, true, 2> E;
     v16i dacc[KT][2];
@@ -200,7 +275,7 @@ __device__ __forceinline__ void sweep_pass_dma(EncodeArgs &a, uint8_t *smem, int
 // 2x2 body instead (where it is compiled), the rest as IQ = 2.
 template <int CT, int KS, int KT, int IQ>
 __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
-                                                     hdc_config_result *res)
+                                                     SlotCount *res)
 {
     if constexpr (IQ == 3 && CT == C_I8 && big_tile(KS, KT)) {
         if (a.x_type == X_INT8) {
@@ -234,17 +309,20 @@ struct SweepLds {
     static constexpr int value = abcd > e ? abcd : e;
 };
 
-template <int FB, int KT, int IQ>
+// The persistent kernel.  Each slot runs with its own work-item size (its
+// configuration's tile id); the LDS holds the largest body of the bucket.
+template <int FB, int KT>
 __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *__restrict__ truth,
-                                               uint8_t *__restrict__ ws, hdc_config_result *__restrict__ out,
-                                               size_t off_desc, size_t off_order, size_t off_regions,
-                                               size_t region, size_t table_bytes, int ncfg, int tiles)
+                                               uint8_t *__restrict__ ws, SweepLayout L, size_t table_bytes,
+                                               int ncfg)
 {
-    __shared__ __align__(16) uint8_t smem[SweepLds<FB, KT, IQ>::value];
+    __shared__ __align__(16) uint8_t smem[SweepLds<FB, KT, 3>::value];
     __shared__ int item_s;
-    const SlotDesc *desc = (const SlotDesc *)(ws + off_desc);
-    const int32_t *order = (const int32_t *)(ws + off_order);
-    const int total = ncfg * tiles;
+    const SlotDesc *desc = (const SlotDesc *)(ws + L.off_desc);
+    const int32_t *order = (const int32_t *)(ws + L.off_order);
+    const int32_t *items = (const int32_t *)(ws + L.off_items);
+    SlotCount *cnt = (SlotCount *)(ws + L.off_count);
+    const int total = items[ncfg];
     for (;;) {
         if (threadIdx.x == 0)
             item_s = (int)atomicAdd((uint32_t *)ws, 1u);
@@ -253,8 +331,17 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         __syncthreads();
         if (item >= total)
             break;
-        const int slot = order[item / tiles];
-        const int tile = item % tiles;
+        // rank of the item: the last r with items[r] <= item
+        int lo = 0, hi = ncfg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int slot = order[lo];
+        const int tile = item - items[lo];
         const SlotDesc s = desc[slot];
         if (s.ct < 0)
             continue;
@@ -263,21 +350,34 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         a.s0 = s.s0;
         a.stride = s.stride;
         a.nd = s.nd;
-        a.ctab = (const int8_t *)(ws + off_regions + region * slot);
-        a.cpop = (const int32_t *)(ws + off_regions + region * slot + table_bytes);
-        const int64_t qblock = (int64_t)tile * (IQ == 1 ? 1 : 2) * 32 * kWaves;
-        if (s.ct == C_I8)
-            sweep_item<C_I8, FB / 32, KT, IQ>(a, smem, qblock, truth, &out[slot]);
-        else if (s.ct == C_FP8)
-            sweep_item<C_FP8, FB / 64, KT, IQ>(a, smem, qblock, truth, &out[slot]);
-        else
-            sweep_item<C_BF16, FB / 16, KT, IQ>(a, smem, qblock, truth, &out[slot]);
+        a.ctab = (const int8_t *)(ws + L.off_regions + L.region * slot);
+        a.cpop = (const int32_t *)(ws + L.off_regions + L.region * slot + table_bytes);
+        const int64_t qblock = (int64_t)tile * (s.iq == 1 ? 1 : 2) * 32 * kWaves;
+        SlotCount *res = &cnt[slot];
+        if (s.ct == C_I8) {
+            if (s.iq == 1)
+                sweep_item<C_I8, FB / 32, KT, 1>(a, smem, qblock, truth, res);
+            else if (s.iq == 2)
+                sweep_item<C_I8, FB / 32, KT, 2>(a, smem, qblock, truth, res);
+            else
+                sweep_item<C_I8, FB / 32, KT, 3>(a, smem, qblock, truth, res);
+        } else if (s.ct == C_FP8) {
+            if (s.iq == 1)
+                sweep_item<C_FP8, FB / 64, KT, 1>(a, smem, qblock, truth, res);
+            else
+                sweep_item<C_FP8, FB / 64, KT, 2>(a, smem, qblock, truth, res);
+        } else {
+            if (s.iq == 1)
+                sweep_item<C_BF16, FB / 16, KT, 1>(a, smem, qblock, truth, res);
+            else
+                sweep_item<C_BF16, FB / 16, KT, 2>(a, smem, qblock, truth, res);
+        }
         if (threadIdx.x == 0)
-            atomicAdd((unsigned long long *)&out[slot].ticks, (unsigned long long)(wall_clock64() - t0));
+            atomicAdd((unsigned long long *)&res->ticks, (unsigned long long)(wall_clock64() - t0));
     }
 }
 
-template <int FB, int KT, int IQ>
+template <int FB, int KT>
 static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a, const SweepLayout &L,
                                       size_t table_bytes, hipStream_t st)
 {
@@ -285,35 +385,24 @@ static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<FB, KT, IQ>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<FB, KT>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int grid = cus * per_cu;
     if (a.max_wg > 0 && a.max_wg < grid)
         grid = a.max_wg;
-    constexpr int QI = (IQ == 1 ? 1 : 2) * 32 * kWaves;   // queries per item
-    const int tiles = (int)((a.n + QI - 1) / QI);
-    hipLaunchKernelGGL((k_sweep<FB, KT, IQ>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, a.out, L.off_desc,
-                       L.off_order, L.off_regions, L.region, table_bytes, a.ncfg, tiles);
+    hipLaunchKernelGGL((k_sweep<FB, KT>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, L, table_bytes,
+                       a.ncfg);
     return hipGetLastError();
 }
 
-// Work-item size from the tile table (0: the built-in 128 queries).
 template <int FB>
 static hipError_t launch_sweep_fb(const EncodeArgs &base, const SweepArgs &a, const SweepLayout &L,
                                   size_t table_bytes, hipStream_t st)
 {
-    const int v = get_tile(KK_SWEEP, a.x_type, C_I8, a.F, a.K);
-    if (sweep_kt(a.K) == 1) {
-        if constexpr (big_tile(FB / 32, 1)) {
-            if (v == SV_ITEM256_DMA)
-                return launch_sweep_kernel<FB, 1, 3>(base, a, L, table_bytes, st);
-        }
-        return v == SV_ITEM256 ? launch_sweep_kernel<FB, 1, 2>(base, a, L, table_bytes, st)
-                               : launch_sweep_kernel<FB, 1, 1>(base, a, L, table_bytes, st);
-    }
-    return v == SV_ITEM256 ? launch_sweep_kernel<FB, 4, 2>(base, a, L, table_bytes, st)
-                           : launch_sweep_kernel<FB, 4, 1>(base, a, L, table_bytes, st);
+    if (sweep_kt(a.K) == 1)
+        return launch_sweep_kernel<FB, 1>(base, a, L, table_bytes, st);
+    return launch_sweep_kernel<FB, 4>(base, a, L, table_bytes, st);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
@@ -321,15 +410,19 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     const SweepLayout L(a.ncfg, a.D, a.K);
     const int KT = sweep_kt(a.K);
     const size_t table_bytes = sweep_table_bytes(a.D, a.K);
-    hipLaunchKernelGGL(k_sweep_setup, dim3(1), dim3(1024), 0, st, a.cfgs, a.ncfg, a.D, a.n, a.ws, a.out,
-                       L.off_desc, L.off_order);
+    // the configurations go up with the other work of the stream (from
+    // pageable memory the runtime stages them before returning)
+    hipError_t e = hipMemcpyAsync(a.ws + L.off_cfg, a.cfgs, (size_t)a.ncfg * sizeof(hdc_config),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sweep_setup, dim3(1), dim3(1024), 0, st, a.ncfg, a.D, a.n, a.x_type, a.K, a.ws, L);
     const int64_t per_slot = table_chunks(a.D) * KT * 64;
     const unsigned gx = (unsigned)((per_slot + 255) / 256 < 1024 ? (per_slot + 255) / 256 : 1024);
-    hipLaunchKernelGGL(k_sweep_tables, dim3(gx, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L.off_desc,
-                       L.off_regions, L.region, KT, per_slot);
-    hipLaunchKernelGGL(k_sweep_popc, dim3(KT * 32, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L.off_desc,
-                       L.off_regions, L.region, table_bytes);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(k_sweep_tables, dim3(gx, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L, KT, per_slot);
+    hipLaunchKernelGGL(k_sweep_popc, dim3(KT * 32, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L,
+                       table_bytes);
+    e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     EncodeArgs base;
@@ -342,12 +435,28 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     base.P = a.P;
     base.ldp = a.ldp;
     base.K = a.K;
-    if (a.F <= 128) return launch_sweep_fb<128>(base, a, L, table_bytes, st);
-    if (a.F <= 256) return launch_sweep_fb<256>(base, a, L, table_bytes, st);
-    if (a.F <= 512) return launch_sweep_fb<512>(base, a, L, table_bytes, st);
-    if (a.F <= 640) return launch_sweep_fb<640>(base, a, L, table_bytes, st);
-    if (a.F <= 832) return launch_sweep_fb<832>(base, a, L, table_bytes, st);
-    return launch_sweep_fb<1024>(base, a, L, table_bytes, st);
+    if (a.F <= 128) e = launch_sweep_fb<128>(base, a, L, table_bytes, st);
+    else if (a.F <= 256) e = launch_sweep_fb<256>(base, a, L, table_bytes, st);
+    else if (a.F <= 512) e = launch_sweep_fb<512>(base, a, L, table_bytes, st);
+    else if (a.F <= 640) e = launch_sweep_fb<640>(base, a, L, table_bytes, st);
+    else if (a.F <= 832) e = launch_sweep_fb<832>(base, a, L, table_bytes, st);
+    else e = launch_sweep_fb<1024>(base, a, L, table_bytes, st);
+    if (e != hipSuccess)
+        return e;
+    // results: ticks -> microseconds of the device wall clock, then down to
+    // the caller's host array (from pinned memory the copy stays
+    // asynchronous; into pageable memory the runtime completes it first)
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
+                                                hipSuccess || khz <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sweep_results, dim3((unsigned)((a.ncfg + 255) / 256)), dim3(256), 0, st, a.ncfg, a.ws, L,
+                       1000.0 / (double)khz);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipMemcpyAsync(a.out, a.ws + L.off_res, (size_t)a.ncfg * sizeof(hdc_config_result),
+                          hipMemcpyDeviceToHost, st);
 }
 
 }  // namespace hdc

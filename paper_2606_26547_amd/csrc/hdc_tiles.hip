@@ -1,9 +1,8 @@
-// Tile table: which kernel shape each (kernel, feature type, compute type,
-// feature width, class tiles) bucket launches.  Entries start at 0 (the
-// built-in rule); an autotuner measures the variants of a bucket and sets
-// the fastest.  Every variant of a bucket computes the same result.
-#include <atomic>
-
+// Tile variants: which kernel shapes each (kernel, feature type, compute
+// type, feature width, class tiles) bucket is compiled with.  A launch names
+// its variant (0 = the built-in rule); an autotuner measures the variants of
+// a bucket and passes the fastest with each call.  Every variant of a bucket
+// computes the same result.  Nothing here is mutable.
 #include "hdc_internal.h"
 
 namespace hdc {
@@ -12,15 +11,7 @@ namespace {
 
 constexpr int kNI = sizeof(kIntWidths) / sizeof(kIntWidths[0]);
 constexpr int kNF = sizeof(kF32Widths) / sizeof(kF32Widths[0]);
-constexpr int kNW = kNI > kNF ? kNI : kNF;
 constexpr int kNS = sizeof(kSweepWidths) / sizeof(kSweepWidths[0]);
-
-// [kind encode/classify][compute][feature kind int/fp32][width][class tiles 1/2/4]
-std::atomic<int> g_enc[2][kComputeTypes][2][kNW][3];
-// [width][class tiles 1/4]
-std::atomic<int> g_sweep[kNS][2];
-
-int kt_index(int kt) { return kt == 1 ? 0 : kt == 2 ? 1 : 2; }
 
 // Variants a bucket is compiled with; the first listed is what 0 selects.
 int encoder_variants(int ct, int x_type, int width, int kt, int *out)
@@ -46,24 +37,14 @@ int encoder_variants(int ct, int x_type, int width, int kt, int *out)
     return n;
 }
 
-std::atomic<int> *encoder_slot(int kind, int x_type, int ct, int F, int K)
+bool encoder_bucket(int kind, int x_type, int ct, int F, int K)
 {
     if ((kind != KK_ENCODE && kind != KK_CLASSIFY) || ct < 0 || ct >= kComputeTypes)
-        return nullptr;
-    const int wi = width_index(x_type, F);
-    if (wi < 0 || K < 1 || K > kMaxK)
-        return nullptr;
-    const int kt = encoder_kt(kind == KK_ENCODE ? M_ENCODE : M_CLASSIFY, K);
-    return &g_enc[kind][ct][x_type == X_FP32 ? 1 : 0][wi][kt_index(kt)];
+        return false;
+    return width_index(x_type, F) >= 0 && K >= 1 && K <= kMaxK;
 }
 
-std::atomic<int> *sweep_slot(int F, int K)
-{
-    const int wi = sweep_width_index(F);
-    if (wi < 0 || K < 1 || K > kMaxK)
-        return nullptr;
-    return &g_sweep[wi][sweep_kt(K) == 1 ? 0 : 1];
-}
+bool sweep_bucket(int F, int K) { return sweep_width_index(F) >= 0 && K >= 1 && K <= kMaxK; }
 
 }  // namespace
 
@@ -93,15 +74,15 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
 {
     int v[8], n = 0;
     if (kind == KK_SWEEP) {
-        if (!sweep_slot(F, K) || x_type == X_FP32)
+        if (!sweep_bucket(F, K) || x_type == X_FP32)
             return -1;
-        v[n++] = SV_ITEM128;
         v[n++] = SV_ITEM256;
+        v[n++] = SV_ITEM128;
         const int wi = sweep_width_index(F);
         if (x_type == X_INT8 && sweep_kt(K) == 1 && big_tile(kSweepWidths[wi] / 32, 1))
             v[n++] = SV_ITEM256_DMA;
     } else {
-        if (!encoder_slot(kind, x_type, ct, F, K))
+        if (!encoder_bucket(kind, x_type, ct, F, K))
             return -1;
         if (x_type == X_FP32 ? ct == C_I8 : ct == C_F32)
             return -1;
@@ -114,28 +95,16 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
     return n;
 }
 
-int get_tile(int kind, int x_type, int ct, int F, int K)
+bool tile_compiled(int kind, int x_type, int ct, int F, int K, int variant)
 {
-    std::atomic<int> *e = kind == KK_SWEEP ? sweep_slot(F, K) : encoder_slot(kind, x_type, ct, F, K);
-    return e ? e->load(std::memory_order_relaxed) : -1;
-}
-
-bool set_tile(int kind, int x_type, int ct, int F, int K, int variant)
-{
-    std::atomic<int> *e = kind == KK_SWEEP ? sweep_slot(F, K) : encoder_slot(kind, x_type, ct, F, K);
-    if (!e)
-        return false;
-    if (variant != 0) {
-        int v[8];
-        const int n = tile_variants(kind, x_type, ct, F, K, v, 8);
-        bool ok = false;
-        for (int i = 0; i < n; ++i)
-            ok |= v[i] == variant;
-        if (!ok)
-            return false;
-    }
-    e->store(variant, std::memory_order_relaxed);
-    return true;
+    if (variant == 0)
+        return true;
+    int v[8];
+    const int n = tile_variants(kind, x_type, ct, F, K, v, 8);
+    for (int i = 0; i < n; ++i)
+        if (v[i] == variant)
+            return true;
+    return false;
 }
 
 }  // namespace hdc

@@ -31,7 +31,7 @@ INT8, UINT8, BF16, FP8_E4M3, FP32, FP8_SPLIT = 0, 1, 2, 3, 4, 5
 DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32, "fp8split": FP8_SPLIT}
 STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
           4: "HDC_ERR_DEVICE"}
-EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_workspace_bytes",
+EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_encode_tiled", "hdc_bundle_workspace_bytes",
            "hdc_bundle", "hdc_bundle_noalloc_limit_bytes", "hdc_bundle_noalloc", "hdc_hamming_argmin", "hdc_hamming_workspace_bytes", "hdc_hamming_prepare",
            "hdc_hamming_argmin_prepared", "hdc_classify_workspace_bytes", "hdc_classify_scratch_bytes", "hdc_classify",
            "hdc_classify_prepare", "hdc_classify_prepared",
@@ -40,7 +40,7 @@ EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_bundle_work
            "hdc_adc_argmax",
            "hdc_cosine_workspace_bytes", "hdc_cosine_prepare", "hdc_cosine_argmax_prepared",
            "hdc_feature_perforate", "hdc_level_quantize", "hdc_level_id_encode",
-           "hdc_tile_variants", "hdc_set_tile", "hdc_get_tile",
+           "hdc_tile_variants",
            "hdc_adc_workspace_bytes", "hdc_adc_prepare", "hdc_adc_argmax_prepared"]
 
 
@@ -53,11 +53,16 @@ class Adc(C.Structure):
 
 
 class Config(C.Structure):
-    _fields_ = [("d_trunc", C.c_int32), ("stride", C.c_int32), ("start", C.c_int32), ("dtype", C.c_int32)]
+    _fields_ = [("d_trunc", C.c_int32), ("stride", C.c_int32), ("start", C.c_int32), ("dtype", C.c_int32),
+                ("tile_id", C.c_int32)]
 
 
 class ConfigResult(C.Structure):
-    _fields_ = [("correct", C.c_int32), ("n", C.c_int32), ("ticks", C.c_uint64)]
+    _fields_ = [("correct", C.c_int32), ("n", C.c_int32), ("device_us", C.c_double)]
+
+
+# host layout of hdc_config_result as a numpy record
+RESULT_DTYPE = np.dtype([("correct", np.int32), ("n", np.int32), ("device_us", np.float64)])
 
 
 class HDCError(RuntimeError):
@@ -72,6 +77,7 @@ _lib.hdc_status_string.argtypes = [C.c_int]
 _lib.hdc_dims_count.restype = _i32
 _lib.hdc_dims_count.argtypes = [Dims]
 _lib.hdc_encode.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i64]
+_lib.hdc_encode_tiled.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i64, _i32]
 _lib.hdc_bundle_workspace_bytes.restype = _sz
 _lib.hdc_bundle_workspace_bytes.argtypes = [_i64, _i32, _i32]
 _lib.hdc_bundle.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i32, _p, _i64, _p, _p, _sz]
@@ -88,10 +94,10 @@ _lib.hdc_classify_workspace_bytes.argtypes = [_i32, _i32]
 _lib.hdc_classify_scratch_bytes.restype = _sz
 _lib.hdc_classify_scratch_bytes.argtypes = [_i64, _i32, _i32]
 _lib.hdc_classify.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _p, _i32,
-                              _i64, _p, _p, _p, _sz, _p, _sz]
+                              _i64, _p, _p, _p, _sz, _p, _sz, _i32]
 _lib.hdc_classify_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_classify_prepared.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _i32,
-                                       _p, _p, _p, _sz, _p, _sz]
+                                       _p, _p, _p, _sz, _p, _sz, _i32]
 _lib.hdc_eval_configs_workspace_bytes.restype = _sz
 _lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32]
 _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
@@ -110,9 +116,6 @@ _lib.hdc_adc_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_adc_argmax_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, Adc, _p, _p, _p, _p, _sz]
 _lib.hdc_tile_variants.restype = _i32
 _lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _p, _i32]
-_lib.hdc_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _i32]
-_lib.hdc_get_tile.restype = _i32
-_lib.hdc_get_tile.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32]
 _lib.hdc_feature_perforate.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, Dims, _p, _i64]
 _lib.hdc_level_quantize.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _i64]
 _lib.hdc_level_id_encode.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i64, _p, _i32, _i64, _i32, _p, _i64]
@@ -177,15 +180,17 @@ class Model:
 
 
 def encode(X: torch.Tensor, F: int, P: torch.Tensor, D: int, compute="int8", start=0, end=None, stride=1,
-           out: torch.Tensor | None = None) -> torch.Tensor:
-    """hdc_encode: packed sign bits [n][words(|S|)] (uint64 viewed as int64)."""
+           out: torch.Tensor | None = None, tile: int = 0) -> torch.Tensor:
+    """hdc_encode_tiled (hdc_encode for tile 0): packed sign bits
+    [n][words(|S|)] (uint64 viewed as int64)."""
     end = D if end is None else end
     nd = dims_count(start, end, stride)
     n = X.shape[0]
     if out is None:
         out = torch.zeros((n, words(nd)), dtype=torch.int64, device=X.device)
-    _check(_lib.hdc_encode(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
-                           DTYPE[compute], Dims(start, end, stride), _ptr(out), out.shape[1]), "hdc_encode")
+    _check(_lib.hdc_encode_tiled(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
+                                 DTYPE[compute], Dims(start, end, stride), _ptr(out), out.shape[1], int(tile)),
+           "hdc_encode")
     return out
 
 
@@ -322,14 +327,6 @@ def tile_variants(kind: str, x_type: str, compute: str, F: int, K: int) -> list[
     return list(buf[:n])
 
 
-def set_tile(kind: str, x_type: str, compute: str, F: int, K: int, variant: int):
-    _check(_lib.hdc_set_tile(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K, variant), "hdc_set_tile")
-
-
-def get_tile(kind: str, x_type: str, compute: str, F: int, K: int) -> int:
-    return int(_lib.hdc_get_tile(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K))
-
-
 class AdcPrepared:
     """Class hypervectors of one (classes, perforation) as the matrix-core
     operand of the ADC-chunked similarity; each call searches a batch of
@@ -403,9 +400,10 @@ def classify_scratch(n: int, nd: int, K: int, device, have: torch.Tensor | None 
 
 def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, compute="int8", start=0,
              d_trunc=None, stride=1, with_dists=False, ws: torch.Tensor | None = None,
-             labels: torch.Tensor | None = None, split: bool = True):
+             labels: torch.Tensor | None = None, split: bool = True, tile: int = 0):
     """hdc_classify: fused encode + Hamming + argmin under one configuration
-    (split=False: no dimension splits for small batches)."""
+    (split=False: no dimension splits for small batches; tile: the kernel
+    shape, 0 = built-in)."""
     d_trunc = D if d_trunc is None else d_trunc
     n, K = X.shape[0], Cw.shape[0]
     nd = dims_count(start, d_trunc, stride)
@@ -419,7 +417,7 @@ def classify(X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor,
     _check(_lib.hdc_classify(_stream(), _ptr(X), _xtype(X), n, F, X.shape[1], _ptr(P), D, P.shape[1],
                              DTYPE[compute], Dims(start, d_trunc, stride), _ptr(Cw), K, Cw.shape[1],
                              _ptr(labels), _ptr(dists), _ptr(ws), ws.numel(), _ptr(sc),
-                             sc.numel() if sc is not None else 0), "hdc_classify")
+                             sc.numel() if sc is not None else 0, int(tile)), "hdc_classify")
     return (labels, dists) if with_dists else labels
 
 
@@ -429,8 +427,9 @@ class Prepared:
     dimension-split scratch of the largest small batch seen (calls through
     one Prepared object are ordered on the stream they are issued on)."""
 
-    def __init__(self, Cw: torch.Tensor, D: int, compute="int8", start=0, d_trunc=None, stride=1):
+    def __init__(self, Cw: torch.Tensor, D: int, compute="int8", start=0, d_trunc=None, stride=1, tile: int = 0):
         self.D, self.K = D, Cw.shape[0]
+        self.tile = tile          # kernel shape of every call (0: built-in)
         self.compute, self.start = compute, start
         self.d_trunc = D if d_trunc is None else d_trunc
         self.stride = stride
@@ -457,7 +456,7 @@ class Prepared:
                                           P.shape[1], DTYPE[self.compute],
                                           Dims(self.start, self.d_trunc, self.stride), self.K, _ptr(labels),
                                           _ptr(dists), _ptr(self.ws), self.ws.numel(), _ptr(sc),
-                                          sc.numel() if sc is not None else 0),
+                                          sc.numel() if sc is not None else 0, int(self.tile)),
                "hdc_classify_prepared")
         return (labels, dists) if with_dists else labels
 
@@ -509,26 +508,46 @@ def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:
     return out
 
 
+def config_array(cfgs, tile: int = 0):
+    """Host hdc_config array from (d_trunc, stride, start, dtype[, tile_id])
+    tuples (dtype a name or an hdc_dtype value; tile_id defaults to `tile`)."""
+    arr = (Config * len(cfgs))()
+    for i, c in enumerate(cfgs):
+        d, k, s, t = c[:4]
+        arr[i] = Config(d, k, s, DTYPE[t] if isinstance(t, str) else int(t), int(c[4]) if len(c) > 4 else tile)
+    return arr
+
+
+def result_view(out: torch.Tensor, ncfg: int) -> np.ndarray:
+    """The hdc_config_result records held in a host uint8 tensor."""
+    return out.numpy()[:ncfg * RESULT_DTYPE.itemsize].view(RESULT_DTYPE)
+
+
 def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
-                 cfgs, ws: torch.Tensor | None = None, max_workgroups: int = 0):
-    """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype-name)], one
-    persistent launch; returns (correct[ncfg], ticks[ncfg]) device tensors.
-    Nothing here waits for the device: the configurations go up through
-    pinned memory on the current stream."""
-    arr = np.array([[d, k, s, DTYPE[t] if isinstance(t, str) else int(t)] for (d, k, s, t) in cfgs],
-                   dtype=np.int32).reshape(-1, 4)
-    dev = torch.from_numpy(arr).pin_memory().to(X.device, non_blocking=True)
+                 cfgs, ws: torch.Tensor | None = None, max_workgroups: int = 0, tile: int = 0,
+                 out: torch.Tensor | None = None):
+    """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype[, tile_id])],
+    one persistent launch.  Without `out` the call waits for the stream and
+    returns the result records (numpy: correct, n, device_us); with `out`, a
+    page-locked host uint8 tensor of at least 16 * len(cfgs) bytes, nothing
+    waits and the records are read later with result_view(out, ncfg) once
+    the stream has passed the call."""
+    arr = config_array(cfgs, tile)
     K = Cw.shape[0]
     need = int(_lib.hdc_eval_configs_workspace_bytes(len(arr), D, K))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
-    out = torch.zeros((len(arr), 4), dtype=torch.int32, device=X.device)   # {correct, n, ticks(u64)}
+    wait = out is None
+    if wait:
+        out = torch.empty(len(arr) * RESULT_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+    assert out.numel() >= len(arr) * RESULT_DTYPE.itemsize and out.device.type == "cpu"
     _check(_lib.hdc_eval_configs(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1], _ptr(truth),
-                                 _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], _ptr(dev), len(arr),
+                                 _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], arr, len(arr),
                                  _ptr(out), _ptr(ws), ws.numel(), int(max_workgroups)), "hdc_eval_configs")
-    correct = out[:, 0]
-    ticks = out[:, 2:4].contiguous().view(torch.int64).view(-1)
-    return correct, ticks
+    if wait:
+        torch.cuda.current_stream().synchronize()
+        return result_view(out, len(arr)).copy()
+    return out
 
 
 def device_clock_hz() -> float:

@@ -201,6 +201,12 @@ class GpuExecutor:
                         seen.add(key)
                         shapes.append(sh)
             choices = AT.autotune(shapes, reps=3)
+            table = AT.TileTable.from_choices(choices)
+            for m in self.models:
+                m.plain.tile = table.get("classify", "int8", "int8", m.F, m.K)
+                if m.tuned.compute == "int8":
+                    m.tuned.tile = m.plain.tile
+                m.sweep_tile = table.get("sweep", "int8", "int8", m.F, m.K)
         for i, m in enumerate(self.models):
             X = torch.zeros((64, m.P.shape[1]), dtype=torch.int8, device=self.dev)
             m.plain(X, m.F, m.P)
@@ -208,7 +214,7 @@ class GpuExecutor:
             if job_cfgs is not None:
                 y = torch.zeros(64, dtype=torch.int32, device=self.dev)
                 hdc.eval_configs(X, m.F, y, m.P, m.D, m.C, job_cfgs(i), ws=m.sweep_ws,
-                                 max_workgroups=self.job_workgroups)
+                                 max_workgroups=self.job_workgroups, tile=m.sweep_tile)
         torch.cuda.synchronize()
         return choices
 
@@ -220,7 +226,8 @@ class GpuExecutor:
                 "dx": torch.empty(n * ld, dtype=torch.int8, device=self.dev),
                 "hl": torch.empty(n, dtype=torch.int32, pin_memory=True),   # labels / truth
                 "dl": torch.empty(n, dtype=torch.int32, device=self.dev),
-                "hc": torch.empty(MAX_JOB_CONFIGS, dtype=torch.int32, pin_memory=True),
+                # per-configuration results (hdc_config_result records)
+                "hc": torch.empty(MAX_JOB_CONFIGS * 16, dtype=torch.uint8, pin_memory=True),
                 "ev": torch.cuda.Event()}
 
     @staticmethod
@@ -263,9 +270,8 @@ class GpuExecutor:
                 dx.copy_(hxt, non_blocking=True)
                 truth = slot["dl"][:b.n]
                 truth.copy_(slot["hl"][:b.n], non_blocking=True)
-                correct, _ = hdc.eval_configs(dx, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws,
-                                              max_workgroups=self.job_workgroups)
-                slot["hc"][:nc].copy_(correct, non_blocking=True)
+                hdc.eval_configs(dx, m.F, truth, m.P, m.D, m.C, r0.cfgs, ws=m.sweep_ws,
+                                 max_workgroups=self.job_workgroups, tile=m.sweep_tile, out=slot["hc"])
                 slot["ev"].record(self.cfg_stream)
             b.handle = ("configs", slot, nc)
             return
@@ -299,7 +305,7 @@ class GpuExecutor:
         slot["ev"].synchronize()
         try:
             if h[0] == "configs":
-                out = [slot["hc"].numpy()[:h[2]].copy()]
+                out = [self.hdc.result_view(slot["hc"], h[2])["correct"].copy()]
             else:
                 res = slot["hl"].numpy()
                 out = [res[off:off + r.n].copy() for r, off in zip(b.requests, b.offsets)]
@@ -325,6 +331,7 @@ class ResidentModel:
         self.C, _ = hdc.bundle(H, self.D, torch.as_tensor(y_train, dtype=torch.int32).to(device), self.K)
         del H, Xtr
         self.plain = hdc.Prepared(self.C, self.D, "int8")
+        self.sweep_tile = 0       # work-item shape of configuration jobs (0: built-in)
         self.tuned_cfg = tuned_cfg or (self.D, 1, 0, "int8")
         d, k, s, t = self.tuned_cfg
         self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
@@ -338,7 +345,7 @@ class ResidentModel:
         from . import hdc
         d, k, s, t = cfg
         self.tuned_cfg = cfg
-        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
+        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k, tile=self.plain.tile if t == "int8" else 0)
 
 
 # ---------------------------------------------------------------- server

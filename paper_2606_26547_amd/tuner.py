@@ -52,15 +52,13 @@ class Result:
 
 
 def sweep(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
-          cfgs) -> list[Result]:
-    """Evaluate every configuration with one persistent launch."""
+          cfgs, tile: int = 0) -> list[Result]:
+    """Evaluate every configuration with one persistent launch (work items
+    of the sweep tile variant `tile` for every configuration, 0 = built-in)."""
     cfgs = [tuple(c) for c in cfgs]
-    correct, ticks = hdc.eval_configs(X, F, truth, P, D, Cw, cfgs)
-    torch.cuda.synchronize()
-    hz = hdc.device_clock_hz()
-    c = correct.cpu().numpy()
-    t = ticks.cpu().numpy()
-    return [Result(cfg, int(c[i]), X.shape[0], float(t[i]) / hz * 1e6) for i, cfg in enumerate(cfgs)]
+    res = hdc.eval_configs(X, F, truth, P, D, Cw, cfgs, tile=tile)
+    return [Result(cfg, int(res["correct"][i]), int(res["n"][i]), float(res["device_us"][i]))
+            for i, cfg in enumerate(cfgs)]
 
 
 def sweep_loop(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
@@ -74,10 +72,11 @@ def sweep_loop(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D:
     return out
 
 
-def time_config(cfg, X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, reps: int = 5) -> float:
+def time_config(cfg, X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, reps: int = 5,
+                tile: int = 0) -> float:
     """Standalone queries/s of one configuration on batch X (median of reps)."""
     d, k, s, t = cfg
-    prep = hdc.Prepared(Cw, D, t, s, d, k)
+    prep = hdc.Prepared(Cw, D, t, s, d, k, tile=tile if t == "int8" else 0)
     labels = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
     prep(X, F, P, labels)
     torch.cuda.synchronize()

@@ -237,15 +237,13 @@ def test_f3_validation_without_device(lib):
     assert lib.hdc_level_id_encode(None, None, 0, 10, 10, fake, 2, fake, 4, 2, 128, None, 2) == 0      # n == 0
 
 
-def test_tile_table_without_device(lib):
-    """Variant lists follow the compiled shapes; set/get round-trip; invalid
-    shapes and variants are rejected; 0 restores the built-in choice."""
+def test_tile_variants_without_device(lib):
+    """Variant lists follow the compiled shapes (built-in first); launches
+    that name a variant the bucket is not compiled with are refused before
+    any device work; the library exports no tile setter."""
     p, i32 = C.c_void_p, C.c_int32
     lib.hdc_tile_variants.restype = i32
     lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32, p, i32]
-    lib.hdc_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32, i32]
-    lib.hdc_get_tile.restype = i32
-    lib.hdc_get_tile.argtypes = [C.c_int, C.c_int, C.c_int, i32, i32]
     ENC, CLS, SWP = 0, 1, 2
     INT8, UINT8, BF16, FP8, FP32 = 0, 1, 2, 3, 4
 
@@ -259,23 +257,31 @@ def test_tile_table_without_device(lib):
     assert variants(CLS, UINT8, INT8, 512, 10) == [4, 3]          # uint8 features: register staging
     assert variants(CLS, INT8, BF16, 617, 26) == [3]
     assert variants(ENC, FP32, FP32, 64, 0) == [4, 3]
-    assert variants(SWP, INT8, INT8, 617, 26) == [1, 2, 3]
-    assert variants(SWP, UINT8, INT8, 617, 26) == [1, 2]          # direct staging needs int8 features
-    assert variants(SWP, INT8, INT8, 617, 100) == [1, 2]          # and one class tile
-    assert variants(SWP, INT8, INT8, 784, 10) == [1, 2]           # and F <= 640
+    assert variants(SWP, INT8, INT8, 617, 26) == [2, 1, 3]        # built-in: items of 256 queries
+    assert variants(SWP, UINT8, INT8, 617, 26) == [2, 1]          # direct staging needs int8 features
+    assert variants(SWP, INT8, INT8, 617, 100) == [2, 1]          # and one class tile
+    assert variants(SWP, INT8, INT8, 784, 10) == [2, 1]           # and F <= 640
     assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
     assert variants(CLS, INT8, INT8, 2000, 26) is None            # beyond the compiled widths
     assert variants(SWP, FP32, FP32, 64, 2) is None
-    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 0
-    assert lib.hdc_set_tile(CLS, INT8, INT8, 600, 20, 2) == 0     # same bucket as (617, 26)
-    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 2
-    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 40) == 0        # two class tiles: another bucket
-    assert lib.hdc_set_tile(CLS, INT8, INT8, 617, 26, 4) == 2     # not compiled for this bucket
-    assert lib.hdc_set_tile(CLS, INT8, INT8, 2000, 26, 1) == 1
-    assert lib.hdc_set_tile(CLS, INT8, INT8, 617, 26, 0) == 0
-    assert lib.hdc_get_tile(CLS, INT8, INT8, 617, 26) == 0
-    assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 2) == 0 and lib.hdc_get_tile(SWP, UINT8, FP8, 640, 1) == 2
-    assert lib.hdc_set_tile(SWP, INT8, INT8, 617, 26, 0) == 0
+    assert not hasattr(lib, "hdc_set_tile") and not hasattr(lib, "hdc_get_tile")
+    p, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
+    fake = C.c_void_p(1 << 20)
+    lib.hdc_encode_tiled.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, p, i64, i32]
+    # (617 features, int8 -> int8) encode bucket: 2x2 and 1x1 direct staging, register QT1
+    assert lib.hdc_encode_tiled(None, fake, INT8, 4, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), fake,
+                                16, 4) == 2                       # two-tile register staging: not compiled
+    assert lib.hdc_encode_tiled(None, fake, INT8, 4, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), fake,
+                                16, -1) == 2
+    assert lib.hdc_encode_tiled(None, None, INT8, 0, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), None,
+                                16, 2) == 0                       # n == 0 with a compiled variant
+    lib.hdc_classify_prepared.argtypes = [p, p, C.c_int, i64, i32, i64, p, i32, i64, C.c_int, Dims, i32, p, p, p,
+                                          sz, p, sz, i32]
+    assert lib.hdc_classify_prepared(None, fake, INT8, 4, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), 100,
+                                     fake, None, fake, 1 << 20, None, 0, 1) == 2   # 2x2 with four class tiles
+    assert lib.hdc_classify_prepared(None, fake, INT8, 0, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), 100,
+                                     fake, None, fake, 1 << 20, None, 0, 2) == 0
+
 
 
 def test_adc_prepared_validation_without_device(lib):
@@ -299,3 +305,38 @@ def test_adc_prepared_validation_without_device(lib):
                                        need - 1) == 3                                         # small ws
     assert lib.hdc_adc_argmax_prepared(None, None, 0, 2, 3, Dims(0, 128, 1), ok, None, None, None, fake,
                                        need) == 0                                             # n == 0
+
+
+class Config(C.Structure):
+    _fields_ = [("d_trunc", C.c_int32), ("stride", C.c_int32), ("start", C.c_int32), ("dtype", C.c_int32),
+                ("tile_id", C.c_int32)]
+
+
+class ConfigResult(C.Structure):
+    _fields_ = [("correct", C.c_int32), ("n", C.c_int32), ("device_us", C.c_double)]
+
+
+def test_eval_configs_host_arrays_without_device(lib):
+    """Configurations and results are host arrays; each configuration's tile
+    id is checked against the bucket before any device work; n == 0 writes
+    empty results on the host."""
+    p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    assert C.sizeof(Config) == 20 and C.sizeof(ConfigResult) == 16
+    lib.hdc_eval_configs.argtypes = [p, p, C.c_int, i64, i32, i64, p, p, i32, i64, p, i32, i64, p, i32, p, p, sz,
+                                     i32]
+    fake, ws = C.c_void_p(1 << 20), C.c_void_p(1 << 24)
+    cfgs = (Config * 3)(Config(1024, 1, 0, 0, 0), Config(2048, 2, 0, 2, 1), Config(10240, 1, 0, 3, 3))
+    out = (ConfigResult * 3)()
+    for r in out:
+        r.correct, r.n, r.device_us = 7, 7, 7.0
+    call = lambda X, xt, n, F, c, o, w: lib.hdc_eval_configs(None, X, xt, n, F, 640, fake, fake, 10240, 640,  # noqa
+                                                            fake, 26, 160, c, 3, o, ws, w, 0)
+    bad = (Config * 3)(Config(1024, 1, 0, 0, 0), Config(2048, 2, 0, 2, 5), Config(10240, 1, 0, 3, 0))
+    assert call(fake, 0, 2000, 617, bad, out, 1 << 30) == 2                   # tile id 5: no such variant
+    dma = (Config * 3)(Config(1024, 1, 0, 0, 3), Config(2048, 2, 0, 2, 0), Config(10240, 1, 0, 3, 0))
+    assert call(fake, 1, 2000, 617, dma, out, 1 << 30) == 2                   # direct staging: int8 features
+    assert call(fake, 0, 2000, 617, None, out, 1 << 30) == 1                  # no configurations
+    assert call(fake, 0, 2000, 617, cfgs, None, 1 << 30) == 1                 # no results
+    assert call(fake, 0, 2000, 617, cfgs, out, 64) == 3                       # workspace
+    assert call(None, 0, 0, 617, cfgs, out, 1 << 30) == 0                     # n == 0
+    assert [(r.correct, r.n, r.device_us) for r in out] == [(0, 0, 0.0)] * 3

@@ -121,19 +121,16 @@ def test_headline_shape_every_tile_sampled(hdc, speech_batch, cfg):
     variants = hdc.tile_variants("classify", "int8", "int8", F, K)
     assert variants
     prep = hdc.Prepared(Cd, D, "int8", start, d_trunc, stride)
-    try:
-        for v in variants:
-            say("headline shape", cfg, "variant", v)
-            hdc.set_tile("classify", "int8", "int8", F, K, v)
-            lab, dists = prep(Xd, F, Pd, with_dists=True)
-            torch.cuda.synchronize()
-            assert np.array_equal(lab.cpu().numpy()[rows], lref), v
-            assert np.array_equal(dists.cpu().numpy()[rows], dref), v
-            # every row: the label is the first minimum of its distances
-            dd = dists.cpu().numpy()
-            assert np.array_equal(lab.cpu().numpy(), dd.argmin(1).astype(np.int32)), v
-    finally:
-        hdc.set_tile("classify", "int8", "int8", F, K, 0)
+    for v in variants:
+        say("headline shape", cfg, "variant", v)
+        prep.tile = v
+        lab, dists = prep(Xd, F, Pd, with_dists=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(lab.cpu().numpy()[rows], lref), v
+        assert np.array_equal(dists.cpu().numpy()[rows], dref), v
+        # every row: the label is the first minimum of its distances
+        dd = dists.cpu().numpy()
+        assert np.array_equal(lab.cpu().numpy(), dd.argmin(1).astype(np.int32)), v
     del Xd
 
 

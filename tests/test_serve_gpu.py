@@ -86,20 +86,15 @@ def test_warm_with_tile_tuning_keeps_labels(setup):
     """Tuning the resident models' tiles at warm-up changes no label."""
     serve, srcs, models = setup
     print("[case] serving tile tuning", flush=True)
-    from paper_2606_26547_amd import autotune as AT
     from paper_2606_26547_amd import hdc
     reqs = [(m, srcs[m].queries(300, 700 + m)[0]) for m in range(len(models))]
     before = run_alone(serve, models, [serve.Request(model=m, X=X) for m, X in reqs])
     ex = serve.GpuExecutor(models)
     job = lambda i: [(models[i].D, 1, 0, "int8"), (models[i].D // 2, 2, 0, "fp8")]   # noqa: E731
-    choices = []
-    try:
-        choices = ex.warm(job, tune_tiles=True)
-        assert len(choices) == 2 * len(models)
-        for c in choices:
-            assert c.chosen in hdc.tile_variants(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K)
-        after = run_alone(serve, models, [serve.Request(model=m, X=X) for m, X in reqs])
-        for a, b in zip(before, after):
-            assert np.array_equal(a, b)
-    finally:
-        AT.reset([c.shape for c in choices])
+    choices = ex.warm(job, tune_tiles=True)
+    assert len(choices) == 2 * len(models)
+    for c in choices:
+        assert c.chosen in hdc.tile_variants(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K)
+    after = run_alone(serve, models, [serve.Request(model=m, X=X) for m, X in reqs])
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)

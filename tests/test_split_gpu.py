@@ -61,18 +61,14 @@ def test_split_classify_matches_oracle(hdc, case):
     lref, dref = O.classify(X, P, Cw, ct, start, d_trunc, stride, with_dists=True)
     Xd, Pd, Cd = hdc.pad_cols(X), hdc.pad_cols(P), dev(Cw.view(np.int64))
     variants = hdc.tile_variants("classify", xt, ct, F, K)
-    try:
-        for v in variants:
-            hdc.set_tile("classify", xt, ct, F, K, v)
-            for split in (True, False):
-                say("split classify", case, "variant", v, "split", split)
-                lab, dists = hdc.classify(Xd, F, Pd, D, Cd, ct, start, d_trunc, stride, with_dists=True,
-                                          split=split)
-                torch.cuda.synchronize()
-                assert np.array_equal(dists.cpu().numpy(), dref), (v, split)
-                assert np.array_equal(lab.cpu().numpy(), lref), (v, split)
-    finally:
-        hdc.set_tile("classify", xt, ct, F, K, 0)
+    for v in variants:
+        for split in (True, False):
+            say("split classify", case, "variant", v, "split", split)
+            lab, dists = hdc.classify(Xd, F, Pd, D, Cd, ct, start, d_trunc, stride, with_dists=True, split=split,
+                                      tile=v)
+            torch.cuda.synchronize()
+            assert np.array_equal(dists.cpu().numpy(), dref), (v, split)
+            assert np.array_equal(lab.cpu().numpy(), lref), (v, split)
 
 
 def test_split_prepared_reuses_scratch(hdc):
@@ -111,24 +107,20 @@ def test_split_encode_matches_oracle(hdc, case):
     X, P = dg.random_case(n, F, D, xt, seed=7 * n + D)
     Xd, Pd = hdc.pad_cols(X), hdc.pad_cols(P)
     variants = hdc.tile_variants("encode", xt, ct, F, 1)
-    try:
-        for v in variants:
-            say("split encode", case, "variant", v)
-            hdc.set_tile("encode", xt, ct, F, 1, v)
-            H = hdc.encode(Xd, F, Pd, D, ct, s, e, k)
-            torch.cuda.synchronize()
-            got = H.cpu().numpy().view(np.uint64)
-            if xt == "fp32":
-                # the sign must be exact wherever |y| exceeds the fp32
-                # summation band gamma_F * sum |x'| (2x slack)
-                nb = hdc.dims_count(s, e, k)
-                Y, absum = O.project(X, P, ct, s, e, k)
-                rb = np.unpackbits(O.encode(X, P, ct, s, e, k).view(np.uint8), axis=1, bitorder="little")[:, :nb]
-                gb = np.unpackbits(got.view(np.uint8), axis=1, bitorder="little")[:, :nb]
-                gamma = 2 * F * 2.0 ** -24 / (1 - F * 2.0 ** -24)
-                sure = np.abs(Y) > gamma * absum[:, None]
-                assert np.array_equal(gb[sure], rb[sure]), v
-            else:
-                assert np.array_equal(got, O.encode(X, P, ct, s, e, k)), v
-    finally:
-        hdc.set_tile("encode", xt, ct, F, 1, 0)
+    for v in variants:
+        say("split encode", case, "variant", v)
+        H = hdc.encode(Xd, F, Pd, D, ct, s, e, k, tile=v)
+        torch.cuda.synchronize()
+        got = H.cpu().numpy().view(np.uint64)
+        if xt == "fp32":
+            # the sign must be exact wherever |y| exceeds the fp32
+            # summation band gamma_F * sum |x'| (2x slack)
+            nb = hdc.dims_count(s, e, k)
+            Y, absum = O.project(X, P, ct, s, e, k)
+            rb = np.unpackbits(O.encode(X, P, ct, s, e, k).view(np.uint8), axis=1, bitorder="little")[:, :nb]
+            gb = np.unpackbits(got.view(np.uint8), axis=1, bitorder="little")[:, :nb]
+            gamma = 2 * F * 2.0 ** -24 / (1 - F * 2.0 ** -24)
+            sure = np.abs(Y) > gamma * absum[:, None]
+            assert np.array_equal(gb[sure], rb[sure]), v
+        else:
+            assert np.array_equal(got, O.encode(X, P, ct, s, e, k)), v

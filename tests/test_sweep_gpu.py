@@ -28,12 +28,11 @@ def test_sweep_grid_matches_oracle(env):
     print("[case] sweep grid vs oracle, 300 queries x 60 configs", flush=True)
     X, y = env["Xs"][:300], env["ys"][:300]
     grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
-    correct, ticks = hdc.eval_configs(hdc.pad_cols(X), ds.F, torch.as_tensor(y).cuda(), hdc.pad_cols(ds.P),
-                                      ds.D, torch.as_tensor(env["C"].view(np.int64)).cuda(), grid)
-    torch.cuda.synchronize()
+    res = hdc.eval_configs(hdc.pad_cols(X), ds.F, torch.as_tensor(y).cuda(), hdc.pad_cols(ds.P),
+                           ds.D, torch.as_tensor(env["C"].view(np.int64)).cuda(), grid)
     ref = O.eval_configs(X, y, ds.P, env["C"], grid)
-    assert np.array_equal(correct.cpu().numpy(), ref)
-    assert (ticks.cpu().numpy() > 0).all()
+    assert np.array_equal(res["correct"], ref)
+    assert (res["n"] == 300).all() and (res["device_us"] > 0).all()
 
 
 def test_sweep_256_slots_consistent(env):
@@ -42,13 +41,11 @@ def test_sweep_256_slots_consistent(env):
     slots = [(d, k, 0, t) for (d, k, t) in dg.sweep_slots(4)]
     Xd, yd = hdc.pad_cols(env["Xs"]), torch.as_tensor(env["ys"]).cuda()
     Pd, Cd = hdc.pad_cols(ds.P), torch.as_tensor(env["C"].view(np.int64)).cuda()
-    correct, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)
-    correct2, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)
-    correct3, _ = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots, max_workgroups=7)   # few workers
-    torch.cuda.synchronize()
-    c = correct.cpu().numpy()
-    assert np.array_equal(c, correct2.cpu().numpy())
-    assert np.array_equal(c, correct3.cpu().numpy())
+    c = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)["correct"]
+    c2 = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots)["correct"]
+    c3 = hdc.eval_configs(Xd, ds.F, yd, Pd, ds.D, Cd, slots, max_workgroups=7)["correct"]   # few workers
+    assert np.array_equal(c, c2)
+    assert np.array_equal(c, c3)
     first = {}
     for s, v in zip(slots, c):
         assert first.setdefault(s, v) == v            # duplicates agree
@@ -67,9 +64,9 @@ def test_sweep_invalid_slots_do_no_work(env):
     hdc, ds = env["hdc"], env["ds"]
     X, y = env["Xs"][:100], env["ys"][:100]
     cfgs = [(99999, 1, 0, "int8"), (1024, 0, 0, "int8"), (1024, 1, 0, "fp32"), (1024, 1, 0, "int8")]
-    correct, ticks = hdc.eval_configs(hdc.pad_cols(X), ds.F, torch.as_tensor(y).cuda(), hdc.pad_cols(ds.P),
-                                      ds.D, torch.as_tensor(env["C"].view(np.int64)).cuda(), cfgs)
-    torch.cuda.synchronize()
-    c, t = correct.cpu().numpy(), ticks.cpu().numpy()
-    assert (c[:3] == 0).all() and (t[:3] == 0).all()
+    res = hdc.eval_configs(hdc.pad_cols(X), ds.F, torch.as_tensor(y).cuda(), hdc.pad_cols(ds.P),
+                           ds.D, torch.as_tensor(env["C"].view(np.int64)).cuda(), cfgs)
+    c, t = res["correct"], res["device_us"]
+    assert (c[:3] == 0).all() and (t[:3] == 0).all() and (res["n"][:3] == 0).all()
+    assert res["n"][3] == 100
     assert c[3] == (O.classify(X, ds.P, env["C"], "int8", 0, 1024, 1) == y).sum()

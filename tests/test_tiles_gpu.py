@@ -45,21 +45,17 @@ def test_every_variant_matches_oracle(hdc, case):
         lref, dref = O.classify(X, P, Cw, ct, with_dists=True)
     else:
         href = O.encode(X, P, ct)
-    try:
-        for v in variants:
-            print("[case]", case, "variant", v, flush=True)
-            hdc.set_tile(kind, xt, ct, F, K, v)
-            if kind == "classify":
-                lab, dists = hdc.classify(Xd, F, Pd, D, Cd, ct, with_dists=True)
-                torch.cuda.synchronize()
-                assert np.array_equal(lab.cpu().numpy(), lref), v
-                assert np.array_equal(dists.cpu().numpy(), dref), v
-            else:
-                H = hdc.encode(Xd, F, Pd, D, ct)
-                torch.cuda.synchronize()
-                assert np.array_equal(H.cpu().numpy().view(np.uint64), href), v
-    finally:
-        hdc.set_tile(kind, xt, ct, F, K, 0)
+    for v in variants:
+        print("[case]", case, "variant", v, flush=True)
+        if kind == "classify":
+            lab, dists = hdc.classify(Xd, F, Pd, D, Cd, ct, with_dists=True, tile=v)
+            torch.cuda.synchronize()
+            assert np.array_equal(lab.cpu().numpy(), lref), v
+            assert np.array_equal(dists.cpu().numpy(), dref), v
+        else:
+            H = hdc.encode(Xd, F, Pd, D, ct, tile=v)
+            torch.cuda.synchronize()
+            assert np.array_equal(H.cpu().numpy().view(np.uint64), href), v
 
 
 @pytest.mark.parametrize("K", [26, 100])
@@ -77,31 +73,31 @@ def test_sweep_item_sizes_agree_with_oracle(hdc, K):
     Xd, Pd = hdc.pad_cols(X), hdc.pad_cols(P)
     Cd = torch.as_tensor(Cw.view(np.int64)).cuda()
     td = torch.as_tensor(truth).cuda()
-    try:
-        for v in hdc.tile_variants("sweep", "int8", "int8", F, K):
-            print("[case] sweep K", K, "variant", v, flush=True)
-            hdc.set_tile("sweep", "int8", "int8", F, K, v)
-            correct, _ = hdc.eval_configs(Xd, F, td, Pd, D, Cd, cfgs)
-            torch.cuda.synchronize()
-            assert np.array_equal(correct.cpu().numpy(), ref), v
-    finally:
-        hdc.set_tile("sweep", "int8", "int8", F, K, 0)
+    variants = hdc.tile_variants("sweep", "int8", "int8", F, K)
+    for v in variants:
+        print("[case] sweep K", K, "variant", v, flush=True)
+        res = hdc.eval_configs(Xd, F, td, Pd, D, Cd, cfgs, tile=v)
+        assert np.array_equal(res["correct"], ref), v
+        assert (res["n"] == n).all() and (res["device_us"] > 0).all()
+    # a different work-item shape per configuration in one launch
+    mixed = [c + (variants[i % len(variants)],) for i, c in enumerate(cfgs)]
+    res = hdc.eval_configs(Xd, F, td, Pd, D, Cd, mixed)
+    assert np.array_equal(res["correct"], ref)
 
 
 def test_autotune_picks_a_compiled_variant(hdc, tmp_path):
     from paper_2606_26547_amd import autotune as AT
     shapes = [AT.Shape("classify", 617, 26, 2048, 8192), AT.Shape("encode", 617, 1, 2048, 8192),
               AT.Shape("sweep", 617, 26, 2048, 1000, cfgs=[(2048, 1, 0, "int8"), (1024, 2, 0, "fp8")])]
-    try:
-        choices = AT.autotune(shapes, reps=2)
-        for c in choices:
-            print("[case] autotune", c.shape.kind, c.chosen_name, c.variants, flush=True)
-            assert c.chosen in hdc.tile_variants(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K)
-            assert hdc.get_tile(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K) == c.chosen
-        path = str(tmp_path / "tiles.json")
-        AT.save(choices, path)
-        AT.reset(shapes)
-        assert AT.load(path) == len(shapes)
-        assert hdc.get_tile("classify", "int8", "int8", 617, 26) == choices[0].chosen
-    finally:
-        AT.reset(shapes)
+    choices = AT.autotune(shapes, reps=2)
+    table = AT.TileTable.from_choices(choices)
+    for c in choices:
+        print("[case] autotune", c.shape.kind, c.chosen_name, c.variants, flush=True)
+        assert c.chosen in hdc.tile_variants(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K)
+        assert table.get(c.shape.kind, "int8", "int8", c.shape.F, c.shape.K) == c.chosen
+    path = str(tmp_path / "tiles.json")
+    AT.save(choices, path)
+    loaded = AT.load(path)
+    assert len(loaded) == len(shapes)
+    assert loaded.get("classify", "int8", "int8", 617, 26) == choices[0].chosen
+    assert loaded.get("classify", "int8", "int8", 617, 40) == 0          # not tuned: built-in

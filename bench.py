@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 MFMA_INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
 # 32-bit VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the fp32
 # vector peak of 157.3 TFLOP/s counts an FMA as two flops and packs two lanes)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -49,7 +50,12 @@ def parse():
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=98304)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ceilings", action="store_true", help="also measure the device ceilings (random-operand "
+                    "int8 MFMA loop, HBM read stream) beside the published peaks")
     ap.add_argument("--no-extras", action="store_true", help="only the timed plain steps (profiling)")
+    ap.add_argument("--only", default="", help="comma list of the extra sections to run (profiling): train, "
+                    "bundle, sweep (with the tuned selection and per-call latency), hamming, adc, cosine, "
+                    "encode_side, retrain, ladder, serving, plain_fp32")
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile choices, no tuning launches")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--full-out", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
@@ -111,7 +117,7 @@ def compact(out: dict) -> dict:
     for key in ("sweep", "bundle", "plain_fp32"):
         if key in out:
             sec = out[key]
-            extras[key] = dict(_pick(sec, "ms", "slots", "queries_per_s", "accuracy", "GB_s"),
+            extras[key] = dict(_pick(sec, "ms", "slots", "queries_per_s", "accuracy", "test_accuracy", "GB_s"),
                                **({"frac": sec["roofline"]["frac"], "bound": sec["roofline"]["bound"]}
                                   if "roofline" in sec else {}))
     if "hamming_unfused" in out:
@@ -128,6 +134,9 @@ def compact(out: dict) -> dict:
     for key in ("cosine", "adc", "retrain"):
         if key in out and "roofline" in out[key]:
             extras[key + "_frac"] = out[key]["roofline"]["frac"]
+    if "ceilings" in out:
+        extras["ceilings"] = {"mfma_i8_TOPs_best": max(out["ceilings"]["mfma_i8_TOPs"].values()),
+                              "hbm_read_GBs_best": max(out["ceilings"]["hbm_read_GBs"].values())}
     if extras:
         c["extras"] = extras
     c["full_record"] = out.get("full_record")
@@ -266,15 +275,22 @@ def main():
                      "ops_per_launch": ops},
     }
 
-    if not args.no_extras:
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(name):
+        return not args.no_extras and (not only or name in only)
+
+    if want("train"):
         # -------------------------------------------------------- training
         ms_train, _, _ = event_loop(train, 5, 1)
         _, ms_bundle_tr, _ = event_loop(lambda: hdc.bundle(Htr, D, ytr, K, ws_b), 20, 3)
         out["train"] = {"ms": ms_train, "n_train": int(Xtr.shape[0]), "bundle_ms": ms_bundle_tr,
                         "note": "encode of the training set + majority bundle (bundle_ms: the bundle alone, "
                                 "device time)"}
+    if want("bundle"):
         # -------------------------------------------------------- bundling at HBM scale
         out["bundle"] = bundle_bench(dev, hdc, torch, event_loop)
+    if want("sweep"):
         # -------------------------------------------------------- sweep + tuned selection
         grid = [(d, k, 0, t) for (d, k, t) in dg.sweep_grid()]
         tuner.sweep(Xsd, F, ysd, Pd, D, Cw, slots, tile=sweep_tile)   # warm-up launch
@@ -286,7 +302,7 @@ def main():
         # operands, persistent kernel, results down into pinned memory) with
         # events on the launch stream
         sweep_out = torch.empty(16 * len(slots), dtype=torch.uint8, pin_memory=True)
-        ws_sw = torch.empty(hdc.lib().hdc_eval_configs_workspace_bytes(len(slots), D, K), dtype=torch.uint8,
+        ws_sw = torch.empty(hdc.lib().hdc_eval_configs_workspace_bytes(len(slots), F, D, K), dtype=torch.uint8,
                             device=dev)
         _, sweep_ms, _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, slots, ws=ws_sw,
                                                              tile=sweep_tile, out=sweep_out), 5, 1)
@@ -333,6 +349,7 @@ def main():
                          "queries_per_call": nte}
         out["latency"] = lat
         out["p99_ms"] = lat["plain"]["p99_ms"]
+    if want("hamming"):
         # -------------------------------------------------------- unfused Hamming search
         # packed query hypervectors (2^20 rows) against resident class bits:
         # bytes = the queries read once (class words are cached), HBM-bound.
@@ -363,20 +380,35 @@ def main():
         out["hamming_unfused"] = ham
         log("hamming GB/s: %s" % {k: (round(v["mfma"]["GB_s"], 1), round(v["popcount"]["GB_s"], 1), v["agree"])
                                   for k, v in ham.items()})
+    if want("plain_fp32"):
+        # -------------------------------------------------------- the plain fp32 workload
+        out["plain_fp32"] = plain_fp32(dev, dg, hdc, torch, event_loop, N)
+    if want("adc"):
         # -------------------------------------------------------- ADC-chunked similarity
         out["adc"] = adc_emulation(dev, hdc, torch, event_loop, ds, Xte, Pd, Cw, F, D)
+    if want("cosine"):
         # -------------------------------------------------------- cosine similarity
         out["cosine"] = cosine_similarity(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
+    if want("encode_side"):
         # -------------------------------------------------------- encode-side knobs
         out["encode_side"] = encode_side(dev, hdc, dg, torch, np, event_loop, sp, Xtr, ytr, Xte, Pd, Xqd, yqd,
                                          F, K, D)
+    if want("retrain"):
         # -------------------------------------------------------- retraining epochs
         out["retrain"] = retraining(dev, hdc, torch, event_loop, ds, Xtr, ytr, Xte, Pd, F, K, D)
+    if want("ladder"):
         # -------------------------------------------------------- precision ladder
         out["ladder"] = ladder(dev, dg, hdc, tuner, torch, np, event_loop, ds, Xte, Pd, Cw, Xqd, F, D)
+    if want("serving"):
         # -------------------------------------------------------- serving
         if args.serve_seconds > 0:
             out["serving"] = serving(args, dev, dg, hdc, tuner, torch)
+
+    if args.ceilings:
+        # ------------------------------------------------------------ device ceilings
+        from paper_2606_26547_amd import ceilings
+        out["ceilings"] = ceilings.measure()
+        log("ceilings: %s" % out["ceilings"])
 
     # ------------------------------------------------------------ CPU oracle
 
@@ -407,7 +439,7 @@ def main():
         log("cpu oracle: %.1f q/s on %d threads (agree %.4f), tuned %.1f q/s, one thread %.1f q/s" %
             (n_cpu / dt, O.threads(), agree, out["cpu_baseline"].get("tuned_value", 0.0),
              out["cpu_baseline"]["single_thread_value"]))
-        if not args.no_extras:
+        if not args.no_extras and not only:
             out["cpu_baseline"]["rows"] = oracle_rows(O, np, ds, F, K, D)
 
     out["full_record"] = args.full_out
@@ -419,6 +451,37 @@ def main():
         log("could not write the full record to %s: %s" % (args.full_out, e))
         out["full_record"] = None
     print(json.dumps(compact(out)), flush=True)
+
+
+def plain_fp32(dev, dg, hdc, torch, event_loop, N):
+    """The plain fp32 workload (64 fp32 features, 10 classes, D = 2048, no
+    approximation): fp32 encode of the 1000 training vectors, majority
+    bundle, fused fp32 classify of the 200 test vectors, then a batch of N
+    further queries of the same mixture for throughput (fp32 MFMA)."""
+    d = dg.config_c1(1)
+    F, K, D = d.X_train.shape[1], d.K, d.P.shape[0]
+    Pd = hdc.pad_cols(d.P, dev)
+    Xtr, Xte = hdc.pad_cols(d.X_train, dev), hdc.pad_cols(d.X_test, dev)
+    ytr = torch.as_tensor(d.y_train).to(dev)
+    Htr = hdc.encode(Xtr, F, Pd, D, "fp32")
+    Cw, _ = hdc.bundle(Htr, D, ytr, K)
+    lab = hdc.classify(Xte, F, Pd, D, Cw, "fp32")
+    acc = float((lab.cpu().numpy() == d.y_test).mean())
+    Xq, yq = dg.c1_queries(N, 1, stream=3)
+    Xqd = hdc.pad_cols(Xq, dev)
+    prep = hdc.Prepared(Cw, D, "fp32")
+    lq = torch.empty(N, dtype=torch.int32, device=dev)
+    _, ms, _ = event_loop(lambda: prep(Xqd, F, Pd, lq), 10, 2)
+    acc_b = float((lq.cpu().numpy() == yq).mean())
+    flops = 2.0 * F * D * N
+    tf = flops / (ms / 1e3) / 1e12
+    log("plain fp32: test accuracy %.3f, batch %d: %.3f ms, %.3e q/s, %.1f TFLOP/s" % (acc, N, ms, N / ms * 1e3, tf))
+    del Xqd
+    return {"F": F, "K": K, "D": D, "test_accuracy": acc, "batch": N, "batch_accuracy": acc_b, "ms": ms,
+            "queries_per_s": N / (ms / 1e3),
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / MFMA_FP32_PEAK_TFLOPS, "flops_per_launch": flops,
+                         "note": "2 F D per query on v_mfma_f32_32x32x2_f32 (fp32 dense peak)"}}
 
 
 def bundle_bench(dev, hdc, torch, event_loop, n=1 << 20, nbits=10240, K=26):

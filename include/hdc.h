@@ -433,7 +433,9 @@ hdc_status hdc_classify_prepared(void *stream,
  *          the stream has passed the call (into page-locked memory the copy
  *          is asynchronous; into pageable memory the call returns only
  *          after the results have arrived)
- *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, D, K), 256-byte aligned
+ *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, F, D, K), 256-byte
+ *          aligned (per-configuration class operands, and the projection
+ *          rows converted to E4M3 for the direct-staged body)
  *   max_workgroups  0: as many workgroups as fit on the device at once;
  *          otherwise at most this many (a configuration job that shares
  *          the device with latency-bound inference leaves it room; the
@@ -451,7 +453,7 @@ typedef struct {
     double device_us;
 } hdc_config_result;
 
-size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
+size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t F, int32_t D, int32_t K);
 hdc_status hdc_eval_configs(void *stream,
                             const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
                             const int32_t *truth,
@@ -482,9 +484,12 @@ hdc_status hdc_eval_configs(void *stream,
  *             sweep: HDC_TILE_SWEEP_256 (work items of 256 queries: int8
  *             configurations take two query tiles per wave where the
  *             registers allow), HDC_TILE_SWEEP_128 (items of 128) and
- *             HDC_TILE_SWEEP_256_DMA (items of 256, int8-feature int8
- *             configurations on the classifier's HDC_TILE_DMA_2X2 body;
- *             int8 features, K <= 32, F <= 640)
+ *             HDC_TILE_SWEEP_256_DMA (items of 256 on direct-staged bodies:
+ *             int8 configurations on the classifier's HDC_TILE_DMA_2X2
+ *             body with int8 features, E4M3 configurations on the same 2x2
+ *             shape reading projection rows converted once per launch,
+ *             bf16 configurations as HDC_TILE_SWEEP_256; K <= 32,
+ *             F <= 640)
  * hdc_tile_variants writes up to `cap` (host array) variant ids the bucket
  * is compiled with, the built-in choice first, and returns how many there
  * are, or -1 for a shape outside the compiled kernels.

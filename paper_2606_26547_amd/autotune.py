@@ -99,7 +99,7 @@ def tune(sh: Shape, reps: int = 5, margin: float = 0.03, seed: int = 1) -> Choic
         result = lambda: H.clone()                                               # noqa: E731
     else:
         truth = torch.randint(0, sh.K, (sh.n,), dtype=torch.int32, device="cuda")
-        ws = torch.empty(int(hdc.lib().hdc_eval_configs_workspace_bytes(len(sh.cfgs), sh.D, sh.K)),
+        ws = torch.empty(int(hdc.lib().hdc_eval_configs_workspace_bytes(len(sh.cfgs), sh.F, sh.D, sh.K)),
                          dtype=torch.uint8, device="cuda")
         out = torch.empty(16 * len(sh.cfgs), dtype=torch.uint8, pin_memory=True)
         cfgs = [tuple(c[:4]) for c in sh.cfgs]

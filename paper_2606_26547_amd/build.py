@@ -20,6 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "hip")
 LIB = os.path.join(PKG, "libhdc.so")
+CEIL_LIB = os.path.join(PKG, "libhdc_ceilings.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled for all device code.
@@ -59,6 +60,13 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])
     os.replace(tmp, LIB)
+    # the ceiling probes (measurement only), a library of their own
+    csrc = os.path.join(PKG, "ceilings", "hdc_ceilings.hip")
+    tmp = CEIL_LIB + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, "-shared", "-o", tmp, csrc], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (csrc, r.stderr[-4000:]))
+    os.replace(tmp, CEIL_LIB)
     if verbose:
         print("built %s from %d sources in %.1fs" % (LIB, len(srcs), time.time() - t0), flush=True)
     return LIB

@@ -627,11 +627,11 @@ hdc_status hdc_classify(void *stream, const void *X, hdc_dtype x_type, int64_t n
                                  ws_bytes, scratch, scratch_bytes, tile);
 }
 
-size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
+size_t hdc_eval_configs_workspace_bytes(int32_t ncfg, int32_t F, int32_t D, int32_t K)
 {
     if (ncfg > kMaxConfigs)
         return 0;
-    return sweep_workspace_bytes(ncfg, D, K);
+    return sweep_workspace_bytes(ncfg, F, D, K);
 }
 
 hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64_t n, int32_t F, int64_t ldx,
@@ -652,7 +652,7 @@ hdc_status hdc_eval_configs(void *stream, const void *X, hdc_dtype x_type, int64
     for (int32_t i = 0; i < ncfg; ++i)
         if (cfgs[i].tile_id < 0 || !tile_compiled(KK_SWEEP, xt, C_I8, F, K, cfgs[i].tile_id))
             return HDC_ERR_UNSUPPORTED;
-    if (!ws || ws_bytes < hdc_eval_configs_workspace_bytes(ncfg, D, K) || !aligned(ws, 256))
+    if (!ws || ws_bytes < hdc_eval_configs_workspace_bytes(ncfg, F, D, K) || !aligned(ws, 256))
         return HDC_ERR_WORKSPACE;
     if (n == 0) {
         for (int32_t i = 0; i < ncfg; ++i)

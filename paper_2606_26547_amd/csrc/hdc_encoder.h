@@ -32,14 +32,18 @@ struct Encoder {
     static constexpr int RSB = KS * KB + 16;               // LDS row stride (16 B skew)
     static constexpr int PIECES = (KS * KSTEP + 15) / 16;  // 16-byte int8 pieces per row (max)
     static constexpr int MP = (PIECES + 7) / 8;            // pieces per thread (8 threads / row)
-    // DMA: int8 projection rows and class fragments go from global memory
-    // straight into LDS (global_load_lds, 16 bytes per lane; int8 features
-    // only, which need no column sums), three stages deep.  Each load fills
-    // 1 KiB of LDS contiguously, so a stage is NIW loads per wave and the
-    // units past the 32 rows land in the stage's slack.
+    // DMA: projection rows and class fragments go from global memory
+    // straight into LDS (global_load_lds, 16 bytes per lane), three stages
+    // deep.  Each load fills 1 KiB of LDS contiguously, so a stage is NIW
+    // loads per wave and the units past the 32 rows land in the stage's
+    // slack.  The rows are copied as they are: int8 +-1 for the int8 path
+    // (int8 features: uint8 ones would need column sums), or rows already
+    // in the compute type (bf16 / E4M3 +-1.0, built once by the caller) for
+    // those paths, which take either feature type.
     // A chunk is RT row tiles of 32 dimensions (RT > 1 with DMA staging
     // only); its class operand is RT * KT KiB.
-    static_assert(!DMA || (CT == C_I8 && XF == 0), "direct LDS staging is for int8 features on int8 MFMA");
+    static_assert(!DMA || (XF == 0 && (CT == C_I8 || CT == C_BF16 || CT == C_FP8)),
+                  "direct LDS staging is for integer features on the int8, bf16 and E4M3 paths");
     static_assert(RT == 1 || DMA, "several row tiles per chunk need direct LDS staging");
     static constexpr int CH = kDimChunk * RT;              // dimensions per chunk
     static constexpr int UPR = RSB / 16;                   // 16-byte units per LDS row
@@ -671,7 +675,7 @@ struct Encoder {
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
         const int64_t qbase = qblock + (int64_t)wave * QPW;
         const int ks_used = (a.F + KSTEP - 1) / KSTEP;
-        const int npc = (ks_used * KSTEP + 15) / 16;
+        const int npc = (ks_used * KB + 15) / 16;   // 16-byte pieces of a row holding features
         const int NC = (a.nd + CH - 1) / CH;
         // loads issued per step after those of the chunk waited for (stores
         // of the encode epilogue are not counted: waiting for more is safe)

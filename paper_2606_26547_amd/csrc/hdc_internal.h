@@ -211,7 +211,7 @@ struct SweepArgs {
     size_t ws_bytes;
     int32_t max_wg;           // 0: fill the device
 };
-size_t sweep_workspace_bytes(int32_t ncfg, int32_t D, int32_t K);
+size_t sweep_workspace_bytes(int32_t ncfg, int32_t F, int32_t D, int32_t K);
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 
 }  // namespace hdc

@@ -2,20 +2,30 @@
 // under many approximation configurations (the inner loop of the tuning
 // system: run each candidate, read back its accuracy and time).
 //
-// Workspace layout (all offsets 256-byte aligned):
+// The host validates the configurations, orders them longest first, lays
+// out their work items and finds the distinct dimension sets (configurations
+// of the same start, end and stride share one class operand), and sends all
+// of it up in one copy.  Workspace layout (all offsets 256-byte aligned):
 //   [0]            queue counter (uint32)
-//   [256]          the configurations as passed (copied from the host)
-//   [..]           slot descriptors, ncfg x SlotDesc
+//   [256]          slot descriptors, ncfg x SlotDesc
 //   [..]           slot order (longest first), ncfg x int32
 //   [..]           first work item of each slot in that order, ncfg + 1 x int32
-//   [..]           per-slot results as counted (correct, n, device ticks)
+//   [..]           per-slot counters (correct, n, device ticks), zeroed
+//   [..]           distinct dimension sets, up to ncfg x TableDesc
 //   [..]           per-slot results as returned (correct, n, device_us)
-//   [..]           per-slot class operand regions of fixed size
-//                  (chunks(D) * KT KiB table + 128 int32 popcounts)
+//   [..]           class operand regions of fixed size, one per distinct
+//                  dimension set (chunks(D) * KT KiB table + 128 int32
+//                  popcounts)
+//   [..]           projection rows converted to E4M3 (direct-staged body)
 // Work item i belongs to the slot whose item range holds it (a binary search
 // over the item offsets); a workgroup takes items from the queue until it is
 // exhausted, so every workgroup reaches the exit whatever the grid size.
 #include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
 
 #include "hdc_encoder.h"
 
@@ -25,7 +35,13 @@ struct SlotDesc {
     int32_t s0, stride, nd, ct;   // ct < 0: invalid configuration (no work)
     int32_t iq;                   // work items: 1 = 128 queries, 2 = 256, 3 = 256 on the direct-staged body
     int32_t tiles;                // work items of the slot
-    int64_t cost;
+    int32_t table;                // its class operand (distinct dimension set)
+    int32_t pad;
+};
+
+// A distinct dimension set.
+struct TableDesc {
+    int32_t s0, stride, nd, pad;
 };
 
 // Per-slot counters of the persistent kernel.
@@ -41,112 +57,46 @@ inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 // 2x2 body reads them in pairs; the pad chunk is zero).
 inline size_t sweep_table_bytes(int D, int K) { return (size_t)table_chunks(D) * sweep_kt(K) * 1024; }
 
+// Rows of the projection converted for the direct-staged E4M3 body: +-1 as
+// E4M3 bytes, pitch ldp_conv (F rounded up to 64), pad columns 0.
+inline size_t conv_pitch(int F) { return (size_t)(F + 63) / 64 * 64; }
+
 struct SweepLayout {
-    size_t off_cfg, off_desc, off_order, off_items, off_count, off_res, off_regions, region, total;
-    SweepLayout(int ncfg, int D, int K)
+    size_t off_desc, off_order, off_items, off_count, off_tabs, off_res, off_regions, region;
+    size_t off_p8, ldp_conv, total;
+    SweepLayout(int ncfg, int F, int D, int K)
     {
-        off_cfg = 256;
-        off_desc = align256(off_cfg + (size_t)ncfg * sizeof(hdc_config));
+        off_desc = 256;
         off_order = align256(off_desc + (size_t)ncfg * sizeof(SlotDesc));
         off_items = align256(off_order + (size_t)ncfg * 4);
         off_count = align256(off_items + (size_t)(ncfg + 1) * 4);
-        off_res = align256(off_count + (size_t)ncfg * sizeof(SlotCount));
+        off_tabs = align256(off_count + (size_t)ncfg * sizeof(SlotCount));
+        off_res = align256(off_tabs + (size_t)ncfg * sizeof(TableDesc));
         off_regions = align256(off_res + (size_t)ncfg * sizeof(hdc_config_result));
         region = align256(sweep_table_bytes(D, K) + 128 * 4);
-        total = off_regions + region * (size_t)ncfg;
+        ldp_conv = conv_pitch(F);
+        off_p8 = align256(off_regions + region * (size_t)ncfg);
+        total = align256(off_p8 + (size_t)D * ldp_conv);
     }
 };
 
-size_t sweep_workspace_bytes(int32_t ncfg, int32_t D, int32_t K)
+size_t sweep_workspace_bytes(int32_t ncfg, int32_t F, int32_t D, int32_t K)
 {
-    if (ncfg <= 0 || D <= 0 || K <= 0 || K > kMaxK)
+    if (ncfg <= 0 || F <= 0 || D <= 0 || K <= 0 || K > kMaxK)
         return 0;
-    return SweepLayout(ncfg, D, K).total;
+    return SweepLayout(ncfg, F, D, K).total;
 }
 
-// Exclusive prefix sums over the block of one value per thread (at most 16
-// waves); `wt` is LDS of 16 ints; returns the block total in *total.
-__device__ __forceinline__ int block_exscan(int v, int *wt, int *total)
+// The converted projection rows (E4M3 +-1.0, zero past F).
+__global__ __launch_bounds__(256) void k_sweep_convert(const int8_t *__restrict__ P, int64_t ldp, int D, int F,
+                                                       uint8_t *__restrict__ ws, SweepLayout L)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int s = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(s, o);
-        if (lane >= o)
-            s += u;
+    uint8_t *p8 = ws + L.off_p8;
+    const int64_t total = (int64_t)D * (int64_t)L.ldp_conv;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t d = i / (int64_t)L.ldp_conv, f = i % (int64_t)L.ldp_conv;
+        p8[i] = f < F ? (P[d * ldp + f] < 0 ? 0xB8u : 0x38u) : 0u;
     }
-    if (lane == 63)
-        wt[wave] = s;
-    __syncthreads();
-    int base = 0, all = 0;
-    for (int w = 0; w < nw; ++w) {
-        base += w < wave ? wt[w] : 0;
-        all += wt[w];
-    }
-    __syncthreads();
-    *total = all;
-    return base + s - v;
-}
-
-// Validate configurations, zero the counters, order the slots by decreasing
-// cost (dimensions x compute cost; ties keep slot order) and lay out their
-// work items in that order.  One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_sweep_setup(int ncfg, int D, int64_t n, int x_type, int K,
-                                                      uint8_t *__restrict__ ws, SweepLayout L)
-{
-    __shared__ int wt[16];
-    const hdc_config *cfgs = (const hdc_config *)(ws + L.off_cfg);
-    SlotDesc *desc = (SlotDesc *)(ws + L.off_desc);
-    int32_t *order = (int32_t *)(ws + L.off_order);
-    int32_t *items = (int32_t *)(ws + L.off_items);
-    SlotCount *cnt = (SlotCount *)(ws + L.off_count);
-    for (int i = threadIdx.x; i < ncfg; i += blockDim.x) {
-        const hdc_config c = cfgs[i];
-        SlotDesc s;
-        s.s0 = c.start;
-        s.stride = c.stride;
-        s.ct = c.dtype == HDC_INT8 ? C_I8 : c.dtype == HDC_BF16 ? C_BF16 : c.dtype == HDC_FP8_E4M3 ? C_FP8 : -1;
-        const bool ok = s.ct >= 0 && c.stride >= 1 && c.start >= 0 && c.d_trunc > c.start && c.d_trunc <= D;
-        if (!ok)
-            s.ct = -1;
-        s.nd = ok ? (c.d_trunc - c.start + c.stride - 1) / c.stride : 0;
-        s.cost = (int64_t)s.nd * (s.ct == C_BF16 ? 2 : 1);
-        // built-in work items: 256 queries
-        s.iq = c.tile_id == SV_ITEM128 ? 1 : c.tile_id == SV_ITEM256_DMA ? 3 : 2;
-        s.tiles = ok ? (int32_t)((n + (s.iq == 1 ? 127 : 255)) / (s.iq == 1 ? 128 : 256)) : 0;
-        desc[i] = s;
-        cnt[i].correct = 0;
-        cnt[i].n = ok ? (int32_t)n : 0;
-        cnt[i].ticks = 0;
-    }
-    if (threadIdx.x == 0)
-        ((uint32_t *)ws)[0] = 0u;
-    __syncthreads();
-    for (int i = threadIdx.x; i < ncfg; i += blockDim.x) {
-        const int64_t ci = desc[i].cost;
-        int rank = 0;
-        for (int j = 0; j < ncfg; ++j) {
-            const int64_t cj = desc[j].cost;
-            rank += (cj > ci) || (cj == ci && j < i);
-        }
-        order[rank] = i;
-    }
-    __syncthreads();
-    // first item of each rank: thread t covers ranks [t * per, (t + 1) * per)
-    const int per = (ncfg + blockDim.x - 1) / blockDim.x;
-    const int r0 = threadIdx.x * per;
-    int local = 0;
-    for (int r = r0; r < r0 + per && r < ncfg; ++r)
-        local += desc[order[r]].tiles;
-    int total;
-    int run = block_exscan(local, wt, &total);
-    for (int r = r0; r < r0 + per && r < ncfg; ++r) {
-        items[r] = run;
-        run += desc[order[r]].tiles;
-    }
-    if (threadIdx.x == 0)
-        items[ncfg] = total;
 }
 
 // Per-slot results in the returned form: device time in microseconds.
@@ -169,9 +119,9 @@ __global__ __launch_bounds__(256) void k_sweep_tables(const uint64_t *__restrict
                                                       uint8_t *__restrict__ ws, SweepLayout L, int KT,
                                                       int64_t per_slot)
 {
-    const int slot = blockIdx.y;
-    const SlotDesc s = ((const SlotDesc *)(ws + L.off_desc))[slot];
-    int8_t *tab = (int8_t *)(ws + L.off_regions + L.region * slot);
+    const int t = blockIdx.y;
+    const TableDesc s = ((const TableDesc *)(ws + L.off_tabs))[t];
+    int8_t *tab = (int8_t *)(ws + L.off_regions + L.region * t);
     // whole pairs of chunks; chunks past nd are written as zeros
     const int64_t total = (int64_t)((s.nd + 2 * kDimChunk - 1) / (2 * kDimChunk)) * 2 * KT * 64;
     for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total && idx < per_slot;
@@ -200,9 +150,9 @@ __global__ __launch_bounds__(256) void k_sweep_popc(const uint64_t *__restrict__
                                                     uint8_t *__restrict__ ws, SweepLayout L, size_t table_bytes)
 {
     __shared__ int part[256];
-    const int slot = blockIdx.y, k = blockIdx.x;
-    const SlotDesc s = ((const SlotDesc *)(ws + L.off_desc))[slot];
-    int32_t *popc = (int32_t *)(ws + L.off_regions + L.region * slot + table_bytes);
+    const int t = blockIdx.y, k = blockIdx.x;
+    const TableDesc s = ((const TableDesc *)(ws + L.off_tabs))[t];
+    int32_t *popc = (int32_t *)(ws + L.off_regions + L.region * t + table_bytes);
     int acc = 0;
     if (k < K)
         for (int64_t dl = threadIdx.x; dl < s.nd; dl += 256) {
@@ -246,20 +196,30 @@ __device__ __forceinline__ void sweep_pass(EncodeArgs &a, uint8_t *smem, int64_t
 // K steps (640 features).
 constexpr bool sweep_qt2(int ct, int ks, int kt) { return ct == C_I8 && ks <= 20 && kt == 1; }
 
-// The fused classifier's direct-staged 2x2 body on one 256-query item
-// (int8 features on the int8 path).
-template <int KS, int KT>
+// Direct-staged bodies of the sweep (work items of 256 queries): up to 640
+// features and one class tile, the int8 path (int8 features) and the E4M3
+// path on the fused classifier's 2x2 shape; the E4M3 body reads projection
+// rows converted once per launch.  (A bf16 body would hold one query tile
+// only, beside its 40-step operand: one LDS fragment per MFMA then keeps
+// LDS, not the matrix cores, busy, and it measured slower than register
+// staging; bf16 configurations stage through registers.)
+constexpr bool dma_sweep_fits(int ct, int ks, int kt)
+{
+    return kt == 1 && (ct == C_I8 || ct == C_FP8) && ks * kstep_of(ct) <= 640;
+}
+
+template <int CT, int KS, int KT, int QT, int RT>
 __device__ __forceinline__ void sweep_pass_dma(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
                                                SlotCount *res)
 {
-    typedef Encoder<C_I8, 0, 2, KS, KT, M_CLASSIFY, 1, true, 2> E;
-    v16i dacc[KT][2];
+    typedef Encoder<CT, 0, QT, KS, KT, M_CLASSIFY, 1, true, RT> E;
+    v16i dacc[KT][QT];
     E::run(a, smem, qblock, dacc);
-    int32_t lab[2];
+    int32_t lab[QT];
     E::finish(a, qblock, dacc, lab);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
+    for (int qt = 0; qt < QT; ++qt) {
         const int64_t q = qblock + (int64_t)wave * E::QPW + qt * 32 + (lane & 31);
         const bool ok = lane < 32 && q < a.n && lab[qt] == truth[q];
         const uint64_t m = __ballot(ok);
@@ -271,15 +231,15 @@ __device__ __forceinline__ void sweep_pass_dma(EncodeArgs &a, uint8_t *smem, int
 // A work item of 128 queries (IQ = 1) or 256 (IQ = 2, 3).  With IQ = 2,
 // int8 slots take both query tiles per wave in one pass where the registers
 // allow (each projection fragment staged once for 256 queries), other slots
-// run two passes; IQ = 3 runs int8-feature int8 slots on the direct-staged
-// 2x2 body instead (where it is compiled), the rest as IQ = 2.
+// run two passes; IQ = 3 runs on the direct-staged bodies where they are
+// compiled (int8 slots need int8 features), the rest as IQ = 2.
 template <int CT, int KS, int KT, int IQ>
 __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *smem, int64_t qblock, const int32_t *truth,
                                                      SlotCount *res)
 {
-    if constexpr (IQ == 3 && CT == C_I8 && big_tile(KS, KT)) {
-        if (a.x_type == X_INT8) {
-            sweep_pass_dma<KS, KT>(a, smem, qblock, truth, res);
+    if constexpr (IQ == 3 && dma_sweep_fits(CT, KS, KT)) {
+        if (CT != C_I8 || a.x_type == X_INT8) {
+            sweep_pass_dma<CT, KS, KT, 2, 2>(a, smem, qblock, truth, res);
             return;
         }
     }
@@ -295,18 +255,28 @@ __device__ __attribute__((noinline)) void sweep_item(EncodeArgs &a, uint8_t *sme
     }
 }
 
+template <int CT, int KS, int KT, int QT, int RT>
+constexpr int dma_lds()
+{
+    if constexpr (dma_sweep_fits(CT, KS, KT))
+        return Encoder<CT, 0, QT, KS, KT, M_CLASSIFY, 1, true, RT>::LDS;
+    else
+        return 0;
+}
+
 template <int FB, int KT, int IQ>
 struct SweepLds {
     static constexpr int a = Encoder<C_I8, 0, 2, FB / 32, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int b = Encoder<C_FP8, 0, 1, FB / 64, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int c = Encoder<C_BF16, 0, 1, FB / 16, KT, M_CLASSIFY, 1>::LDS;
     static constexpr int d = Encoder<C_I8, 0, 1, FB / 32, KT, M_CLASSIFY, 1>::LDS;
-    static constexpr int e = (IQ == 3 && big_tile(FB / 32, KT))
-                                 ? Encoder<C_I8, 0, 2, FB / 32, KT, M_CLASSIFY, 1, true, 2>::LDS : 0;
+    static constexpr int e = IQ == 3 ? dma_lds<C_I8, FB / 32, KT, 2, 2>() : 0;
+    static constexpr int f = IQ == 3 ? dma_lds<C_FP8, FB / 64, KT, 2, 2>() : 0;
     static constexpr int ab = a > b ? a : b;
     static constexpr int cd = c > d ? c : d;
+    static constexpr int ef = e > f ? e : f;
     static constexpr int abcd = ab > cd ? ab : cd;
-    static constexpr int value = abcd > e ? abcd : e;
+    static constexpr int value = abcd > ef ? abcd : ef;
 };
 
 // The persistent kernel.  Each slot runs with its own work-item size (its
@@ -314,7 +284,7 @@ struct SweepLds {
 template <int FB, int KT>
 __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *__restrict__ truth,
                                                uint8_t *__restrict__ ws, SweepLayout L, size_t table_bytes,
-                                               int ncfg)
+                                               int ncfg, int64_t ldp_conv)
 {
     __shared__ __align__(16) uint8_t smem[SweepLds<FB, KT, 3>::value];
     __shared__ int item_s;
@@ -350,8 +320,13 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         a.s0 = s.s0;
         a.stride = s.stride;
         a.nd = s.nd;
-        a.ctab = (const int8_t *)(ws + L.off_regions + L.region * slot);
-        a.cpop = (const int32_t *)(ws + L.off_regions + L.region * slot + table_bytes);
+        // the direct-staged E4M3 body reads the converted rows
+        if (s.iq == 3 && s.ct == C_FP8 && dma_sweep_fits(C_FP8, FB / 64, KT)) {
+            a.P = (const int8_t *)(ws + L.off_p8);
+            a.ldp = ldp_conv;
+        }
+        a.ctab = (const int8_t *)(ws + L.off_regions + L.region * s.table);
+        a.cpop = (const int32_t *)(ws + L.off_regions + L.region * s.table + table_bytes);
         const int64_t qblock = (int64_t)tile * (s.iq == 1 ? 1 : 2) * 32 * kWaves;
         SlotCount *res = &cnt[slot];
         if (s.ct == C_I8) {
@@ -364,8 +339,10 @@ __global__ __launch_bounds__(256) void k_sweep(EncodeArgs base, const int32_t *_
         } else if (s.ct == C_FP8) {
             if (s.iq == 1)
                 sweep_item<C_FP8, FB / 64, KT, 1>(a, smem, qblock, truth, res);
-            else
+            else if (s.iq == 2)
                 sweep_item<C_FP8, FB / 64, KT, 2>(a, smem, qblock, truth, res);
+            else
+                sweep_item<C_FP8, FB / 64, KT, 3>(a, smem, qblock, truth, res);
         } else {
             if (s.iq == 1)
                 sweep_item<C_BF16, FB / 16, KT, 1>(a, smem, qblock, truth, res);
@@ -392,7 +369,7 @@ static hipError_t launch_sweep_kernel(const EncodeArgs &base, const SweepArgs &a
     if (a.max_wg > 0 && a.max_wg < grid)
         grid = a.max_wg;
     hipLaunchKernelGGL((k_sweep<FB, KT>), dim3(grid), dim3(256), 0, st, base, a.truth, a.ws, L, table_bytes,
-                       a.ncfg);
+                       a.ncfg, (int64_t)L.ldp_conv);
     return hipGetLastError();
 }
 
@@ -407,21 +384,77 @@ static hipError_t launch_sweep_fb(const EncodeArgs &base, const SweepArgs &a, co
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
 {
-    const SweepLayout L(a.ncfg, a.D, a.K);
+    const SweepLayout L(a.ncfg, a.F, a.D, a.K);
     const int KT = sweep_kt(a.K);
     const size_t table_bytes = sweep_table_bytes(a.D, a.K);
-    // the configurations go up with the other work of the stream (from
-    // pageable memory the runtime stages them before returning)
-    hipError_t e = hipMemcpyAsync(a.ws + L.off_cfg, a.cfgs, (size_t)a.ncfg * sizeof(hdc_config),
-                                  hipMemcpyHostToDevice, st);
+    // ---- host setup: slot descriptors, order, work items, distinct sets
+    std::vector<uint8_t> blob(L.off_regions, 0);
+    SlotDesc *desc = (SlotDesc *)(blob.data() + L.off_desc);
+    int32_t *order = (int32_t *)(blob.data() + L.off_order);
+    int32_t *items = (int32_t *)(blob.data() + L.off_items);
+    SlotCount *cnt = (SlotCount *)(blob.data() + L.off_count);
+    TableDesc *tabs = (TableDesc *)(blob.data() + L.off_tabs);
+    std::vector<int64_t> cost(a.ncfg);
+    std::map<std::tuple<int, int, int>, int> seen;
+    bool direct = false;
+    for (int i = 0; i < a.ncfg; ++i) {
+        const hdc_config c = a.cfgs[i];
+        SlotDesc s;
+        memset(&s, 0, sizeof s);
+        s.ct = c.dtype == HDC_INT8 ? C_I8 : c.dtype == HDC_BF16 ? C_BF16 : c.dtype == HDC_FP8_E4M3 ? C_FP8 : -1;
+        const bool ok = s.ct >= 0 && c.stride >= 1 && c.start >= 0 && c.d_trunc > c.start && c.d_trunc <= a.D;
+        if (!ok)
+            s.ct = -1;
+        s.s0 = ok ? c.start : 0;
+        s.stride = ok ? c.stride : 1;
+        s.nd = ok ? (c.d_trunc - c.start + c.stride - 1) / c.stride : 0;
+        // built-in work items: 256 queries
+        s.iq = c.tile_id == SV_ITEM128 ? 1 : c.tile_id == SV_ITEM256_DMA ? 3 : 2;
+        s.tiles = ok ? (int32_t)((a.n + (s.iq == 1 ? 127 : 255)) / (s.iq == 1 ? 128 : 256)) : 0;
+        if (ok) {
+            const auto key = std::make_tuple(s.s0, s.stride, s.nd);
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                const int t = (int)seen.size();
+                it = seen.emplace(key, t).first;
+                tabs[t] = TableDesc{s.s0, s.stride, s.nd, 0};
+            }
+            s.table = it->second;
+            direct |= s.iq == 3 && s.ct == C_FP8;
+        }
+        desc[i] = s;
+        cost[i] = (int64_t)s.nd * (s.ct == C_BF16 ? 2 : 1);
+        cnt[i].correct = 0;
+        cnt[i].n = ok ? (int32_t)a.n : 0;
+        cnt[i].ticks = 0;
+        order[i] = i;
+    }
+    std::stable_sort(order, order + a.ncfg, [&](int x, int y) { return cost[x] > cost[y]; });
+    int32_t run = 0;
+    for (int r = 0; r < a.ncfg; ++r) {
+        items[r] = run;
+        run += desc[order[r]].tiles;
+    }
+    items[a.ncfg] = run;
+    const int ntab = (int)seen.size();
+    // the queue counter (offset 0) goes up as 0 with the rest
+    hipError_t e = hipMemcpyAsync(a.ws, blob.data(), blob.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sweep_setup, dim3(1), dim3(1024), 0, st, a.ncfg, a.D, a.n, a.x_type, a.K, a.ws, L);
-    const int64_t per_slot = table_chunks(a.D) * KT * 64;
-    const unsigned gx = (unsigned)((per_slot + 255) / 256 < 1024 ? (per_slot + 255) / 256 : 1024);
-    hipLaunchKernelGGL(k_sweep_tables, dim3(gx, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L, KT, per_slot);
-    hipLaunchKernelGGL(k_sweep_popc, dim3(KT * 32, a.ncfg), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L,
-                       table_bytes);
+    if (ntab > 0) {
+        const int64_t per_slot = table_chunks(a.D) * KT * 64;
+        const unsigned gx = (unsigned)((per_slot + 255) / 256 < 1024 ? (per_slot + 255) / 256 : 1024);
+        hipLaunchKernelGGL(k_sweep_tables, dim3(gx, ntab), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L, KT,
+                           per_slot);
+        hipLaunchKernelGGL(k_sweep_popc, dim3(KT * 32, ntab), dim3(256), 0, st, a.C, a.K, a.ldc, a.ws, L,
+                           table_bytes);
+    }
+    if (direct) {
+        const int64_t total = (int64_t)a.D * (int64_t)L.ldp_conv;
+        const int64_t g = (total + 255) / 256;
+        hipLaunchKernelGGL(k_sweep_convert, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st, a.P, a.ldp, a.D,
+                           a.F, a.ws, L);
+    }
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;

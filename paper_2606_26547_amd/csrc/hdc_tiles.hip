@@ -79,7 +79,9 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
         v[n++] = SV_ITEM256;
         v[n++] = SV_ITEM128;
         const int wi = sweep_width_index(F);
-        if (x_type == X_INT8 && sweep_kt(K) == 1 && big_tile(kSweepWidths[wi] / 32, 1))
+        // the direct-staged bodies: up to 640 features, one class tile (int8
+        // configurations take them with int8 features only)
+        if (sweep_kt(K) == 1 && kSweepWidths[wi] <= 640)
             v[n++] = SV_ITEM256_DMA;
     } else {
         if (!encoder_bucket(kind, x_type, ct, F, K))

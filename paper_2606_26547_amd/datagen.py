@@ -183,6 +183,16 @@ def config_c1(seed: int = 1) -> Dataset:
                    dict(x_type="fp32", seed=seed, **c))
 
 
+def c1_queries(n: int, seed: int = 1, stream: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Further fp32 queries of the plain workload's mixture (the class means
+    of config_c1(seed), balanced labels), for batches beyond its test set."""
+    c = C1
+    mu = rng(seed, _S_MIX).standard_normal((c["K"], c["F"]))
+    y = balanced_labels(n, c["K"], rng(seed, _S_LABELS, 1 + stream))
+    X = (mu[y] + c["sigma"] * rng(seed, _S_EXTRA, stream).standard_normal((n, c["F"]))).astype(np.float32)
+    return X, y
+
+
 class SpeechLike:
     """The c2 mixture with its train-set quantisation scales; can draw any
     number of further quantised queries (c4 and the scaled bench batches)."""

@@ -99,7 +99,7 @@ _lib.hdc_classify_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_classify_prepared.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _i32, _i64, C.c_int, Dims, _i32,
                                        _p, _p, _p, _sz, _p, _sz, _i32]
 _lib.hdc_eval_configs_workspace_bytes.restype = _sz
-_lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32]
+_lib.hdc_eval_configs_workspace_bytes.argtypes = [_i32, _i32, _i32, _i32]
 _lib.hdc_eval_configs.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, _p, _p, _i32, _i64, _p, _i32, _i64,
                                   _p, _i32, _p, _p, _sz, _i32]
 _lib.hdc_device_clock_hz.restype = C.c_double
@@ -534,7 +534,7 @@ def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, 
     the stream has passed the call."""
     arr = config_array(cfgs, tile)
     K = Cw.shape[0]
-    need = int(_lib.hdc_eval_configs_workspace_bytes(len(arr), D, K))
+    need = int(_lib.hdc_eval_configs_workspace_bytes(len(arr), F, D, K))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=X.device)
     wait = out is None

@@ -336,7 +336,7 @@ class ResidentModel:
         d, k, s, t = self.tuned_cfg
         self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
         # workspace of configuration jobs (up to max_job_cfgs configurations)
-        need = int(hdc.lib().hdc_eval_configs_workspace_bytes(max_job_cfgs, self.D, self.K))
+        need = int(hdc.lib().hdc_eval_configs_workspace_bytes(max_job_cfgs, self.F, self.D, self.K))
         self.sweep_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
         self.resident_bytes = (self.P.numel() + self.C.numel() * 8 + self.plain.ws.numel()
                                + self.tuned.ws.numel() + self.sweep_ws.numel())

@@ -258,7 +258,7 @@ def test_tile_variants_without_device(lib):
     assert variants(CLS, INT8, BF16, 617, 26) == [3]
     assert variants(ENC, FP32, FP32, 64, 0) == [4, 3]
     assert variants(SWP, INT8, INT8, 617, 26) == [2, 1, 3]        # built-in: items of 256 queries
-    assert variants(SWP, UINT8, INT8, 617, 26) == [2, 1]          # direct staging needs int8 features
+    assert variants(SWP, UINT8, INT8, 617, 26) == [2, 1, 3]       # (int8 configurations then stage through registers)
     assert variants(SWP, INT8, INT8, 617, 100) == [2, 1]          # and one class tile
     assert variants(SWP, INT8, INT8, 784, 10) == [2, 1]           # and F <= 640
     assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
@@ -329,12 +329,12 @@ def test_eval_configs_host_arrays_without_device(lib):
     out = (ConfigResult * 3)()
     for r in out:
         r.correct, r.n, r.device_us = 7, 7, 7.0
-    call = lambda X, xt, n, F, c, o, w: lib.hdc_eval_configs(None, X, xt, n, F, 640, fake, fake, 10240, 640,  # noqa
+    call = lambda X, xt, n, F, c, o, w: lib.hdc_eval_configs(None, X, xt, n, F, 704, fake, fake, 10240, 704,  # noqa
                                                             fake, 26, 160, c, 3, o, ws, w, 0)
     bad = (Config * 3)(Config(1024, 1, 0, 0, 0), Config(2048, 2, 0, 2, 5), Config(10240, 1, 0, 3, 0))
     assert call(fake, 0, 2000, 617, bad, out, 1 << 30) == 2                   # tile id 5: no such variant
     dma = (Config * 3)(Config(1024, 1, 0, 0, 3), Config(2048, 2, 0, 2, 0), Config(10240, 1, 0, 3, 0))
-    assert call(fake, 1, 2000, 617, dma, out, 1 << 30) == 2                   # direct staging: int8 features
+    assert call(fake, 0, 2000, 700, dma, out, 1 << 30) == 2                   # direct staging: F <= 640
     assert call(fake, 0, 2000, 617, None, out, 1 << 30) == 1                  # no configurations
     assert call(fake, 0, 2000, 617, cfgs, None, 1 << 30) == 1                 # no results
     assert call(fake, 0, 2000, 617, cfgs, out, 64) == 3                       # workspace

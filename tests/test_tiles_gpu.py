@@ -58,12 +58,15 @@ def test_every_variant_matches_oracle(hdc, case):
             assert np.array_equal(H.cpu().numpy().view(np.uint64), href), v
 
 
-@pytest.mark.parametrize("K", [26, 100])
-def test_sweep_item_sizes_agree_with_oracle(hdc, K):
+@pytest.mark.parametrize("K,F,xt", [(26, 617, "int8"), (100, 617, "int8"), (26, 617, "uint8"), (10, 100, "int8")],
+                         ids=str)
+def test_sweep_item_sizes_agree_with_oracle(hdc, K, F, xt):
     """Work items of 128 and of 256 queries (int8 slots with two query tiles
-    per wave) give the oracle's correct counts for every slot."""
-    n, F, D = 1000, 617, 2048
-    X, P = dg.random_case(n, F, D, "int8", seed=K)
+    per wave) and the direct-staged bodies (int8 and E4M3 configurations,
+    the latter on converted projection rows) give the oracle's correct
+    counts for every slot."""
+    n, D = 1000, 2048
+    X, P = dg.random_case(n, F, D, xt, seed=K + F)
     g = np.random.default_rng(K + 1)
     Cw = g.integers(0, 2 ** 63, size=(K, D // 64), dtype=np.int64).view(np.uint64)
     truth = g.integers(0, K, size=n).astype(np.int32)
@@ -73,9 +76,9 @@ def test_sweep_item_sizes_agree_with_oracle(hdc, K):
     Xd, Pd = hdc.pad_cols(X), hdc.pad_cols(P)
     Cd = torch.as_tensor(Cw.view(np.int64)).cuda()
     td = torch.as_tensor(truth).cuda()
-    variants = hdc.tile_variants("sweep", "int8", "int8", F, K)
+    variants = hdc.tile_variants("sweep", xt, "int8", F, K)
     for v in variants:
-        print("[case] sweep K", K, "variant", v, flush=True)
+        print("[case] sweep K", K, "F", F, xt, "variant", v, flush=True)
         res = hdc.eval_configs(Xd, F, td, Pd, D, Cd, cfgs, tile=v)
         assert np.array_equal(res["correct"], ref), v
         assert (res["n"] == n).all() and (res["device_us"] > 0).all()

@@ -57,7 +57,11 @@ def parse():
                     "bundle, sweep (with the tuned selection and per-call latency), hamming, adc, cosine, "
                     "encode_side, retrain, ladder, serving, plain_fp32")
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile choices, no tuning launches")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of each open-loop serving run")
+    ap.add_argument("--serve-budgets", default="16G,64M,5M",
+                    help="HBM budgets of the open-loop serving runs (in-flight request bytes)")
+    ap.add_argument("--serve-saturation-seconds", type=float, default=3.0,
+                    help="length of the closed-loop saturation run (0: none)")
     ap.add_argument("--full-out", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
                     help="where the full result record is written (the last stdout line is a summary of it)")
     return ap.parse_args()
@@ -129,7 +133,10 @@ def compact(out: dict) -> dict:
                             for wl, r in out["ladder"].items()}
     if "serving" in out:
         sv = out["serving"]
-        extras["serving"] = {m: _pick(sv[m], "p50_ms", "p99_ms", "queries_per_s")
+        extras["serving"] = {m: dict(_pick(sv[m], "p50_ms", "p99_ms", "queries_per_s"),
+                                     saturation_qps=sv[m].get("runs", {}).get("saturation", {}).get("queries_per_s"),
+                                     p99_by_budget={b: r.get("p99_ms") for b, r in sv[m].get("runs", {}).items()
+                                                    if b != "saturation"})
                              for m in ("plain", "tuned") if m in sv}
     for key in ("cosine", "adc", "retrain"):
         if key in out and "roofline" in out[key]:
@@ -782,12 +789,21 @@ def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F,
     return res
 
 
+def _bytes(text: str) -> int:
+    mult = {"K": 1 << 10, "M": 1 << 20, "G": 1 << 30}
+    return int(float(text[:-1]) * mult[text[-1]]) if text[-1] in mult else int(text)
+
+
 def serving(args, dev, dg, hdc, tuner, torch):
-    """Open-loop Poisson stream over the 8 resident serving models: 95%
-    inference requests of 1..4096 queries (log-uniform), 5% configuration
-    jobs (16 configurations x 512 labelled queries); HBM budget 16 GiB.
-    Reported per mode (plain / tuned): p50 / p99 latency from arrival to
-    labels on the host, and completed queries per second."""
+    """The serving loop over the 8 resident serving models, plain and tuned.
+    Open loop: a Poisson stream of 2000 requests/s, 95% inference requests of
+    1..4096 queries (log-uniform), 5% configuration jobs (16 configurations
+    x 512 labelled queries), at each HBM budget for in-flight requests (16 GiB:
+    admission never waits; small budgets make it wait); p50 / p99 latency from
+    arrival to labels on the host, completed queries per second, peak admitted
+    bytes and how many requests waited for budget.  Closed loop: 64
+    inference requests kept outstanding, the sustained queries per second
+    (the capacity, which the open-loop rate does not reach)."""
     from paper_2606_26547_amd import serve
 
     srcs = dg.serving_models(5)
@@ -807,33 +823,49 @@ def serving(args, dev, dg, hdc, tuner, torch):
         D = models[mi].D
         return [(d, k, 0, t) for d in (D, D // 2, D // 4, D // 8) for k in (1, 2) for t in ("int8", "fp8")]
 
+    budgets = [b for b in args.serve_budgets.split(",") if b]
     report = {"models": tuned_cfgs, "rate_req_s": 2000.0, "seconds": args.serve_seconds,
-              "budget_bytes": 16 << 30}
+              "resident_bytes": sum(m.resident_bytes for m in models), "budgets": budgets}
     for mode in ("plain", "tuned"):
         ex = serve.GpuExecutor(models)
         tiles = ex.warm(job_cfgs, tune_tiles=(mode == "plain"))
         if tiles:
             report["tiles"] = {"%s F=%d K=%d D=%d" % (c.shape.kind, c.shape.F, c.shape.K, c.shape.D): c.chosen_name
                                for c in tiles}
-        srv = serve.Server(ex, budget=16 << 30)
-        # a short untimed stream first (staging slots, allocator caches)
-        for _, f in serve.open_loop(srv, srcs, 2000.0, 0.3, seed=99, tuned=(mode == "tuned"), job_cfgs=job_cfgs):
-            f.result(timeout=300)
-        srv.completed.clear()
-        t0 = time.perf_counter()
-        futs = serve.open_loop(srv, srcs, 2000.0, args.serve_seconds, seed=7, tuned=(mode == "tuned"),
-                               job_cfgs=job_cfgs)
-        for _, f in futs:
-            f.result(timeout=300)
-        wall = time.perf_counter() - t0
-        srv.close()
-        rep = srv.latency_report("infer")
-        rep["configs_jobs"] = srv.latency_report("configs")
-        rep["queries_per_s"] = rep.get("queries", 0) / wall
-        rep["peak_admitted_bytes"] = srv.sched.peak_used
-        report[mode] = rep
-        log("serving %s: p50 %.3f ms p99 %.3f ms, %d requests" % (mode, rep.get("p50_ms", -1), rep.get("p99_ms", -1),
-                                                                rep.get("requests", 0)))
+        runs = {}
+        for bname in budgets:
+            srv = serve.Server(ex, budget=_bytes(bname))
+            # a short untimed stream first (staging slots, allocator caches)
+            for _, f in serve.open_loop(srv, srcs, 2000.0, 0.3, seed=99, tuned=(mode == "tuned"),
+                                        job_cfgs=job_cfgs):
+                f.result(timeout=300)
+            srv.completed.clear()
+            srv.sched.blocked = 0
+            t0 = time.perf_counter()
+            futs = serve.open_loop(srv, srcs, 2000.0, args.serve_seconds, seed=7, tuned=(mode == "tuned"),
+                                   job_cfgs=job_cfgs)
+            for _, f in futs:
+                f.result(timeout=300)
+            wall = time.perf_counter() - t0
+            srv.close()
+            rep = srv.latency_report("infer")
+            rep["configs_jobs"] = srv.latency_report("configs")
+            rep["queries_per_s"] = rep.get("queries", 0) / wall
+            rep["peak_admitted_bytes"] = srv.sched.peak_used
+            rep["waited_for_budget"] = srv.sched.blocked
+            runs[bname] = rep
+            log("serving %s %s: p50 %.3f ms p99 %.3f ms, %d requests, %.0f q/s, %d waited for budget" %
+                (mode, bname, rep.get("p50_ms", -1), rep.get("p99_ms", -1), rep.get("requests", 0),
+                 rep["queries_per_s"], rep["waited_for_budget"]))
+        if args.serve_saturation_seconds > 0:
+            srv = serve.Server(ex, budget=16 << 30)
+            q, wall = serve.closed_loop(srv, srcs, 64, args.serve_saturation_seconds, seed=21,
+                                        tuned=(mode == "tuned"))
+            srv.close()
+            runs["saturation"] = {"concurrency": 64, "queries_per_s": q / wall, "seconds": wall}
+            log("serving %s saturation: %.0f q/s" % (mode, q / wall))
+        # the first budget's run is the headline of this mode
+        report[mode] = dict(runs[budgets[0]], runs=runs) if budgets else {"runs": runs}
     return report
 
 

@@ -89,6 +89,7 @@ class Scheduler:
         self.admitted = collections.defaultdict(collections.deque)   # lane -> requests
         self.inflight = collections.defaultdict(int)                  # lane -> batches in flight
         self.peak_used = 0
+        self.blocked = 0                            # requests that waited for budget at the queue head
 
     def lane(self, r: Request):
         return ("configs", r.rid) if r.kind == "configs" else (r.model, bool(r.tuned))
@@ -105,6 +106,9 @@ class Scheduler:
             r = self.waiting[0]
             need = self.bytes_of(r)
             if self.used + need > self.budget:
+                if not getattr(r, "blocked", False):
+                    r.blocked = True
+                    self.blocked += 1
                 break
             self.waiting.popleft()
             self.used += need
@@ -498,6 +502,39 @@ def open_loop(server: Server, sources, rate: float, duration: float, seed: int, 
         r.t_arrival = t0 + ta
         out.append((r, server.submit(r)))
     return out
+
+
+def closed_loop(server: Server, sources, concurrency: int, duration: float, seed: int, tuned: bool,
+                max_n: int = 4096):
+    """Drive ``server`` at saturation: ``concurrency`` inference requests
+    (log-uniform sizes, random models) are kept outstanding for ``duration``
+    seconds, a new one submitted as each completes.  Returns (completed
+    queries, wall seconds)."""
+    import concurrent.futures as cf
+
+    from .datagen import rng
+    g = rng(seed, 14)
+    pool = {m: src.queries(max_n, 200 + m)[0] for m, src in enumerate(sources)}
+
+    def new_request():
+        m = int(g.integers(0, len(sources)))
+        n = int(np.floor(np.exp(g.uniform(0, np.log(max_n + 1)))).clip(1, max_n))
+        off = int(g.integers(0, max_n - n + 1))
+        return server.submit(Request(model=m, X=pool[m][off:off + n], tuned=tuned)), n
+
+    out = dict(new_request() for _ in range(concurrency))
+    done_q, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < duration:
+        finished, _ = cf.wait(list(out), timeout=1.0, return_when=cf.FIRST_COMPLETED)
+        for f in finished:
+            f.result()
+            done_q += out.pop(f)
+            fut, n = new_request()
+            out[fut] = n
+    wall = time.perf_counter() - t0
+    for f in list(out):
+        f.result(timeout=300)
+    return done_q, wall
 
 
 def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:

@@ -8,7 +8,8 @@ from types import SimpleNamespace
 import numpy as np
 import pytest
 
-from paper_2606_26547_amd.serve import AdmissionError, Request, Scheduler, Server, poisson_arrivals, request_sizes
+from paper_2606_26547_amd.serve import (AdmissionError, Request, Scheduler, Server, closed_loop, poisson_arrivals,
+                                        request_sizes)
 
 
 class FakeExecutor:
@@ -69,6 +70,25 @@ def test_scheduler_admission_respects_budget_and_fifo():
     assert [r for r in b2[0].requests] == rs[3:]
     with pytest.raises(AdmissionError):
         s.submit(req(0, 200))                           # 2000 bytes > budget
+    assert s.blocked == 1                               # rs[3] waited at the head of the queue once
+
+
+def test_closed_loop_keeps_requests_outstanding():
+    """Saturation driver: a fixed number of requests stays in flight, each
+    completion submits the next; every completed query is counted."""
+
+    class Src:
+        def queries(self, n, stream):
+            return np.random.default_rng(stream).integers(-127, 128, size=(n, 16)).astype(np.int8), None
+
+    ex = FakeExecutor(latency=lambda b: 0.003)
+    srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n)
+    q, wall = closed_loop(srv, [Src(), Src(), Src()], concurrency=8, duration=0.3, seed=1, tuned=False, max_n=64)
+    srv.close()
+    assert wall >= 0.3 and q > 0
+    done = sum(c[3] for c in srv.completed)
+    assert done >= q                                    # the drained tail completes too
+    assert ex.max_concurrent <= 3 * 2                   # three model lanes, depth 2
 
 
 def test_scheduler_batches_per_lane_with_depth_and_max_batch():

@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 MFMA_INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
+SWEEP_SHARED = 4               # hdc tile id of the shared sweep path
 # 32-bit VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the fp32
 # vector peak of 157.3 TFLOP/s counts an FMA as two flops and packs two lanes)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -121,7 +122,8 @@ def compact(out: dict) -> dict:
     for key in ("sweep", "bundle", "plain_fp32"):
         if key in out:
             sec = out[key]
-            extras[key] = dict(_pick(sec, "ms", "slots", "queries_per_s", "accuracy", "test_accuracy", "GB_s"),
+            extras[key] = dict(_pick(sec, "ms", "slots", "queries_per_s", "accuracy", "test_accuracy", "GB_s",
+                                     "per_config_ms", "shared_ms"),
                                **({"frac": sec["roofline"]["frac"], "bound": sec["roofline"]["bound"]}
                                   if "roofline" in sec else {}))
     if "hamming_unfused" in out:
@@ -311,22 +313,43 @@ def main():
         sweep_out = torch.empty(16 * len(slots), dtype=torch.uint8, pin_memory=True)
         ws_sw = torch.empty(hdc.lib().hdc_eval_configs_workspace_bytes(len(slots), F, D, K), dtype=torch.uint8,
                             device=dev)
-        _, sweep_ms, _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, slots, ws=ws_sw,
-                                                             tile=sweep_tile, out=sweep_out), 5, 1)
+        # the configuration table is built once and reused by each launch
+        arrs = {t: hdc.config_array(slots, t) for t in (0, SWEEP_SHARED, sweep_tile)}
+        sweep_ms_by = {}
+        for t in (0, SWEEP_SHARED):
+            _, sweep_ms_by[t], _ = event_loop(lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, arrs[t], ws=ws_sw,
+                                                                       out=sweep_out), 5, 1)
+        sweep_ms = sweep_ms_by.get(sweep_tile) or event_loop(
+            lambda: hdc.eval_configs(Xsd, F, ysd, Pd, D, Cw, arrs[sweep_tile], ws=ws_sw, out=sweep_out), 5, 1)[1]
         # algorithmic encode work of the 256 slots: 2 F |S| per query
         sweep_ops = sum(2.0 * F * hdc.dims_count(s_, d_, k_) * Xsd.shape[0] for (d_, k_, s_, _) in slots)
+        # what the shared path encodes: the union of the slots' sets once for
+        # the int8 / bf16 slots and once for the E4M3 slots
+        shared_ops = sum(2.0 * F * D * Xsd.shape[0] for dt in ("int8", "fp8")
+                         if any(s_[3] in ((dt, "bf16") if dt == "int8" else (dt,)) for s_ in slots))
         grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid, tile=sweep_tile)
         best, plain_r = tuner.select_tuned(
             grid_res, (D, 1, 0, "int8"), 1.0,
             timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw, tile=cls_tile_id))
+        pc_ms, sh_ms = sweep_ms_by[0], sweep_ms_by[SWEEP_SHARED]
         out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
-                        "ms": sweep_ms, "wall_ms": sweep_wall_ms, "one_launch": True,
-                        "roofline": {"bound": "mfma", "achieved": sweep_ops / (sweep_ms / 1e3) / 1e12,
+                        "tile": hdc.TILE_NAMES["sweep"].get(sweep_tile, "built-in"),
+                        "ms": sweep_ms, "wall_ms": sweep_wall_ms, "one_call": True,
+                        "per_config_ms": pc_ms, "shared_ms": sh_ms, "shared_speedup": pc_ms / sh_ms,
+                        "roofline": {"bound": "mfma", "achieved": sweep_ops / (pc_ms / 1e3) / 1e12,
                                      "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s",
-                                     "frac": sweep_ops / (sweep_ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS,
+                                     "frac": sweep_ops / (pc_ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS,
                                      "ops_per_launch": sweep_ops,
-                                     "note": "sum over slots of 2 F |S| x queries (int8 peak for every "
-                                             "slot dtype; bf16 slots run at half that rate)"}}
+                                     "note": "per-configuration path: sum over slots of 2 F |S| x queries "
+                                             "(int8 peak for every slot dtype; bf16 slots run at half that "
+                                             "rate)"},
+                        "shared_roofline": {"bound": "mfma", "achieved": shared_ops / (sh_ms / 1e3) / 1e12,
+                                            "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s",
+                                            "frac": shared_ops / (sh_ms / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS,
+                                            "ops_per_launch": shared_ops,
+                                            "note": "shared path: the two encodings of the union (2 F D x "
+                                                    "queries each) over the whole call; the masked Hamming "
+                                                    "search is VALU work and not counted"}}
         d, k, s, tdt = best.cfg
         tuned = hdc.Prepared(Cw, D, tdt, s, d, k, tile=cls_tile_id if tdt == "int8" else 0)
         tl = torch.empty(N, dtype=torch.int32, device=dev)

@@ -103,9 +103,10 @@ def tune(sh: Shape, reps: int = 5, margin: float = 0.03, seed: int = 1) -> Choic
                          dtype=torch.uint8, device="cuda")
         out = torch.empty(16 * len(sh.cfgs), dtype=torch.uint8, pin_memory=True)
         cfgs = [tuple(c[:4]) for c in sh.cfgs]
+        arrs = {v: hdc.config_array(cfgs, v) for v in variants}      # built once, outside the timing
 
         def run(v):
-            hdc.eval_configs(X, sh.F, truth, P, sh.D, C, cfgs, ws=ws, tile=v, out=out)
+            hdc.eval_configs(X, sh.F, truth, P, sh.D, C, arrs[v], ws=ws, out=out)
         result = lambda: torch.as_tensor(hdc.result_view(out, len(cfgs))["correct"].copy())  # noqa: E731
     ch = Choice(shape=sh)
     ref = None

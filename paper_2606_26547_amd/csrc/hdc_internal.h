@@ -109,8 +109,10 @@ enum TileVariant : int { TV_AUTO = 0, TV_DMA_2X2 = 1, TV_DMA_1X1 = 2, TV_REG_QT1
 // Tile variants of the configuration sweep (per configuration): work items of
 // 128 queries (one query tile per wave) or of 256 (int8 slots with two query
 // tiles per wave where the registers allow, other slots in two passes), or of
-// 256 with int8-feature int8 slots on the direct-staged 2x2 body.
-enum SweepVariant : int { SV_AUTO = 0, SV_ITEM128 = 1, SV_ITEM256 = 2, SV_ITEM256_DMA = 3 };
+// 256 with int8-feature int8 slots on the direct-staged 2x2 body; or shared:
+// the configurations of one compute type take their Hamming distances from
+// one encoding of the union of their dimension sets.
+enum SweepVariant : int { SV_AUTO = 0, SV_ITEM128 = 1, SV_ITEM256 = 2, SV_ITEM256_DMA = 3, SV_SHARED = 4 };
 enum KernelKind : int { KK_ENCODE = 0, KK_CLASSIFY = 1, KK_SWEEP = 2 };
 
 // Shape rules shared by the kernel templates and the variant listing.

@@ -16,10 +16,25 @@
 //   [..]           class operand regions of fixed size, one per distinct
 //                  dimension set (chunks(D) * KT KiB table + 128 int32
 //                  popcounts)
+//   [..]           shared search items, up to ncfg x ShItem
+//   [..]           shared end counters (correct, device ticks), zeroed
 //   [..]           projection rows converted to E4M3 (direct-staged body)
+//   [..]           packed encodings of the shared path: one region per
+//                  encoding (int8, E4M3), kShQueries rows of ceil(D / 64)
+//                  words
 // Work item i belongs to the slot whose item range holds it (a binary search
 // over the item offsets); a workgroup takes items from the queue until it is
 // exhausted, so every workgroup reaches the exit whatever the grid size.
+//
+// Shared configurations (tile SV_SHARED) skip the persistent kernel.  The
+// encoding of one dimension depends on that dimension's projection row and
+// the queries only, and so does its class bit; the configurations of one
+// compute type therefore take their distances from one encoding of the
+// union of their dimension sets (64-aligned from below), by masked Hamming
+// distance (bf16 configurations from the int8 encoding, which equals theirs
+// for integer features).  Configurations with the same start and stride form a chain
+// whose sets are prefixes of each other: one pass over the chain's words
+// gives every end's distances on the way.
 #include <string.h>
 
 #include <algorithm>
@@ -50,6 +65,28 @@ struct SlotCount {
     uint64_t ticks;
 };
 
+// Shared path: ends per search item, words per LDS chunk, queries per pass.
+constexpr int kShEnds = 16;
+constexpr int kShWords = 16;
+constexpr int kShQueries = 4096;
+
+// A search item: one chain (compute type region, start, stride) and up to
+// kShEnds of its set ends, ascending; it reads absolute words [a0, a1).
+struct ShItem {
+    int32_t reg;                  // encoding region
+    int32_t s0, stride;
+    int32_t wlo;                  // absolute word of the region's column 0
+    int32_t a0, a1;
+    int32_t nend, pad;
+    int32_t end[kShEnds];         // one past the last dimension of each set
+    int32_t slot[kShEnds];        // its end counter
+};
+
+struct EndCount {
+    int32_t correct, pad;
+    uint64_t ticks;
+};
+
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Class tiles compiled into the sweep kernel: 1 (K <= 32) or 4 (K <= 128).
@@ -62,8 +99,8 @@ inline size_t sweep_table_bytes(int D, int K) { return (size_t)table_chunks(D) *
 inline size_t conv_pitch(int F) { return (size_t)(F + 63) / 64 * 64; }
 
 struct SweepLayout {
-    size_t off_desc, off_order, off_items, off_count, off_tabs, off_res, off_regions, region;
-    size_t off_p8, ldp_conv, total;
+    size_t off_desc, off_order, off_items, off_count, off_tabs, off_sh, off_end, off_res, off_regions, region;
+    size_t off_p8, ldp_conv, off_h, hreg, wd, total;
     SweepLayout(int ncfg, int F, int D, int K)
     {
         off_desc = 256;
@@ -71,12 +108,17 @@ struct SweepLayout {
         off_items = align256(off_order + (size_t)ncfg * 4);
         off_count = align256(off_items + (size_t)(ncfg + 1) * 4);
         off_tabs = align256(off_count + (size_t)ncfg * sizeof(SlotCount));
-        off_res = align256(off_tabs + (size_t)ncfg * sizeof(TableDesc));
+        off_sh = align256(off_tabs + (size_t)ncfg * sizeof(TableDesc));
+        off_end = align256(off_sh + (size_t)ncfg * sizeof(ShItem));
+        off_res = align256(off_end + (size_t)ncfg * sizeof(EndCount));
         off_regions = align256(off_res + (size_t)ncfg * sizeof(hdc_config_result));
         region = align256(sweep_table_bytes(D, K) + 128 * 4);
         ldp_conv = conv_pitch(F);
         off_p8 = align256(off_regions + region * (size_t)ncfg);
-        total = align256(off_p8 + (size_t)D * ldp_conv);
+        wd = (size_t)(D + 63) / 64;
+        hreg = align256((size_t)kShQueries * wd * 8);
+        off_h = align256(off_p8 + (size_t)D * ldp_conv);
+        total = off_h + 2 * hreg;
     }
 };
 
@@ -107,10 +149,17 @@ __global__ __launch_bounds__(256) void k_sweep_results(int ncfg, const uint8_t *
     if (i >= ncfg)
         return;
     const SlotCount c = ((const SlotCount *)(ws + L.off_count))[i];
+    const SlotDesc d = ((const SlotDesc *)(ws + L.off_desc))[i];
     hdc_config_result r;
-    r.correct = c.correct;
     r.n = c.n;
-    r.device_us = (double)c.ticks * us_per_tick;
+    if (d.iq == SV_SHARED && d.ct >= 0) {
+        const EndCount e = ((const EndCount *)(ws + L.off_end))[d.table];
+        r.correct = e.correct;
+        r.device_us = (double)e.ticks * us_per_tick;
+    } else {
+        r.correct = c.correct;
+        r.device_us = (double)c.ticks * us_per_tick;
+    }
     ((hdc_config_result *)(ws + L.off_res))[i] = r;
 }
 
@@ -168,6 +217,146 @@ __global__ __launch_bounds__(256) void k_sweep_popc(const uint64_t *__restrict__
     }
     if (threadIdx.x == 0)
         popc[k] = part[0];
+}
+
+// Bits of absolute word a that belong to the set {s0 + i * stride} below
+// `end`: the first one at or after s0 on the stride's grid, then doubled
+// along the stride.
+__device__ __forceinline__ uint64_t chain_mask(int a, int s0, int stride, int end)
+{
+    const int base = 64 * a;
+    if (base + 64 <= s0 || base >= end)
+        return 0;
+    int j0 = s0 - base;
+    if (j0 < 0) {
+        const int r = (base - s0) % stride;
+        j0 = r ? stride - r : 0;
+    }
+    if (j0 >= 64)
+        return 0;
+    uint64_t m = 1ull << j0;
+    for (int sh = stride; sh < 64; sh <<= 1)
+        m |= m << sh;
+    const int rem = end - base;
+    return rem < 64 ? m & ((1ull << rem) - 1) : m;
+}
+
+// Shared search: workgroup (query block of 64, item).  Each of the NW
+// waves takes KCW classes of the same 64 queries (one query per lane).
+// Chunks of kShWords words of the queries' encodings and of the class words
+// go through registers (the next chunk's loads are in flight while the
+// current one is counted) into LDS, both cut to the chain's set by masks
+// computed one chunk ahead.  Per word, a lane adds popcount(h ^ c) to each
+// of its classes' distances.  At the last word of a set's end, the
+// distances up to that end (that word cut below the end) are ranked by the
+// key distance * 128 + class, whose minimum is the first smallest distance;
+// the waves meet in an LDS minimum.  The 64 labels of each end are then
+// compared with the truth and counted into the end's counter.
+template <int KCW, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_shared(const uint64_t *__restrict__ C, int K, int64_t ldc,
+                                                          const int32_t *__restrict__ truth, int nq,
+                                                          uint8_t *__restrict__ ws, SweepLayout L)
+{
+    constexpr int T = 64 * NW;
+    constexpr int CW = kShWords * NW * KCW / T;      // class words per thread and chunk
+    constexpr int HW = kShWords * 64 / T;            // encoding words per thread and chunk
+    static_assert(CW >= 1 && HW >= 1 && kShWords % HW == 0, "chunk split");
+    __shared__ uint64_t cm[kShWords][NW * KCW];
+    __shared__ uint64_t hs[64][kShWords + 1];
+    __shared__ uint64_t msk[2][kShWords];
+    __shared__ int best[kShEnds][64];
+    __shared__ int ends[kShEnds];
+    const ShItem &it = ((const ShItem *)(ws + L.off_sh))[blockIdx.y];
+    const uint64_t *H = (const uint64_t *)(ws + L.off_h + L.hreg * it.reg);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int qb = blockIdx.x * 64;
+    const int nend = it.nend, s0 = it.s0, stride = it.stride, wlo = it.wlo, a0 = it.a0, a1 = it.a1;
+    const int end_max = it.end[nend - 1];
+    const uint64_t t0 = wall_clock64();
+    for (int i = tid; i < kShEnds * 64; i += T)
+        best[i >> 6][i & 63] = 0x7fffffff;
+    if (tid < nend)
+        ends[tid] = it.end[tid];
+    // this thread's share of a chunk: words hw .. hw + HW - 1 of query row
+    // hq, and class words (word i % kShWords, class i / kShWords) for
+    // i = tid + T r
+    const int hq = tid / (kShWords / HW), hw = HW * (tid % (kShWords / HW));
+    const bool hrow = qb + hq < nq;
+    const uint64_t *hp = H + (int64_t)(qb + hq) * L.wd - wlo + hw;
+    uint64_t rh[HW], rc[CW];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int x = 0; x < HW; ++x)
+            rh[x] = hrow && c0 + hw + x < a1 ? hp[c0 + x] : 0;
+#pragma unroll
+        for (int r = 0; r < CW; ++r) {
+            const int i = tid + T * r, ww = i & (kShWords - 1), k = i / kShWords;
+            rc[r] = k < K && c0 + ww < a1 ? C[(int64_t)k * ldc + c0 + ww] : 0;
+        }
+    };
+    if (tid < kShWords)
+        msk[0][tid] = chain_mask(a0 + tid, s0, stride, end_max);
+    fetch(a0);
+    __syncthreads();
+    const int kb = wave * KCW;
+    int acc[KCW];
+#pragma unroll
+    for (int j = 0; j < KCW; ++j)
+        acc[j] = 0;
+    int e = 0;    // next end to emit
+    int b = 0;
+    for (int c0 = a0; c0 < a1; c0 += kShWords, b ^= 1) {
+        const int nw = a1 - c0 < kShWords ? a1 - c0 : kShWords;
+#pragma unroll
+        for (int x = 0; x < HW; ++x)
+            hs[hq][hw + x] = rh[x] & msk[b][hw + x];
+#pragma unroll
+        for (int r = 0; r < CW; ++r) {
+            const int i = tid + T * r, ww = i & (kShWords - 1), k = i / kShWords;
+            cm[ww][k] = rc[r] & msk[b][ww];
+        }
+        if (c0 + kShWords < a1) {
+            if (tid < kShWords)
+                msk[b ^ 1][tid] = chain_mask(c0 + kShWords + tid, s0, stride, end_max);
+            fetch(c0 + kShWords);
+        }
+        __syncthreads();
+        for (int w = 0; w < nw; ++w) {
+            const uint64_t h = hs[lane][w];
+            const int a = c0 + w;
+            // sets whose last dimension lies in this word
+            while (e < nend && (ends[e] - 1) / 64 == a) {
+                const int rem = ends[e] - 64 * a;
+                const uint64_t pm = rem >= 64 ? ~0ull : (1ull << rem) - 1;
+                int key = 0x7fffffff;
+#pragma unroll
+                for (int j = 0; j < KCW; ++j) {
+                    const int k = kb + j;
+                    const int d = acc[j] + (int)__popcll((h ^ cm[w][k]) & pm);
+                    if (k < K)
+                        key = min(key, d * 128 + k);
+                }
+                atomicMin(&best[e][lane], key);
+                ++e;
+            }
+#pragma unroll
+            for (int j = 0; j < KCW; ++j)
+                acc[j] += (int)__popcll(h ^ cm[w][kb + j]);
+        }
+        __syncthreads();    // the chunk's LDS reads are done
+    }
+    EndCount *cnt = (EndCount *)(ws + L.off_end);
+    const uint64_t dt = wall_clock64() - t0;
+    for (int x = wave; x < nend; x += NW) {
+        const int q = qb + lane;
+        const bool ok = q < nq && (best[x][lane] & 127) == truth[q];
+        const uint64_t m = __ballot(ok);
+        if (lane == 0) {
+            if (m)
+                atomicAdd(&cnt[it.slot[x]].correct, (int)__popcll(m));
+            atomicAdd((unsigned long long *)&cnt[it.slot[x]].ticks, (unsigned long long)dt);
+        }
+    }
 }
 
 // One encoder pass of QT query tiles per wave over the queries from qblock,
@@ -396,6 +585,11 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     TableDesc *tabs = (TableDesc *)(blob.data() + L.off_tabs);
     std::vector<int64_t> cost(a.ncfg);
     std::map<std::tuple<int, int, int>, int> seen;
+    // shared configurations: chains (compute type, start, stride) -> end ->
+    // end counter, and the dimension range [lo, hi) of each compute type
+    std::map<std::tuple<int, int, int>, std::map<int, int>> chains;
+    std::map<int, std::pair<int, int>> ranges;
+    int nslots = 0;
     bool direct = false;
     for (int i = 0; i < a.ncfg; ++i) {
         const hdc_config c = a.cfgs[i];
@@ -409,9 +603,29 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
         s.stride = ok ? c.stride : 1;
         s.nd = ok ? (c.d_trunc - c.start + c.stride - 1) / c.stride : 0;
         // built-in work items: 256 queries
-        s.iq = c.tile_id == SV_ITEM128 ? 1 : c.tile_id == SV_ITEM256_DMA ? 3 : 2;
-        s.tiles = ok ? (int32_t)((a.n + (s.iq == 1 ? 127 : 255)) / (s.iq == 1 ? 128 : 256)) : 0;
-        if (ok) {
+        s.iq = c.tile_id == SV_ITEM128 ? 1 : c.tile_id == SV_ITEM256_DMA ? 3 : c.tile_id == SV_SHARED ? SV_SHARED : 2;
+        s.tiles = ok && s.iq != SV_SHARED ? (int32_t)((a.n + (s.iq == 1 ? 127 : 255)) / (s.iq == 1 ? 128 : 256)) : 0;
+        if (ok && s.iq == SV_SHARED) {
+            // its end counter: one per distinct (encoding, start, stride,
+            // end).  Integer features (|x| <= 255) and +-1 rows are exact in
+            // bf16 and so are the sums (|y| < 2^24) in its fp32 accumulator:
+            // the bf16 encoding is the exact integer encoding, the int8 one.
+            const int rct = s.ct == C_BF16 ? C_I8 : s.ct;
+            const int end = s.s0 + (s.nd - 1) * s.stride + 1;
+            auto &ch = chains[std::make_tuple(rct, s.s0, s.stride)];
+            auto it = ch.find(end);
+            if (it == ch.end())
+                it = ch.emplace(end, nslots++).first;
+            s.table = it->second;
+            auto rg_it = ranges.find(rct);
+            if (rg_it == ranges.end())
+                rg_it = ranges.emplace(rct, std::make_pair(a.D, 0)).first;
+            auto &rg = rg_it->second;
+            if (rg.first > s.s0 / 64 * 64)
+                rg.first = s.s0 / 64 * 64;
+            if (rg.second < end)
+                rg.second = end;
+        } else if (ok) {
             const auto key = std::make_tuple(s.s0, s.stride, s.nd);
             auto it = seen.find(key);
             if (it == seen.end()) {
@@ -437,6 +651,38 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     }
     items[a.ncfg] = run;
     const int ntab = (int)seen.size();
+    // shared search items: each chain's ends in groups of kShEnds, longest
+    // word range first; one encoding region per compute type
+    std::map<int, int> reg_of;
+    std::vector<int> reg_ct;
+    for (const auto &r : ranges) {
+        reg_of[r.first] = (int)reg_ct.size();
+        reg_ct.push_back(r.first);
+    }
+    std::vector<ShItem> sh;
+    for (const auto &ch : chains) {
+        const int ct = std::get<0>(ch.first), s0 = std::get<1>(ch.first), stride = std::get<2>(ch.first);
+        std::vector<std::pair<int, int>> ends(ch.second.begin(), ch.second.end());
+        for (size_t g = 0; g < ends.size(); g += kShEnds) {
+            ShItem t;
+            memset(&t, 0, sizeof t);
+            t.reg = reg_of[ct];
+            t.s0 = s0;
+            t.stride = stride;
+            t.wlo = ranges[ct].first / 64;
+            t.nend = (int)(ends.size() - g < (size_t)kShEnds ? ends.size() - g : kShEnds);
+            for (int x = 0; x < t.nend; ++x) {
+                t.end[x] = ends[g + x].first;
+                t.slot[x] = ends[g + x].second;
+            }
+            t.a0 = s0 / 64;
+            t.a1 = (t.end[t.nend - 1] - 1) / 64 + 1;
+            sh.push_back(t);
+        }
+    }
+    std::stable_sort(sh.begin(), sh.end(), [](const ShItem &x, const ShItem &y) { return x.a1 - x.a0 > y.a1 - y.a0; });
+    if (!sh.empty())
+        memcpy(blob.data() + L.off_sh, sh.data(), sh.size() * sizeof(ShItem));
     // the queue counter (offset 0) goes up as 0 with the rest
     hipError_t e = hipMemcpyAsync(a.ws, blob.data(), blob.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
@@ -468,14 +714,49 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st)
     base.P = a.P;
     base.ldp = a.ldp;
     base.K = a.K;
-    if (a.F <= 128) e = launch_sweep_fb<128>(base, a, L, table_bytes, st);
-    else if (a.F <= 256) e = launch_sweep_fb<256>(base, a, L, table_bytes, st);
-    else if (a.F <= 512) e = launch_sweep_fb<512>(base, a, L, table_bytes, st);
-    else if (a.F <= 640) e = launch_sweep_fb<640>(base, a, L, table_bytes, st);
-    else if (a.F <= 832) e = launch_sweep_fb<832>(base, a, L, table_bytes, st);
-    else e = launch_sweep_fb<1024>(base, a, L, table_bytes, st);
-    if (e != hipSuccess)
-        return e;
+    if (run > 0) {
+        if (a.F <= 128) e = launch_sweep_fb<128>(base, a, L, table_bytes, st);
+        else if (a.F <= 256) e = launch_sweep_fb<256>(base, a, L, table_bytes, st);
+        else if (a.F <= 512) e = launch_sweep_fb<512>(base, a, L, table_bytes, st);
+        else if (a.F <= 640) e = launch_sweep_fb<640>(base, a, L, table_bytes, st);
+        else if (a.F <= 832) e = launch_sweep_fb<832>(base, a, L, table_bytes, st);
+        else e = launch_sweep_fb<1024>(base, a, L, table_bytes, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    // shared configurations, kShQueries queries per pass: encode the range
+    // of each compute type, then one search launch over every item
+    for (int64_t q0 = 0; !sh.empty() && q0 < a.n; q0 += kShQueries) {
+        const int nq = (int)(a.n - q0 < kShQueries ? a.n - q0 : kShQueries);
+        for (size_t r = 0; r < reg_ct.size(); ++r) {
+            EncodeArgs ea = base;
+            ea.X = (const int8_t *)a.X + q0 * a.ldx;
+            ea.n = nq;
+            ea.s0 = ranges[reg_ct[r]].first;
+            ea.stride = 1;
+            ea.nd = ranges[reg_ct[r]].second - ea.s0;
+            ea.H32 = (uint32_t *)(a.ws + L.off_h + L.hreg * r);
+            ea.ldh32 = 2 * (int64_t)L.wd;
+            ea.max_split = 1 << 30;
+            e = launch_encode(ea, reg_ct[r], M_ENCODE, Tile{0}, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        const dim3 grid((unsigned)((nq + 63) / 64), (unsigned)sh.size());
+        // eight waves per query block, K / 8 classes each (rounded up to 4, 8, 16)
+        if (a.K <= 32)
+            hipLaunchKernelGGL((k_sweep_shared<4, 8>), grid, dim3(512), 0, st, a.C, a.K, a.ldc, a.truth + q0, nq,
+                               a.ws, L);
+        else if (a.K <= 64)
+            hipLaunchKernelGGL((k_sweep_shared<8, 8>), grid, dim3(512), 0, st, a.C, a.K, a.ldc, a.truth + q0, nq,
+                               a.ws, L);
+        else
+            hipLaunchKernelGGL((k_sweep_shared<16, 8>), grid, dim3(512), 0, st, a.C, a.K, a.ldc, a.truth + q0, nq,
+                               a.ws, L);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     // results: ticks -> microseconds of the device wall clock, then down to
     // the caller's host array (from pinned memory the copy stays
     // asynchronous; into pageable memory the runtime completes it first)

@@ -83,6 +83,8 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
         // configurations take them with int8 features only)
         if (sweep_kt(K) == 1 && kSweepWidths[wi] <= 640)
             v[n++] = SV_ITEM256_DMA;
+        // one encoding per compute type, masked Hamming search per chain
+        v[n++] = SV_SHARED;
     } else {
         if (!encoder_bucket(kind, x_type, ct, F, K))
             return -1;

@@ -315,7 +315,7 @@ def level_id_encode(lev: torch.Tensor, ID: torch.Tensor, LV: torch.Tensor, D: in
 KERNEL = {"encode": 0, "classify": 1, "sweep": 2}
 TILE_NAMES = {"encode": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
               "classify": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
-              "sweep": {1: "items_128", 2: "items_256", 3: "items_256_dma"}}
+              "sweep": {1: "items_128", 2: "items_256", 3: "items_256_dma", 4: "shared"}}
 
 
 def tile_variants(kind: str, x_type: str, compute: str, F: int, K: int) -> list[int]:
@@ -508,14 +508,18 @@ def convert_features(X: torch.Tensor, F: int, compute: str) -> torch.Tensor:
     return out
 
 
-def config_array(cfgs, tile: int = 0):
-    """Host hdc_config array from (d_trunc, stride, start, dtype[, tile_id])
-    tuples (dtype a name or an hdc_dtype value; tile_id defaults to `tile`)."""
-    arr = (Config * len(cfgs))()
-    for i, c in enumerate(cfgs):
-        d, k, s, t = c[:4]
-        arr[i] = Config(d, k, s, DTYPE[t] if isinstance(t, str) else int(t), int(c[4]) if len(c) > 4 else tile)
-    return arr
+def config_array(cfgs, tile: int = 0) -> np.ndarray:
+    """Host hdc_config array ([n][5] int32: d_trunc, stride, start, dtype,
+    tile_id) from (d_trunc, stride, start, dtype[, tile_id]) tuples (dtype a
+    name or an hdc_dtype value; tile_id defaults to `tile`).  An array
+    already in that form is returned as it is, so a caller that evaluates
+    the same configurations repeatedly builds it once."""
+    if isinstance(cfgs, np.ndarray):
+        assert cfgs.dtype == np.int32 and cfgs.ndim == 2 and cfgs.shape[1] == 5 and cfgs.flags.c_contiguous
+        return cfgs
+    rows = [(c[0], c[1], c[2], DTYPE[c[3]] if isinstance(c[3], str) else c[3], c[4] if len(c) > 4 else tile)
+            for c in cfgs]
+    return np.array(rows, dtype=np.int32).reshape(-1, 5)
 
 
 def result_view(out: torch.Tensor, ncfg: int) -> np.ndarray:
@@ -526,8 +530,8 @@ def result_view(out: torch.Tensor, ncfg: int) -> np.ndarray:
 def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
                  cfgs, ws: torch.Tensor | None = None, max_workgroups: int = 0, tile: int = 0,
                  out: torch.Tensor | None = None):
-    """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype[, tile_id])],
-    one persistent launch.  Without `out` the call waits for the stream and
+    """hdc_eval_configs: cfgs = [(d_trunc, stride, start, dtype[, tile_id])]
+    or a config_array of them.  Without `out` the call waits for the stream and
     returns the result records (numpy: correct, n, device_us); with `out`, a
     page-locked host uint8 tensor of at least 16 * len(cfgs) bytes, nothing
     waits and the records are read later with result_view(out, ncfg) once
@@ -542,7 +546,7 @@ def eval_configs(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, 
         out = torch.empty(len(arr) * RESULT_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
     assert out.numel() >= len(arr) * RESULT_DTYPE.itemsize and out.device.type == "cpu"
     _check(_lib.hdc_eval_configs(_stream(), _ptr(X), _xtype(X), X.shape[0], F, X.shape[1], _ptr(truth),
-                                 _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], arr, len(arr),
+                                 _ptr(P), D, P.shape[1], _ptr(Cw), K, Cw.shape[1], arr.ctypes.data, len(arr),
                                  _ptr(out), _ptr(ws), ws.numel(), int(max_workgroups)), "hdc_eval_configs")
     if wait:
         torch.cuda.current_stream().synchronize()

@@ -257,10 +257,10 @@ def test_tile_variants_without_device(lib):
     assert variants(CLS, UINT8, INT8, 512, 10) == [4, 3]          # uint8 features: register staging
     assert variants(CLS, INT8, BF16, 617, 26) == [3]
     assert variants(ENC, FP32, FP32, 64, 0) == [4, 3]
-    assert variants(SWP, INT8, INT8, 617, 26) == [2, 1, 3]        # built-in: items of 256 queries
-    assert variants(SWP, UINT8, INT8, 617, 26) == [2, 1, 3]       # (int8 configurations then stage through registers)
-    assert variants(SWP, INT8, INT8, 617, 100) == [2, 1]          # and one class tile
-    assert variants(SWP, INT8, INT8, 784, 10) == [2, 1]           # and F <= 640
+    assert variants(SWP, INT8, INT8, 617, 26) == [2, 1, 3, 4]     # built-in: items of 256 queries; 4 shared
+    assert variants(SWP, UINT8, INT8, 617, 26) == [2, 1, 3, 4]    # (int8 configurations then stage through registers)
+    assert variants(SWP, INT8, INT8, 617, 100) == [2, 1, 4]       # and one class tile
+    assert variants(SWP, INT8, INT8, 784, 10) == [2, 1, 4]        # and F <= 640
     assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
     assert variants(CLS, INT8, INT8, 2000, 26) is None            # beyond the compiled widths
     assert variants(SWP, FP32, FP32, 64, 2) is None

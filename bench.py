@@ -876,10 +876,15 @@ def serving(args, dev, dg, hdc, tuner, torch):
             rep["queries_per_s"] = rep.get("queries", 0) / wall
             rep["peak_admitted_bytes"] = srv.sched.peak_used
             rep["waited_for_budget"] = srv.sched.blocked
+            rep["max_loop_ms"] = srv.max_loop_s * 1e3
+            rep["loop_passes_over_10ms"] = srv.loop_stalls
+            rep["staging_slots"] = ex.nslots
             runs[bname] = rep
-            log("serving %s %s: p50 %.3f ms p99 %.3f ms, %d requests, %.0f q/s, %d waited for budget" %
+            log("serving %s %s: p50 %.3f ms p99 %.3f ms, %d requests, %.0f q/s, %d waited for budget, "
+                "longest loop pass %.1f ms (%d over 10 ms), %d staging slots" %
                 (mode, bname, rep.get("p50_ms", -1), rep.get("p99_ms", -1), rep.get("requests", 0),
-                 rep["queries_per_s"], rep["waited_for_budget"]))
+                 rep["queries_per_s"], rep["waited_for_budget"], rep["max_loop_ms"], rep["loop_passes_over_10ms"],
+                 ex.nslots))
         if args.serve_saturation_seconds > 0:
             srv = serve.Server(ex, budget=16 << 30)
             q, wall = serve.closed_loop(srv, srcs, 64, args.serve_saturation_seconds, seed=21,

@@ -416,7 +416,10 @@ hdc_status hdc_classify_prepared(void *stream,
  *     out[c].correct   = #{i : label_i == truth[i]}
  *     out[c].n         = n (0 for a configuration that does no work)
  *     out[c].device_us = device wall-clock time summed over c's work items
- * (several items run concurrently, so this is busy time, not elapsed time).
+ * (several items run concurrently, so this is busy time, not elapsed time;
+ * for a configuration on the shared path, the time of the search items
+ * that rank it, which it shares with the other configurations of its
+ * chain, without the shared encoding).
  * A configuration with an unsupported dtype or an empty / out-of-range
  * dimension set does no work and reports n = 0.  Work is scheduled longest
  * configuration first.
@@ -434,12 +437,14 @@ hdc_status hdc_classify_prepared(void *stream,
  *          is asynchronous; into pageable memory the call returns only
  *          after the results have arrived)
  *   ws     >= hdc_eval_configs_workspace_bytes(ncfg, F, D, K), 256-byte
- *          aligned (per-configuration class operands, and the projection
- *          rows converted to E4M3 for the direct-staged body)
+ *          aligned (per-configuration class operands, the projection rows
+ *          converted to E4M3 for the direct-staged body, and the shared
+ *          path's two encodings of 4096 queries at a time)
  *   max_workgroups  0: as many workgroups as fit on the device at once;
  *          otherwise at most this many (a configuration job that shares
  *          the device with latency-bound inference leaves it room; the
- *          work queue finishes every item whatever the count)
+ *          work queue finishes every item whatever the count).  It bounds
+ *          the persistent kernel only, not the shared path's launches
  * ------------------------------------------------------------------- */
 typedef struct {
     int32_t d_trunc, stride, start;
@@ -489,7 +494,16 @@ hdc_status hdc_eval_configs(void *stream,
  *             body with int8 features, E4M3 configurations on the same 2x2
  *             shape reading projection rows converted once per launch,
  *             bf16 configurations as HDC_TILE_SWEEP_256; K <= 32,
- *             F <= 640)
+ *             F <= 640) and HDC_TILE_SWEEP_SHARED (every bucket: the
+ *             configurations with this tile take their distances from one
+ *             encoding of the union of their dimension sets per encoding
+ *             -- int8, which bf16 configurations share since integer
+ *             features make the two identical, and E4M3 -- by masked
+ *             Hamming distance; a configuration's set depends only on its
+ *             own start, stride and end, and the set of configurations
+ *             with one start and stride is searched in one pass whose
+ *             prefix sums give every end; same counts, no per-configuration
+ *             encode)
  * hdc_tile_variants writes up to `cap` (host array) variant ids the bucket
  * is compiled with, the built-in choice first, and returns how many there
  * are, or -1 for a shape outside the compiled kernels.
@@ -507,7 +521,8 @@ enum {
     HDC_TILE_REG_QT2 = 4,
     HDC_TILE_SWEEP_128 = 1,
     HDC_TILE_SWEEP_256 = 2,
-    HDC_TILE_SWEEP_256_DMA = 3
+    HDC_TILE_SWEEP_256_DMA = 3,
+    HDC_TILE_SWEEP_SHARED = 4
 };
 
 int32_t hdc_tile_variants(hdc_kernel kind, hdc_dtype x_type, hdc_dtype compute, int32_t F, int32_t K,

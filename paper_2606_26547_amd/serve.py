@@ -58,7 +58,7 @@ class Request:
 
 @dataclasses.dataclass
 class Batch:
-    key: tuple                          # (model, tuned) or ("configs", rid)
+    key: tuple                          # (model, tuned) or ("configs",)
     requests: list
     offsets: list
     n: int
@@ -75,9 +75,11 @@ class Scheduler:
 
     ``bytes_of(request)`` gives the device bytes a request holds while it is
     in flight; ``budget`` is what is left of the HBM budget after the
-    resident models.  A lane is (model, tuned) for inference and a private
-    lane per configuration job; each lane has at most ``depth`` batches in
-    flight."""
+    resident models.  A lane is (model, tuned) for inference, and one lane
+    holds the configuration jobs (one job per batch: they run one after the
+    other on the executor's configuration stream anyway, so more in flight
+    would only hold staging slots); each lane has at most ``depth`` batches
+    in flight."""
 
     def __init__(self, budget: int, bytes_of, max_batch: int = 16384, depth: int = 2):
         self.budget = int(budget)
@@ -92,7 +94,7 @@ class Scheduler:
         self.blocked = 0                            # requests that waited for budget at the queue head
 
     def lane(self, r: Request):
-        return ("configs", r.rid) if r.kind == "configs" else (r.model, bool(r.tuned))
+        return ("configs",) if r.kind == "configs" else (r.model, bool(r.tuned))
 
     def submit(self, r: Request):
         need = self.bytes_of(r)
@@ -181,7 +183,8 @@ class GpuExecutor:
         self.free = collections.deque()
         self.nslots = 0
         if slots is None:
-            slots = depth * (len(models) + 2)
+            # every lane of one mode (plain or tuned) and the configuration lane
+            slots = depth * (len(models) + 1) + 2
         for _ in range(slots):
             self.free.append(self._new_slot())
 
@@ -368,6 +371,10 @@ class Server:
         self.poll_s = poll_s
         self.next_id = 0
         self.completed = []                 # (rid, kind, model, n, latency_s)
+        # longest pass of the scheduling loop, and passes over 10 ms (a
+        # stalled loop delays every request behind it)
+        self.max_loop_s = 0.0
+        self.loop_stalls = 0
         # Everything allocated so far (models, pools, staging) lives as long
         # as the server: move it out of the cyclic collector's view, so that
         # a full collection during serving does not stall the loop for tens
@@ -411,7 +418,15 @@ class Server:
         return r.future
 
     def _loop(self):
+        t_prev = time.perf_counter()
         while True:
+            t_now = time.perf_counter()
+            gap = t_now - t_prev
+            t_prev = t_now
+            if gap > self.max_loop_s:
+                self.max_loop_s = gap
+            if gap > 0.01:
+                self.loop_stalls += 1
             with self.lock:
                 batches = self.sched.next_batches()
                 stopping = self.stop_flag and self.sched.idle() and not self.running

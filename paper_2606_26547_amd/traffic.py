@@ -13,6 +13,11 @@ still hash to it, the batch is the same and the tile variant matches.
         --copy-bytes N --batch B --tile T --sources FILE...
 
 Each DIR is a rocprofv3 output directory holding *counter_collection.csv.
+The copy the counters are calibrated on is this module's own:
+
+    python -m paper_2606_26547_amd.traffic --copy-run BYTES
+
+copies BYTES (a multiple of 4) from one device buffer to another six times.
 """
 from __future__ import annotations
 
@@ -49,7 +54,22 @@ def sources_hash(sources: list[str]) -> str:
     return hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in sources)).hexdigest()
 
 
+def copy_run(nbytes: int, reps: int = 6):
+    """The calibration copy: device to device, `reps` times."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "--copy-run":
+        copy_run(int(argv[1]))
+        return
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--key", required=True)
     ap.add_argument("--kernel", required=True, help="regex of the kernel name")

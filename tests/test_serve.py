@@ -152,6 +152,18 @@ def test_config_jobs_run_alone_and_failures_are_isolated():
     assert all(len(b.requests) == 1 for b in ex.launched if b.requests[0].kind == "configs")
 
 
+def test_config_jobs_share_one_lane_of_bounded_depth():
+    """Configuration jobs queue on one lane: at most `depth` of them hold a
+    staging slot at a time, however many arrive together, and all finish."""
+    ex = FakeExecutor(latency=lambda b: 0.01)
+    srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n, depth=2)
+    jobs = [srv.submit(req(m % 3, 20, seed=m, kind="configs", cfgs=[(1024, 1, 0, "int8")] * (m + 1),
+                           truth=np.zeros(20))) for m in range(12)]
+    assert [j.result(timeout=10)[0] for j in jobs] == list(range(1, 13))
+    srv.close()
+    assert ex.max_concurrent <= 2
+
+
 def test_malformed_requests_are_rejected_at_submit():
     ex = FakeExecutor()
     srv = Server(ex, budget=10 ** 9, bytes_of=lambda r: r.n)

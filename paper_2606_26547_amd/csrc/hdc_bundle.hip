@@ -17,7 +17,8 @@
 // depend on the order in which rows are visited):
 //   1. group the entries by (class, sign) into a row-index list: per-block
 //      histograms, one scan, a scatter (one fused single-workgroup kernel
-//      for small inputs);
+//      for small inputs; a small bundle does all three steps in one kernel,
+//      k_bundle_small);
 //   2. count: each workgroup takes a segment of up to R rows of one group
 //      and a column tile of the hypervectors; every lane owns V dwords of
 //      the row and counts the set bits of the rows it reads with bit-sliced
@@ -452,6 +453,85 @@ __global__ __launch_bounds__(256) void k_group_count(CountArgs a)
     }
 }
 
+// Small bundles (n <= kSmallRows rows): one kernel instead of grouping,
+// counting and binarising.  Workgroup (class k, column tile): the rows
+// labelled k are listed in LDS (in any order: the counts are integers), the
+// four waves count them as k_group_count does (sixteen rows per step, wave
+// w from row 16w on, 64 rows apart), merge their per-dimension counts in
+// LDS, and the tile's class words are written directly: bit d is set when
+// more than half of the class's rows have it (acc < 0 with acc = rows -
+// 2 * count); pad bits and an empty class give 0.
+template <int V>
+__global__ __launch_bounds__(256) void k_bundle_small(const uint32_t *__restrict__ H32, int64_t ldh32, int W32,
+                                                      int nbits, const int32_t *__restrict__ labels, int n,
+                                                      uint32_t *__restrict__ C32, int64_t ldc32,
+                                                      int32_t *__restrict__ counts)
+{
+    __shared__ int32_t list[kSmallRows];
+    __shared__ int lcnt[32 * V * 65];
+    __shared__ int nrows;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int k = blockIdx.x, tile = blockIdx.y;
+    if (t == 0)
+        nrows = 0;
+    for (int i = t; i < 32 * V * 65; i += 256)
+        lcnt[i] = 0;
+    __syncthreads();
+    for (int i = t; i < n; i += 256)
+        if (labels[i] == k)
+            list[atomicAdd(&nrows, 1)] = i;
+    __syncthreads();
+    const int rows = nrows;
+    const int c0 = tile * 64 * V + lane * V;
+    BitCounters<V> c;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        c.ones[v] = c.twos[v] = c.fours[v] = c.eights[v] = 0;
+#pragma unroll
+        for (int p = 0; p < kPlanes; ++p)
+            c.sp[p][v] = 0;
+    }
+    const bool colok = c0 < W32;
+    const int coff = colok ? c0 : 0;
+    const int64_t last = rows - 1;
+    for (int r = 16 * wave; r < rows; r += 64) {
+        int32_t cur[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            cur[u] = list[r + u <= last ? r + u : last];
+        uint32_t x[16][V];
+        load_rows<V>(H32, ldh32, cur, coff, x);
+        add_rows<V>(x, r, last, colok, c);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        for (int j = 0; j < 32; ++j) {
+            int cnt = (int)((c.ones[v] >> j) & 1u) + 2 * (int)((c.twos[v] >> j) & 1u) +
+                      4 * (int)((c.fours[v] >> j) & 1u) + 8 * (int)((c.eights[v] >> j) & 1u);
+            int hi16 = 0;
+#pragma unroll
+            for (int p = kPlanes - 1; p >= 0; --p)
+                hi16 = 2 * hi16 + (int)((c.sp[p][v] >> j) & 1u);
+            cnt += 16 * hi16;
+            if (cnt)
+                atomicAdd(&lcnt[(v * 32 + j) * 65 + lane], cnt);
+        }
+    __syncthreads();
+    // thread e < 64V writes dword tile * 64V + e (lane e / V, part e % V)
+    if (t < 64 * V) {
+        const int dw = tile * 64 * V + t, ln = t / V, v = t % V;
+        if (dw < W32) {
+            uint32_t bits = 0;
+            for (int j = 0; j < 32; ++j)
+                if (32 * dw + j < nbits && 2 * lcnt[(v * 32 + j) * 65 + ln] > rows)
+                    bits |= 1u << j;
+            C32[(int64_t)k * ldc32 + dw] = bits;
+        }
+    }
+    if (counts && tile == 0 && t == 0)
+        counts[k] = rows;
+}
+
 // Class words from the accumulators: bit d of class k = (acc[k][d] < 0).
 // One wave per word.
 __global__ __launch_bounds__(256) void k_binarize(const int32_t *__restrict__ acc, int K, int nbits, int W,
@@ -580,6 +660,17 @@ hipError_t launch_group_count(int mode, const uint64_t *H, int64_t n, int nbits,
     g.n_wrong = mode == GM_RETRAIN ? n_wrong : nullptr;
     g.zero = mode == GM_RETRAIN ? nullptr : acc;
     g.zero_count = mode == GM_RETRAIN ? 0 : (int64_t)K * nbits;
+    if (mode == GM_BUNDLE && n > 0 && n <= kSmallRows) {
+        const dim3 grid((unsigned)K, (unsigned)L.T);
+        const int W32 = 2 * ((nbits + 63) / 64);
+        if (L.V == 2)
+            hipLaunchKernelGGL(k_bundle_small<2>, grid, dim3(256), 0, st, (const uint32_t *)H, 2 * ldh, W32, nbits,
+                               labels, (int)n, (uint32_t *)C, 2 * ldc, counts);
+        else
+            hipLaunchKernelGGL(k_bundle_small<1>, grid, dim3(256), 0, st, (const uint32_t *)H, 2 * ldh, W32, nbits,
+                               labels, (int)n, (uint32_t *)C, 2 * ldc, counts);
+        return hipGetLastError();
+    }
     if (L.B == 1) {
         const int64_t zb = g.zero ? (g.zero_count + 1023) / 1024 : 0;
         hipLaunchKernelGGL(k_group_small, dim3((unsigned)(1 + (zb < 1024 ? zb : 1024))), dim3(1024), 0, st, g);

@@ -356,6 +356,29 @@ class ResidentModel:
 
 
 # ---------------------------------------------------------------- server
+# Automatic cyclic collection is off while any server runs (see Server).
+_gc_lock = threading.Lock()
+_gc_servers = 0
+_gc_was_enabled = True
+
+
+def _gc_hold():
+    global _gc_servers, _gc_was_enabled
+    with _gc_lock:
+        if _gc_servers == 0:
+            _gc_was_enabled = gc.isenabled()
+            gc.disable()
+        _gc_servers += 1
+
+
+def _gc_release():
+    global _gc_servers
+    with _gc_lock:
+        _gc_servers -= 1
+        if _gc_servers == 0 and _gc_was_enabled:
+            gc.enable()
+
+
 class Server:
     """Scheduler thread: admits, batches, launches and completes requests."""
 
@@ -375,12 +398,21 @@ class Server:
         # stalled loop delays every request behind it)
         self.max_loop_s = 0.0
         self.loop_stalls = 0
-        # Everything allocated so far (models, pools, staging) lives as long
-        # as the server: move it out of the cyclic collector's view, so that
-        # a full collection during serving does not stall the loop for tens
-        # of milliseconds.
+        self.closed = False
+        # The cyclic collector.  Everything allocated so far (models, pools,
+        # staging) lives as long as the server: it is moved out of the
+        # collector's view.  While the server runs, the interpreter's
+        # automatic collections are off: under a steady request stream they
+        # reach the oldest generation every few seconds, and a pass over
+        # every live request, future and result there stopped the loop for
+        # hundreds of milliseconds.  The loop collects the young generations
+        # itself instead (their size is bounded by the work of the last
+        # interval, so each pass is short); when the last running server is
+        # closed, the automatic collector is turned back on if it was on.
         gc.collect()
         gc.freeze()
+        _gc_hold()
+        self.gc_young_s, self.gc_mid_s = 0.05, 1.0
         self.thread = threading.Thread(target=self._loop, daemon=True)
         self.thread.start()
 
@@ -419,6 +451,7 @@ class Server:
 
     def _loop(self):
         t_prev = time.perf_counter()
+        t_young = t_mid = t_prev
         while True:
             t_now = time.perf_counter()
             gap = t_now - t_prev
@@ -427,6 +460,12 @@ class Server:
                 self.max_loop_s = gap
             if gap > 0.01:
                 self.loop_stalls += 1
+            if t_now - t_mid > self.gc_mid_s:
+                gc.collect(1)
+                t_mid = t_young = t_now
+            elif t_now - t_young > self.gc_young_s:
+                gc.collect(0)
+                t_young = t_now
             with self.lock:
                 batches = self.sched.next_batches()
                 stopping = self.stop_flag and self.sched.idle() and not self.running
@@ -474,6 +513,9 @@ class Server:
     def close(self, timeout: float = 60.0):
         self.stop_flag = True
         self.thread.join(timeout)
+        if not self.closed:
+            self.closed = True
+            _gc_release()
 
     def latency_report(self, kind="infer"):
         lat = np.array([c[4] for c in self.completed if c[1] == kind])

@@ -94,7 +94,8 @@ def test_encode_fp32_features_band(hdc, ct):
 # two); classes spanning several count segments (the large-n, small-K cases)
 BUNDLE_CASES = [(1, 64, 1, None), (1, 1, 1, None), (100, 100, 3, None), (6238, 2048, 26, None),
                 (5000, 1000, 128, None), (300, 10240, 10, None), (777, 130, 3, 5), (16385, 8192, 26, None),
-                (40000, 10240, 3, 161), (70001, 2048, 100, None), (0, 640, 4, None)]
+                (40000, 10240, 3, 161), (70001, 2048, 100, None), (0, 640, 4, None), (8192, 640, 7, None),
+                (8193, 640, 7, None)]
 
 
 @pytest.mark.parametrize("case", BUNDLE_CASES, ids=str)

@@ -212,3 +212,19 @@ def test_arrival_process_and_sizes():
     n = request_sizes(10000, seed=2)
     assert n.min() >= 1 and n.max() <= 4096
     assert 300 < n.mean() < 700                          # log-uniform on [1, 4096]: mean ~ 492
+
+
+def test_automatic_gc_is_off_while_serving_and_restored():
+    """Automatic cyclic collection stops while servers run (the loop collects
+    the young generations itself) and comes back after the last one closes."""
+    import gc
+    assert gc.isenabled()
+    a = Server(FakeExecutor(), budget=10 ** 9, bytes_of=lambda r: r.n)
+    b = Server(FakeExecutor(), budget=10 ** 9, bytes_of=lambda r: r.n)
+    assert not gc.isenabled()
+    assert a.submit(req(0, 4)).result(timeout=5).shape == (4,)
+    a.close()
+    assert not gc.isenabled()                       # b still runs
+    b.close()
+    b.close()                                       # a second close changes nothing
+    assert gc.isenabled()

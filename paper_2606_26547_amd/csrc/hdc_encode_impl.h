@@ -7,12 +7,15 @@
 
 namespace hdc {
 
-// Grid (query block, dimension split).  Split z of Z takes the whole
+// Grid: query blocks, or (dimension split, query block) when the launch
+// splits its dimensions (a.nsplit = Z > 1).  Split z of Z takes the whole
 // 64-dimension words [z * per, (z + 1) * per) of the dimension list: its
 // projection rows, its half-words of the packed output and its part of the
-// class operand.  In classify mode every split adds its own part of the
-// class sums, so a split launch writes them to part[z][n][K] and
-// k_split_argmin finishes.
+// class operand.  Workgroups are dealt to the XCDs in turn by linear id, so
+// with the split index fastest each XCD's L2 holds the projection rows of
+// its splits only, not all of them.  In classify mode every split adds its
+// own part of the class sums, so a split launch writes them to
+// part[z][n][K] and k_split_argmin finishes.
 template <int CT, int XF, int QT, int KS, int KT, int MODE, bool DMA, int RT>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT>::WAVES)))
@@ -20,8 +23,9 @@ void k_encode(EncodeArgs a)
 {
     typedef Encoder<CT, XF, QT, KS, KT, MODE, 0, DMA, RT> E;
     __shared__ __align__(16) uint8_t smem[E::LDS];
-    const int64_t qblock = (int64_t)blockIdx.x * E::QPB;
-    const int Z = gridDim.y, z = blockIdx.y;
+    const int Z = a.nsplit;
+    const int z = Z > 1 ? (int)blockIdx.x : 0;
+    const int64_t qblock = (int64_t)(Z > 1 ? blockIdx.y : blockIdx.x) * E::QPB;
     if (Z > 1) {
         const int per = split_units(a.nd, Z);
         const int d0 = 64 * z * per;                    // first dimension (list index) of the split
@@ -115,8 +119,10 @@ static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
     const int64_t blocks = (a.n + E::QPB - 1) / E::QPB;
     // resident workgroups: one per CU per wave per SIMD the kernel is built for
     const int Z = split_count(blocks, a.nd, a.max_split, 256 * E::WAVES);
-    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE, DMA, RT>), dim3((unsigned)blocks, (unsigned)Z), dim3(256),
-                       0, st, a);
+    EncodeArgs b = a;
+    b.nsplit = Z;
+    const dim3 grid = Z > 1 ? dim3((unsigned)Z, (unsigned)blocks) : dim3((unsigned)blocks);
+    hipLaunchKernelGGL((k_encode<CT, XF, QT, KS, KT, MODE, DMA, RT>), grid, dim3(256), 0, st, b);
     if (MODE == M_CLASSIFY && Z > 1)
         hipLaunchKernelGGL(k_split_argmin, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, st, a, Z);
     return hipGetLastError();

@@ -43,6 +43,7 @@ struct EncodeArgs {
     // part[split][K][n] (int32), then a small kernel takes the argmin.
     int32_t max_split;
     int32_t *part;
+    int32_t nsplit;        // set by the launch: the splits it uses (1 = none)
 };
 
 // Dimension splits of an encoder launch with `blocks` query blocks over nd

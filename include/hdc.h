@@ -137,8 +137,10 @@ hdc_status hdc_encode_tiled(void *stream,
  *   H       [n][ldh] uint64 hypervectors of nbits elements each, 8-byte
  *           aligned
  *   labels  [n] int32 in [0, K) (precondition; out-of-range rows are skipped)
- *   C       [K][ldc] uint64 output, ldc >= ceil(nbits/64)
- *   counts  [K] int32 output n_k, may be NULL
+ *   C       [K][ldc] uint64 output, ldc >= ceil(nbits/64): words 0 ..
+ *           ceil(nbits/64) - 1 of every class row are written (bits past
+ *           nbits 0), words past them are left as they are
+ *   counts  [K] int32 output n_k (every entry written), may be NULL
  *   ws      >= hdc_bundle_workspace_bytes(n, nbits, K) bytes, 256-byte
  *           aligned (the class sums, a row index list grouped by class and
  *           its offsets)

@@ -477,6 +477,7 @@ __global__ __launch_bounds__(256) void k_bundle_small(const uint32_t *__restrict
     for (int i = t; i < 32 * V * 65; i += 256)
         lcnt[i] = 0;
     __syncthreads();
+#pragma unroll 4
     for (int i = t; i < n; i += 256)
         if (labels[i] == k)
             list[atomicAdd(&nrows, 1)] = i;
@@ -494,14 +495,35 @@ __global__ __launch_bounds__(256) void k_bundle_small(const uint32_t *__restrict
     const bool colok = c0 < W32;
     const int coff = colok ? c0 : 0;
     const int64_t last = rows - 1;
-    for (int r = 16 * wave; r < rows; r += 64) {
+    // the next sixteen rows' loads are in flight while the current ones
+    // are counted
+    auto fetch = [&](int r, uint32_t (&x)[16][V]) {
         int32_t cur[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u)
             cur[u] = list[r + u <= last ? r + u : last];
-        uint32_t x[16][V];
         load_rows<V>(H32, ldh32, cur, coff, x);
-        add_rows<V>(x, r, last, colok, c);
+    };
+    int r = 16 * wave;
+    if (r < rows) {
+        uint32_t xa[16][V], xb[16][V];
+        fetch(r, xa);
+        while (true) {
+            const bool more = r + 64 < rows;
+            if (more)
+                fetch(r + 64, xb);
+            add_rows<V>(xa, r, last, colok, c);
+            r += 64;
+            if (!more)
+                break;
+            const bool more2 = r + 64 < rows;
+            if (more2)
+                fetch(r + 64, xa);
+            add_rows<V>(xb, r, last, colok, c);
+            r += 64;
+            if (!more2)
+                break;
+        }
     }
 #pragma unroll
     for (int v = 0; v < V; ++v)

@@ -197,8 +197,9 @@ def encode(X: torch.Tensor, F: int, P: torch.Tensor, D: int, compute="int8", sta
 def bundle(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, ws: torch.Tensor | None = None):
     """hdc_bundle: class hypervectors [K][words(nbits)] and class sizes."""
     W = words(nbits)
-    Cw = torch.zeros((K, W), dtype=torch.int64, device=H.device)
-    counts = torch.zeros(K, dtype=torch.int32, device=H.device)
+    # every word of every class, and every class size, is written by the call
+    Cw = torch.empty((K, W), dtype=torch.int64, device=H.device)
+    counts = torch.empty(K, dtype=torch.int32, device=H.device)
     need = int(_lib.hdc_bundle_workspace_bytes(H.shape[0], nbits, K))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=H.device)
@@ -213,9 +214,9 @@ def bundle_noalloc(H: torch.Tensor, nbits: int, labels: torch.Tensor, K: int, Cw
     scratch (no workspace); fills Cw [K][words(nbits)] and counts [K] (the
     tensors are allocated here when not given)."""
     if Cw is None:
-        Cw = torch.zeros((K, words(nbits)), dtype=torch.int64, device=H.device)
+        Cw = torch.empty((K, words(nbits)), dtype=torch.int64, device=H.device)
     if counts is None:
-        counts = torch.zeros(K, dtype=torch.int32, device=H.device)
+        counts = torch.empty(K, dtype=torch.int32, device=H.device)
     _check(_lib.hdc_bundle_noalloc(_stream(), _ptr(H), H.shape[0], nbits, H.shape[1], _ptr(labels), K, _ptr(Cw),
                                    Cw.shape[1], _ptr(counts)), "hdc_bundle_noalloc")
     return Cw, counts

@@ -163,8 +163,11 @@ C1 = dict(K=10, F=64, D=2048, n_train=1000, n_test=200, sigma=0.5)
 # D = 10240, 0.908 at D' = 4096, 0.894 at D' = 2048).
 C2 = dict(K=26, F=617, D=10240, n_train=6238, n_test=1559, comps=3, tau=0.55, sigma=3.0,
           overlap=0.55)
+# p_in / p_out fixed so that the plain model does not saturate (measured
+# with the oracle, model from the first 6000 training images: 0.937 at
+# D = 8192, and 0.46 at D' = 2048 with stride 4), keeping ~80% zero pixels.
 C3 = dict(K=10, F=784, D=8192, n_train=60000, n_test=10000, side=28, mask_frac=0.30,
-          p_in=0.6, p_out=0.02)
+          p_in=0.33, p_out=0.15)
 C4 = dict(n_queries=2000, n_slots=256,
           d_trunc=(1024, 2048, 4096, 8192, 10240), stride=(1, 2, 4, 8), dtype=("int8", "bf16", "fp8"))
 

@@ -171,9 +171,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); got --gpus %d, WORLD_SIZE %d" % (args.gpus, world),
-              file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(queries or sweep slots would shard across GPUs without communication); "
+              "got --gpus %d, WORLD_SIZE %d" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -63,6 +63,8 @@ def parse():
                     help="HBM budgets of the open-loop serving runs (in-flight request bytes)")
     ap.add_argument("--serve-saturation-seconds", type=float, default=3.0,
                     help="length of the closed-loop saturation run (0: none)")
+    ap.add_argument("--serve-poll-us", type=float, default=10.0,
+                    help="how long the serving loop sleeps when it has nothing to launch or complete")
     ap.add_argument("--full-out", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
                     help="where the full result record is written (the last stdout line is a summary of it)")
     return ap.parse_args()
@@ -857,7 +859,7 @@ def serving(args, dev, dg, hdc, tuner, torch):
                                for c in tiles}
         runs = {}
         for bname in budgets:
-            srv = serve.Server(ex, budget=_bytes(bname))
+            srv = serve.Server(ex, budget=_bytes(bname), poll_s=args.serve_poll_us * 1e-6)
             # a short untimed stream first (staging slots, allocator caches)
             for _, f in serve.open_loop(srv, srcs, 2000.0, 0.3, seed=99, tuned=(mode == "tuned"),
                                         job_cfgs=job_cfgs):
@@ -886,7 +888,7 @@ def serving(args, dev, dg, hdc, tuner, torch):
                  rep["queries_per_s"], rep["waited_for_budget"], rep["max_loop_ms"], rep["loop_passes_over_10ms"],
                  ex.nslots))
         if args.serve_saturation_seconds > 0:
-            srv = serve.Server(ex, budget=16 << 30)
+            srv = serve.Server(ex, budget=16 << 30, poll_s=args.serve_poll_us * 1e-6)
             q, wall = serve.closed_loop(srv, srcs, 64, args.serve_saturation_seconds, seed=21,
                                         tuned=(mode == "tuned"))
             srv.close()

@@ -383,7 +383,7 @@ class Server:
     """Scheduler thread: admits, batches, launches and completes requests."""
 
     def __init__(self, executor, budget: int, max_batch: int = 16384, depth: int = 2,
-                 bytes_of=None, poll_s: float = 2e-4):
+                 bytes_of=None, poll_s: float = 1e-5):
         self.ex = executor
         if bytes_of is None:
             bytes_of = lambda r: GpuExecutor.request_bytes(r, executor.models[r.model].F)  # noqa: E731

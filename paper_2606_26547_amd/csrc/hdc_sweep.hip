@@ -303,7 +303,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_shared(const uint64_t *__rest
 #pragma unroll
     for (int j = 0; j < KCW; ++j)
         acc[j] = 0;
-    int e = 0;    // next end to emit
+    int e = 0;    // next end to emit, and the word of its last dimension
+    int elw = __builtin_amdgcn_readfirstlane((ends[0] - 1) / 64);
     int b = 0;
     for (int c0 = a0; c0 < a1; c0 += kShWords, b ^= 1) {
         const int nw = a1 - c0 < kShWords ? a1 - c0 : kShWords;
@@ -321,27 +322,52 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_shared(const uint64_t *__rest
             fetch(c0 + kShWords);
         }
         __syncthreads();
-        for (int w = 0; w < nw; ++w) {
-            const uint64_t h = hs[lane][w];
-            const int a = c0 + w;
-            // sets whose last dimension lies in this word
-            while (e < nend && (ends[e] - 1) / 64 == a) {
-                const int rem = ends[e] - 64 * a;
-                const uint64_t pm = rem >= 64 ? ~0ull : (1ull << rem) - 1;
-                int key = 0x7fffffff;
+        for (int w = 0; w < nw;) {
+            if (c0 + w == elw) {
+                // sets whose last dimension lies in this word
+                const int a = c0 + w;
+                const uint64_t h = hs[lane][w];
+                while (e < nend && (ends[e] - 1) / 64 == a) {
+                    const int rem = ends[e] - 64 * a;
+                    const uint64_t pm = rem >= 64 ? ~0ull : (1ull << rem) - 1;
+                    int key = 0x7fffffff;
 #pragma unroll
-                for (int j = 0; j < KCW; ++j) {
-                    const int k = kb + j;
-                    const int d = acc[j] + (int)__popcll((h ^ cm[w][k]) & pm);
-                    if (k < K)
-                        key = min(key, d * 128 + k);
+                    for (int j = 0; j < KCW; ++j) {
+                        const int k = kb + j;
+                        const int d = acc[j] + (int)__popcll((h ^ cm[w][k]) & pm);
+                        if (k < K)
+                            key = min(key, d * 128 + k);
+                    }
+                    atomicMin(&best[e][lane], key);
+                    ++e;
                 }
-                atomicMin(&best[e][lane], key);
-                ++e;
-            }
+                elw = e < nend ? __builtin_amdgcn_readfirstlane((ends[e] - 1) / 64) : 0x7fffffff;
 #pragma unroll
-            for (int j = 0; j < KCW; ++j)
-                acc[j] += (int)__popcll(h ^ cm[w][kb + j]);
+                for (int j = 0; j < KCW; ++j)
+                    acc[j] += (int)__popcll(h ^ cm[w][kb + j]);
+                ++w;
+                continue;
+            }
+            // words up to the next set's last word: four at a time, their
+            // LDS reads issued together
+            const int stop = elw - c0 < nw ? elw - c0 : nw;
+            for (; w + 4 <= stop; w += 4) {
+                uint64_t h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    h[u] = hs[lane][w + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < KCW; ++j)
+                        acc[j] += (int)__popcll(h[u] ^ cm[w + u][kb + j]);
+            }
+            for (; w < stop; ++w) {
+                const uint64_t h = hs[lane][w];
+#pragma unroll
+                for (int j = 0; j < KCW; ++j)
+                    acc[j] += (int)__popcll(h ^ cm[w][kb + j]);
+            }
         }
         __syncthreads();    // the chunk's LDS reads are done
     }

@@ -139,8 +139,10 @@ def compact(out: dict) -> dict:
         sv = out["serving"]
         extras["serving"] = {m: dict(_pick(sv[m], "p50_ms", "p99_ms", "queries_per_s"),
                                      saturation_qps=sv[m].get("runs", {}).get("saturation", {}).get("queries_per_s"),
+                                     saturation_4096_qps=sv[m].get("runs", {}).get("saturation_4096", {})
+                                     .get("queries_per_s"),
                                      p99_by_budget={b: r.get("p99_ms") for b, r in sv[m].get("runs", {}).items()
-                                                    if b != "saturation"})
+                                                    if not b.startswith("saturation")})
                              for m in ("plain", "tuned") if m in sv}
     for key in ("cosine", "adc", "retrain"):
         if key in out and "roofline" in out[key]:
@@ -894,6 +896,15 @@ def serving(args, dev, dg, hdc, tuner, torch):
             srv.close()
             runs["saturation"] = {"concurrency": 64, "queries_per_s": q / wall, "seconds": wall}
             log("serving %s saturation: %.0f q/s" % (mode, q / wall))
+            # the same with every request at the largest size (4096 queries):
+            # per-request host work is amortised, so the device sets the pace
+            srv = serve.Server(ex, budget=16 << 30, poll_s=args.serve_poll_us * 1e-6)
+            q, wall = serve.closed_loop(srv, srcs, 16, args.serve_saturation_seconds, seed=22,
+                                        tuned=(mode == "tuned"), fixed_n=4096)
+            srv.close()
+            runs["saturation_4096"] = {"concurrency": 16, "request_queries": 4096, "queries_per_s": q / wall,
+                                       "seconds": wall}
+            log("serving %s saturation, 4096-query requests: %.0f q/s" % (mode, q / wall))
         # the first budget's run is the headline of this mode
         report[mode] = dict(runs[budgets[0]], runs=runs) if budgets else {"runs": runs}
     return report

@@ -228,3 +228,22 @@ def test_automatic_gc_is_off_while_serving_and_restored():
     b.close()
     b.close()                                       # a second close changes nothing
     assert gc.isenabled()
+
+
+def test_gpu_executor_staging_copy():
+    """The executor's staging copy writes each request at its offset and
+    zeroes the pad columns, as one plain copy would."""
+    import torch
+
+    from paper_2606_26547_amd.serve import GpuExecutor
+    ex = GpuExecutor.__new__(GpuExecutor)          # no device needed for the host copy
+    ex.torch = torch
+    g = np.random.default_rng(0)
+    reqs = [SimpleNamespace(n=n, X=g.integers(-127, 128, size=(n, 37)).astype(np.int8)) for n in (1, 250, 9, 1000)]
+    offs = list(np.cumsum([0] + [r.n for r in reqs])[:-1])
+    b = SimpleNamespace(requests=reqs, offsets=offs, n=sum(r.n for r in reqs))
+    hxt = torch.full((b.n, 64), 7, dtype=torch.int8)
+    ex._stage(hxt, b, 37, 64)
+    ref = np.zeros((b.n, 64), np.int8)
+    ref[:, :37] = np.concatenate([r.X for r in reqs])
+    assert np.array_equal(hxt.numpy(), ref)

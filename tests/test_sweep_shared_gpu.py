@@ -102,3 +102,19 @@ def test_shared_chains_match_oracle(env, n, F, D, K, xdt, seed):
     assert (res["n"] == n).all()
     per = _run(hdc, X, F, truth, P, D, C, cfgs, 0)
     assert np.array_equal(per["correct"], ref)
+
+
+def test_shared_invalid_configs_do_no_work(env):
+    """Unsupported dtypes and empty or out-of-range sets report n = 0 and no
+    time on the shared path too; the valid ones beside them are unaffected."""
+    hdc, ds = env["hdc"], env["ds"]
+    print("[case] shared sweep, invalid configurations", flush=True)
+    X, y = env["Xs"][:100], env["ys"][:100]
+    cfgs = [(99999, 1, 0, "int8"), (1024, 0, 0, "int8"), (1024, 1, 0, "fp32"), (1024, 1, 0, "int8"),
+            (1024, 1, 1024, "bf16"), (2048, 3, 5, "fp8")]
+    res = _run(hdc, X, ds.F, y, ds.P, ds.D, env["C"], cfgs, SHARED)
+    c, t, n = res["correct"], res["device_us"], res["n"]
+    assert (c[[0, 1, 2, 4]] == 0).all() and (t[[0, 1, 2, 4]] == 0).all() and (n[[0, 1, 2, 4]] == 0).all()
+    assert n[3] == 100 and n[5] == 100
+    assert c[3] == (O.classify(X, ds.P, env["C"], "int8", 0, 1024, 1) == y).sum()
+    assert c[5] == (O.classify(X, ds.P, env["C"], "fp8", 5, 2048, 3) == y).sum()

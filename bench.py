@@ -837,13 +837,21 @@ def serving(args, dev, dg, hdc, tuner, torch):
     models = [serve.ResidentModel(s.P, s.X_train, s.y_train, s.K) for s in srcs]
     tuned_cfgs = []
     for s, m in zip(srcs, models):
+        # per-model tuning: the 24-point grid (D', stride, encoding type) on
+        # 2048 labelled queries in one sweep call (shared path), then the
+        # cheapest candidates within 1 point re-timed on a 4096-query batch
         Xv, yv = s.queries(2048, 900)
-        grid = [(d, k, 0, "int8") for d in sorted({m.D, m.D // 2, m.D // 4, m.D // 8}) for k in (1, 2)]
-        res = tuner.sweep(hdc.pad_cols(Xv, dev), m.F, torch.as_tensor(yv).to(dev), m.P, m.D, m.C, grid)
-        best, plain = tuner.select_tuned(res, (m.D, 1, 0, "int8"), 1.0)
+        Xt = hdc.pad_cols(s.queries(4096, 901)[0], dev)
+        grid = [(d, k, 0, t) for d in sorted({m.D, m.D // 2, m.D // 4, m.D // 8}) for k in (1, 2)
+                for t in ("int8", "bf16", "fp8")]
+        res = tuner.sweep(hdc.pad_cols(Xv, dev), m.F, torch.as_tensor(yv).to(dev), m.P, m.D, m.C, grid,
+                          tile=SWEEP_SHARED)
+        best, plain = tuner.select_tuned(res, (m.D, 1, 0, "int8"), 1.0, max_timed=6,
+                                         timer=lambda c, m=m, Xt=Xt: tuner.time_config(c, Xt, m.F, m.P, m.D, m.C))
         m.set_tuned(best.cfg)
         tuned_cfgs.append({"F": m.F, "K": m.K, "D": m.D, "tuned": list(best.cfg),
-                           "acc_plain": plain.accuracy, "acc_tuned": best.accuracy})
+                           "acc_plain": plain.accuracy, "acc_tuned": best.accuracy,
+                           "qps_4096_plain": plain.qps, "qps_4096_tuned": best.qps})
     torch.cuda.synchronize()
 
     def job_cfgs(mi):

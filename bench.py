@@ -876,6 +876,7 @@ def serving(args, dev, dg, hdc, tuner, torch):
                 f.result(timeout=300)
             srv.completed.clear()
             srv.sched.blocked = 0
+            srv.max_loop_s, srv.loop_stalls = 0.0, 0
             t0 = time.perf_counter()
             futs = serve.open_loop(srv, srcs, 2000.0, args.serve_seconds, seed=7, tuned=(mode == "tuned"),
                                    job_cfgs=job_cfgs)

@@ -340,3 +340,19 @@ def test_eval_configs_host_arrays_without_device(lib):
     assert call(fake, 0, 2000, 617, cfgs, out, 64) == 3                       # workspace
     assert call(None, 0, 0, 617, cfgs, out, 1 << 30) == 0                     # n == 0
     assert [(r.correct, r.n, r.device_us) for r in out] == [(0, 0, 0.0)] * 3
+
+
+def test_config_array_layout():
+    """The binding's configuration table is the C struct layout (five int32:
+    d_trunc, stride, start, dtype, tile_id), tile ids default to the call's,
+    and an array already in that form passes through unchanged."""
+    import numpy as np
+
+    from paper_2606_26547_amd import hdc
+    a = hdc.config_array([(1024, 2, 0, "int8"), (2048, 1, 3, "fp8", 4), (512, 4, 1, hdc.DTYPE["bf16"])], tile=2)
+    assert a.dtype == np.int32 and a.shape == (3, 5) and a.flags.c_contiguous
+    assert a.tolist() == [[1024, 2, 0, hdc.DTYPE["int8"], 2], [2048, 1, 3, hdc.DTYPE["fp8"], 4],
+                          [512, 4, 1, hdc.DTYPE["bf16"], 2]]
+    assert C.sizeof(Config) == a.itemsize * a.shape[1]
+    assert hdc.config_array(a) is a
+    assert hdc.TILE_NAMES["sweep"][4] == "shared"

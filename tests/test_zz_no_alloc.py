@@ -30,8 +30,10 @@ def test_bundle_noalloc_matches_bundle():
     lib = hdc.lib()
     assert lib.hdc_bundle_noalloc_limit_bytes() == 32 << 20
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    # the multi-block grouping path first, then the single-workgroup path
-    for n, nbits, K in ((40000, 10240, 26), (3000, 2048, 10)):
+    # the multi-block grouping path twice (the second call on a smaller
+    # input reuses the scratch the first one left behind), then a small
+    # bundle (one kernel, no scratch)
+    for n, nbits, K in ((40000, 10240, 26), (20000, 4096, 40), (3000, 2048, 10)):
         say("bundle_noalloc", n, nbits, K)
         assert lib.hdc_bundle_workspace_bytes(n, nbits, K) <= lib.hdc_bundle_noalloc_limit_bytes()
         H, y = _inputs(n, nbits, K, n)

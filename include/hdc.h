@@ -409,10 +409,12 @@ hdc_status hdc_classify_prepared(void *stream,
                                  int32_t tile);
 
 /* ---------------------------------------------------------------------
- * hdc_eval_configs -- one persistent launch that evaluates many
- * approximation configurations on the same queries: the inner loop of the
- * paper's tuning system, which runs each candidate configuration and reads
- * back its quality of service and time (Sec. 3, Sec. 4.1).  For every
+ * hdc_eval_configs -- one call that evaluates many approximation
+ * configurations on the same queries (a persistent kernel over per-
+ * configuration work items, and/or the shared path; see the sweep tile
+ * variants below): the inner loop of the paper's tuning system, which runs
+ * each candidate configuration and reads back its quality of service and
+ * time (Sec. 3, Sec. 4.1).  For every
  * configuration c, the queries are classified exactly as hdc_classify with
  * dims {cfg.start, cfg.d_trunc, cfg.stride} and compute = cfg.dtype, and
  *     out[c].correct   = #{i : label_i == truth[i]}

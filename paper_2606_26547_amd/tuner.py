@@ -5,7 +5,9 @@ candidate approximation configuration is compiled, run by a user driver
 that reports its quality of service (QoS) and time, and the search keeps the
 fastest configuration whose QoS stays within a user bound (Sec. 5.2 uses
 "baseline QoS minus 0.05").  Here every candidate is evaluated on the device
-in one persistent launch (``hdc_eval_configs``), QoS is classification
+in one call (``hdc_eval_configs``: a persistent kernel, or the shared path
+that ranks all configurations of an encoding type from one encoding), QoS is
+classification
 accuracy on the sweep queries, and the bound is an accuracy loss of at most
 ``budget_pts`` points against the plain (unapproximated) configuration.
 
@@ -53,8 +55,9 @@ class Result:
 
 def sweep(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D: int, Cw: torch.Tensor,
           cfgs, tile: int = 0) -> list[Result]:
-    """Evaluate every configuration with one persistent launch (work items
-    of the sweep tile variant `tile` for every configuration, 0 = built-in)."""
+    """Evaluate every configuration in one hdc_eval_configs call, every
+    configuration with the sweep tile variant `tile` (0 = the built-in
+    per-configuration items; 4 = the shared path)."""
     cfgs = [tuple(c) for c in cfgs]
     res = hdc.eval_configs(X, F, truth, P, D, Cw, cfgs, tile=tile)
     return [Result(cfg, int(res["correct"][i]), int(res["n"][i]), float(res["device_us"][i]))

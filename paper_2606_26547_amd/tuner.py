@@ -7,9 +7,9 @@ fastest configuration whose QoS stays within a user bound (Sec. 5.2 uses
 "baseline QoS minus 0.05").  Here every candidate is evaluated on the device
 in one call (``hdc_eval_configs``: a persistent kernel, or the shared path
 that ranks all configurations of an encoding type from one encoding), QoS is
-classification
-accuracy on the sweep queries, and the bound is an accuracy loss of at most
-``budget_pts`` points against the plain (unapproximated) configuration.
+classification accuracy on the sweep queries, and the bound is an accuracy
+loss of at most ``budget_pts`` points against the plain (unapproximated)
+configuration.
 
 A configuration is (d_trunc, stride, start, dtype): the encoding and Hamming
 reductions run over dimensions S = {start + j*stride < d_trunc} (reduction

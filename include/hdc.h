@@ -488,7 +488,10 @@ hdc_status hdc_eval_configs(void *stream,
  *   variants  encoder / classifier: HDC_TILE_DMA_2X2 and HDC_TILE_DMA_1X1
  *             (projection staged straight into LDS; two query tiles x two
  *             dimension tiles per wave, or one of each; int8 features on the
- *             int8 path), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
+ *             int8 path), HDC_TILE_DMA_2X3 (classifier only, one class tile,
+ *             F <= 640: two query tiles x three dimension tiles, 96-
+ *             dimension chunks in two LDS stages; never splits its
+ *             dimensions), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
  *             staging, two or one query tiles of 32 per wave);
  *             sweep: HDC_TILE_SWEEP_256 (work items of 256 queries: int8
  *             configurations take two query tiles per wave where the
@@ -523,6 +526,7 @@ enum {
     HDC_TILE_DMA_1X1 = 2,
     HDC_TILE_REG_QT1 = 3,
     HDC_TILE_REG_QT2 = 4,
+    HDC_TILE_DMA_2X3 = 5,
     HDC_TILE_SWEEP_128 = 1,
     HDC_TILE_SWEEP_256 = 2,
     HDC_TILE_SWEEP_256_DMA = 3,

@@ -132,11 +132,21 @@ static hipError_t launch_one(const EncodeArgs &a, hipStream_t st)
 // Where the registers allow (big_tile), each wave (one per SIMD) multiplies
 // two query tiles by two row tiles per chunk: four independent accumulator
 // chains, each projection fragment read from LDS feeds two MFMAs, and a
-// barrier every 80 MFMAs.  Otherwise (or when the tile table asks for it)
-// one tile of each, two waves per SIMD.
+// barrier every 80 MFMAs; the classifier can also take three row tiles per
+// chunk (TV_DMA_2X3: a barrier every 120 MFMAs, two stages).  Otherwise (or
+// when the tile table asks for it) one tile of each, two waves per SIMD.
 template <int KS, int KT, int MODE>
 static hipError_t launch_dma(const EncodeArgs &a, int variant, hipStream_t st)
 {
+    if constexpr (MODE == M_CLASSIFY && big3_tile(KS, KT)) {
+        // 96-dimension chunks: a dimension split would end inside a chunk
+        // and read the next split's class tiles, so this shape never splits
+        if (variant == TV_DMA_2X3) {
+            EncodeArgs b = a;
+            b.max_split = 1;
+            return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 3>(b, st);
+        }
+    }
     if constexpr (big_tile(KS, KT)) {
         if (variant != TV_DMA_1X1)
             return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 2>(a, st);
@@ -153,7 +163,7 @@ static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStr
 {
     const int v = tile.variant;
     if constexpr (CT == C_I8 && XF == 0) {
-        if (a.x_type == X_INT8 && (v == TV_AUTO || v == TV_DMA_2X2 || v == TV_DMA_1X1)) {
+        if (a.x_type == X_INT8 && (v == TV_AUTO || v == TV_DMA_2X2 || v == TV_DMA_1X1 || v == TV_DMA_2X3)) {
             if (mode == M_ENCODE)
                 return launch_dma<KS, 1, M_ENCODE>(a, v, st);
             const int kt = class_tiles(a.K);

@@ -41,16 +41,18 @@ struct Encoder {
     // in the compute type (bf16 / E4M3 +-1.0, built once by the caller) for
     // those paths, which take either feature type.
     // A chunk is RT row tiles of 32 dimensions (RT > 1 with DMA staging
-    // only); its class operand is RT * KT KiB.
+    // only; three row tiles classify only, in two stages); its class operand
+    // is RT * KT KiB.
     static_assert(!DMA || (XF == 0 && (CT == C_I8 || CT == C_BF16 || CT == C_FP8)),
                   "direct LDS staging is for integer features on the int8, bf16 and E4M3 paths");
     static_assert(RT == 1 || DMA, "several row tiles per chunk need direct LDS staging");
+    static_assert(RT != 3 || MODE == M_CLASSIFY, "three row tiles per chunk: classify only");
     static constexpr int CH = kDimChunk * RT;              // dimensions per chunk
     static constexpr int UPR = RSB / 16;                   // 16-byte units per LDS row
     static constexpr int NIW = (CH * UPR + 64 * kWaves - 1) / (64 * kWaves);
     static constexpr int NCT = RT * KT;                    // class tiles per chunk
     static constexpr int NCW = (NCT + kWaves - 1) / kWaves;   // class-tile loads per wave
-    static constexpr int NBUF = DMA ? 3 : 2;               // LDS stages
+    static constexpr int NBUF = DMA ? (RT == 3 ? 2 : 3) : 2;   // LDS stages
     static constexpr int SSZ = DMA ? NIW * kWaves * 1024 : CH * RSB;   // bytes per stage
     static constexpr int OFF_C = NBUF * SSZ;
     static constexpr int OFF_CS = OFF_C + (MODE == M_CLASSIFY ? NBUF * NCT * 1024 : 0);
@@ -661,25 +663,28 @@ struct Encoder {
         asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(G) : "memory");
     }
 
-    // Three-stage loop: step c multiplies the RT row tiles of chunk c one
-    // after the other, each with the previous row tile's epilogue between
-    // its MFMAs (the first pass also issues the loads of chunk c+2 there),
-    // reads each tile's class fragments into registers right after its
-    // pass, waits for chunk c+1's loads and synchronises once.  Row tile
-    // passes alternate between two accumulator sets: with RT = 2 that is
-    // fixed within a step, with RT = 1 the loop is unrolled by two.
+    // Staged loop: step c multiplies the RT row tiles of chunk c one after
+    // the other, each with the previous row tile's epilogue between its
+    // MFMAs (the first pass also issues the loads of the chunk NBUF - 1
+    // ahead there), reads each tile's class fragments into registers right
+    // after its pass, waits for chunk c+1's loads and synchronises once.
+    // Three stages for one or two row tiles; two for three (96-dimension
+    // chunks: 120 MFMAs per wave between barriers), whose next chunk's
+    // loads then have one step to land.  Row tile passes rotate through RT
+    // accumulator sets (two with RT = 1, the loop unrolled by two).
     static __device__ __forceinline__ void run_dma(const EncodeArgs &a, uint8_t *smem, int64_t qblock,
                                                    v16i (&dacc)[KT][QT])
     {
-        static_assert(RT == 1 || RT == 2, "one or two row tiles per chunk");
+        static_assert(RT == 1 || RT == 2 || RT == 3, "one to three row tiles per chunk");
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5;
         const int64_t qbase = qblock + (int64_t)wave * QPW;
         const int ks_used = (a.F + KSTEP - 1) / KSTEP;
         const int npc = (ks_used * KB + 15) / 16;   // 16-byte pieces of a row holding features
         const int NC = (a.nd + CH - 1) / CH;
         // loads issued per step after those of the chunk waited for (stores
-        // of the encode epilogue are not counted: waiting for more is safe)
-        constexpr int G = NLOADS;
+        // of the encode epilogue are not counted: waiting for more is safe);
+        // with two stages the chunk waited for is the one issued last
+        constexpr int G = NBUF == 3 ? NLOADS : 0;
 
         xfrag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
@@ -694,7 +699,7 @@ struct Encoder {
         auto lc = [&](int i) { return L + OFF_C + i * (NCT * 1024); };
         const Loader ld(a, NC, npc, wave, lane);
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < NBUF - 1; ++c)
 #pragma unroll
             for (int i = 0; i < NLOADS; ++i)
                 ld.issue(i, c, lp(c), lc(c));
@@ -714,20 +719,37 @@ struct Encoder {
             tile_mma(cur, xr, lp(b) + rt * kDimChunk * RSB, nullptr, false, lane, hook);
             read_cf(rt);
         };
-        auto loads = [&](int c) {   // loads of chunk c + 2 into the free stage
-            const int b2 = b == 0 ? 2 : b - 1;   // (b + 2) % 3
-            return LoadHook{ld, c + 2, lp(b2), lc(b2)};
+        auto loads = [&](int c) {   // loads of chunk c + NBUF - 1 into the free stage
+            if constexpr (NBUF == 3) {
+                const int b2 = b == 0 ? 2 : b - 1;   // (b + 2) % 3
+                return LoadHook{ld, c + 2, lp(b2), lc(b2)};
+            } else {
+                return LoadHook{ld, c + 1, lp(b ^ 1), lc(b ^ 1)};
+            }
         };
         auto epi = [&](Parts &prev, int w) { return EpiHook{Epilogue{a, prev, dacc, cf, w, lane, g, qbase}}; };
         typedef Both<EpiHook, LoadHook> EpiLoad;
         typedef Both<NoHook, LoadHook> JustLoad;
         auto finish_step = [&]() {
             dma_barrier<G>();
-            b = b == 2 ? 0 : b + 1;
+            b = b == NBUF - 1 ? 0 : b + 1;
         };
 
         Parts P0, P1;
-        if constexpr (RT == 2) {
+        if constexpr (RT == 3) {
+            Parts P2;
+            pass(0, P0, JustLoad{NoHook{}, loads(0)});
+            pass(1, P1, epi(P0, 0));
+            pass(2, P2, epi(P1, 1));
+            finish_step();
+            for (int c = 1; c < NC; ++c) {
+                pass(0, P0, EpiLoad{epi(P2, 3 * c - 1), loads(c)});
+                pass(1, P1, epi(P0, 3 * c));
+                pass(2, P2, epi(P1, 3 * c + 1));
+                finish_step();
+            }
+            run_epilogue(Epilogue{a, P2, dacc, cf, 3 * NC - 1, lane, g, qbase});
+        } else if constexpr (RT == 2) {
             pass(0, P0, JustLoad{NoHook{}, loads(0)});
             pass(1, P1, epi(P0, 0));
             finish_step();

@@ -96,9 +96,10 @@ constexpr int kMaxLevels = 1024;
 
 inline int class_tiles(int K) { return (K + 31) / 32 <= 1 ? 1 : ((K + 31) / 32 <= 2 ? 2 : 4); }
 inline int64_t chunks(int nd) { return (nd + kDimChunk - 1) / kDimChunk; }
-// The fused classifier's class operand covers a whole number of its widest
-// dimension chunks (kMaxRT tiles of 32); rows past the dimension count are 0.
-constexpr int kMaxRT = 2;
+// The fused classifier's class operand covers a whole number of every
+// chunk width it is read in (2 and 3 tiles of 32: a multiple of kMaxRT
+// tiles); rows past the dimension count are 0.
+constexpr int kMaxRT = 6;
 inline int64_t table_chunks(int nd) { return (chunks(nd) + kMaxRT - 1) / kMaxRT * kMaxRT; }
 inline size_t class_table_bytes(int nd, int K) { return (size_t)table_chunks(nd) * class_tiles(K) * 1024; }
 
@@ -106,7 +107,8 @@ inline size_t class_table_bytes(int nd, int K) { return (size_t)table_chunks(nd)
 // with two query tiles x two row tiles per wave or one of each (int8
 // features on the int8 path), or register staging with one or two query
 // tiles per wave.
-enum TileVariant : int { TV_AUTO = 0, TV_DMA_2X2 = 1, TV_DMA_1X1 = 2, TV_REG_QT1 = 3, TV_REG_QT2 = 4 };
+enum TileVariant : int { TV_AUTO = 0, TV_DMA_2X2 = 1, TV_DMA_1X1 = 2, TV_REG_QT1 = 3, TV_REG_QT2 = 4,
+                         TV_DMA_2X3 = 5 };
 // Tile variants of the configuration sweep (per configuration): work items of
 // 128 queries (one query tile per wave) or of 256 (int8 slots with two query
 // tiles per wave where the registers allow, other slots in two passes), or of
@@ -120,6 +122,9 @@ enum KernelKind : int { KK_ENCODE = 0, KK_CLASSIFY = 1, KK_SWEEP = 2 };
 // Direct staging with 2x2 tiles fits the registers up to 20 K steps and two
 // class tiles.
 constexpr bool big_tile(int ks, int kt) { return ks <= 20 && kt <= 2; }
+// The classifier's 2x3 shape (two query tiles x three row tiles, chunks of
+// 96 dimensions in a two-stage ring): one class tile.
+constexpr bool big3_tile(int ks, int kt) { return ks <= 20 && kt == 1; }
 // Two query tiles per wave fit beside the accumulators (register staging).
 constexpr bool qt2_fits(int ct, int ks) { return (ct == C_I8 && ks <= 16) || (ct == C_F32 && ks <= 64); }
 // K step (features per MFMA) of a compute type.

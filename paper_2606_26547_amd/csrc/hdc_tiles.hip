@@ -14,7 +14,7 @@ constexpr int kNF = sizeof(kF32Widths) / sizeof(kF32Widths[0]);
 constexpr int kNS = sizeof(kSweepWidths) / sizeof(kSweepWidths[0]);
 
 // Variants a bucket is compiled with; the first listed is what 0 selects.
-int encoder_variants(int ct, int x_type, int width, int kt, int *out)
+int encoder_variants(int ct, int x_type, int width, int kt, bool classify, int *out)
 {
     const int ks = width / kstep_of(ct);
     int n = 0;
@@ -22,6 +22,8 @@ int encoder_variants(int ct, int x_type, int width, int kt, int *out)
         if (big_tile(ks, kt))
             out[n++] = TV_DMA_2X2;
         out[n++] = TV_DMA_1X1;
+        if (classify && big3_tile(ks, kt))
+            out[n++] = TV_DMA_2X3;
     }
     if (qt2_fits(ct, ks))
         out[n++] = TV_REG_QT2;
@@ -92,7 +94,8 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
             return -1;
         const int wi = width_index(x_type, F);
         const int width = x_type == X_FP32 ? kF32Widths[wi] : kIntWidths[wi];
-        n = encoder_variants(ct, x_type, width, encoder_kt(kind == KK_ENCODE ? M_ENCODE : M_CLASSIFY, K), v);
+        n = encoder_variants(ct, x_type, width, encoder_kt(kind == KK_ENCODE ? M_ENCODE : M_CLASSIFY, K),
+                             kind == KK_CLASSIFY, v);
     }
     for (int i = 0; i < n && i < cap; ++i)
         out[i] = v[i];

@@ -315,7 +315,7 @@ def level_id_encode(lev: torch.Tensor, ID: torch.Tensor, LV: torch.Tensor, D: in
 
 KERNEL = {"encode": 0, "classify": 1, "sweep": 2}
 TILE_NAMES = {"encode": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
-              "classify": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2"},
+              "classify": {1: "dma_2x2", 2: "dma_1x1", 3: "reg_qt1", 4: "reg_qt2", 5: "dma_2x3"},
               "sweep": {1: "items_128", 2: "items_256", 3: "items_256_dma", 4: "shared"}}
 
 

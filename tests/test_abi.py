@@ -101,7 +101,7 @@ def test_validation_without_device(lib):
     assert lib.hdc_hamming_argmin(None, fake, 4, 2, fake, 3, 1, 100, Dims(0, 64, 1), fake, None, None) == 1
     assert lib.hdc_hamming_argmin(None, None, 0, 2, fake, 3, 2, 100, Dims(0, 64, 1), None, None, None) == 0
     lib.hdc_classify_workspace_bytes.restype = C.c_size_t
-    assert lib.hdc_classify_workspace_bytes(10240, 26) == 320 * 1024 + 512
+    assert lib.hdc_classify_workspace_bytes(10240, 26) == 324 * 1024 + 512   # 320 tiles, padded to 6
     assert lib.hdc_classify_workspace_bytes(10240, 200) == 0
     lib.hdc_hamming_workspace_bytes.restype = C.c_size_t
     lib.hdc_hamming_workspace_bytes.argtypes = [Dims, i32]
@@ -252,7 +252,7 @@ def test_tile_variants_without_device(lib):
         n = lib.hdc_tile_variants(*a, buf, 8)
         return None if n < 0 else list(buf[:n])
     # 617 features -> 640-wide int8 kernels: 20 K steps, no two-tile register staging
-    assert variants(CLS, INT8, INT8, 617, 26) == [1, 2, 3]
+    assert variants(CLS, INT8, INT8, 617, 26) == [1, 2, 5, 3]
     assert variants(CLS, INT8, INT8, 617, 100) == [2, 3]          # four class tiles: one query tile
     assert variants(CLS, UINT8, INT8, 512, 10) == [4, 3]          # uint8 features: register staging
     assert variants(CLS, INT8, BF16, 617, 26) == [3]

@@ -490,8 +490,10 @@ hdc_status hdc_eval_configs(void *stream,
  *             dimension tiles per wave, or one of each; int8 features on the
  *             int8 path), HDC_TILE_DMA_2X3 (classifier only, one class tile,
  *             F <= 640: two query tiles x three dimension tiles, 96-
- *             dimension chunks in two LDS stages; never splits its
- *             dimensions), HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
+ *             dimension chunks in two LDS stages; it cannot split its
+ *             dimensions, so a batch too small to fill the device runs on
+ *             the 2x2 shape with dimension splits instead),
+ *             HDC_TILE_REG_QT2 and HDC_TILE_REG_QT1 (register
  *             staging, two or one query tiles of 32 per wave);
  *             sweep: HDC_TILE_SWEEP_256 (work items of 256 queries: int8
  *             configurations take two query tiles per wave where the

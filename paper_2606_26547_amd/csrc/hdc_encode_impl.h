@@ -140,11 +140,17 @@ static hipError_t launch_dma(const EncodeArgs &a, int variant, hipStream_t st)
 {
     if constexpr (MODE == M_CLASSIFY && big3_tile(KS, KT)) {
         // 96-dimension chunks: a dimension split would end inside a chunk
-        // and read the next split's class tiles, so this shape never splits
+        // and read the next split's class tiles, so this shape never splits;
+        // a batch the 2x2 shape would split (too few query blocks to fill
+        // the device) runs on that shape instead
         if (variant == TV_DMA_2X3) {
-            EncodeArgs b = a;
-            b.max_split = 1;
-            return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 3>(b, st);
+            typedef Encoder<C_I8, 0, 2, KS, KT, MODE, 0, true, 2> E2;
+            const int64_t blocks = (a.n + E2::QPB - 1) / E2::QPB;
+            if (split_count(blocks, a.nd, a.max_split, 256 * E2::WAVES) == 1) {
+                EncodeArgs b = a;
+                b.max_split = 1;
+                return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 3>(b, st);
+            }
         }
     }
     if constexpr (big_tile(KS, KT)) {

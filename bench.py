@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile choices, no tuning launches")
     ap.add_argument("--classify-tile", default=None,
                     help="tile variant of the headline classifier by name (dma_2x2, dma_2x3, ...): no tuning for it")
+    ap.add_argument("--classify-form", default="auto", choices=["auto", "int8", "int8shift"],
+                    help="projection form of the int8 classifier: the +-1 projection (int8), the shifted one "
+                         "(int8shift: weights p + 1, the same results), or whichever the tuning times faster")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of each open-loop serving run")
     ap.add_argument("--serve-budgets", default="16G,64M,5M",
                     help="HBM budgets of the open-loop serving runs (in-flight request bytes)")
@@ -107,10 +110,11 @@ def compact(out: dict) -> dict:
     full record goes to a file).  Stays well under 4 KB."""
     c = _pick(out, "metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
               "scaling", "vs_baseline", "dtype", "data", "accuracy_plain", "p50_ms", "p99_ms")
-    c["config"] = _pick(out.get("config", {}), "workload", "F", "K", "D", "batch", "parallelism")
+    c["config"] = _pick(out.get("config", {}), "workload", "F", "K", "D", "batch", "parallelism",
+                        "projection_form")
     if "roofline" in out:
         c["roofline"] = _pick(out["roofline"], "bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                              "ms_per_launch")
+                              "ms_per_launch", "tile")
     if "cpu_baseline" in out:
         c["cpu_baseline"] = _pick(out["cpu_baseline"], "value", "unit", "cores", "kind", "sample", "cpu_model",
                                   "tuned_value", "single_thread_value")
@@ -158,6 +162,11 @@ def compact(out: dict) -> dict:
     return _r(c)
 
 
+def traffic_key(tile: str, form: str) -> str:
+    """Key of the headline launch's record in profiles/traffic.json."""
+    return "k_encode_classify_speech_b262144_" + tile + ("_shift" if form == "int8shift" else "")
+
+
 def measured_traffic(key: str, batch: int, tile: str):
     """HBM bytes per launch of a kernel from profiles/traffic.json (rocprofv3
     FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when the kernel's
@@ -200,6 +209,9 @@ def main():
     log("data ready in %.1fs: F=%d K=%d D=%d batch=%d" % (time.time() - t0, F, K, D, N))
 
     Pd = hdc.pad_cols(ds.P, dev)
+    # the model's projection in the shifted form (made once with the model;
+    # int8 classification on it gives the same labels and distances)
+    Ps = hdc.shift_projection(Pd, F)
     Xtr = hdc.pad_cols(ds.X_train, dev)
     ytr = torch.as_tensor(ds.y_train).to(dev)
     Xqd = hdc.pad_cols(Xq, dev)
@@ -242,25 +254,35 @@ def main():
     tile_shapes = [AT.Shape("encode", F, 1, D, 8192), AT.Shape("sweep", F, K, D, dg.C4["n_queries"], cfgs=slots)]
     t0 = time.time()
     tiles = AT.autotune(tile_shapes) if not args.no_autotune else []
-    # the headline classifier is tuned at the batch it is timed on; its
-    # variants give identical labels, so a 1% margin is enough
+    # the headline classifier is tuned at the batch it is timed on, in both
+    # projection forms; its variants give identical labels, so a 1% margin
+    # is enough
+    forms = ["int8", "int8shift"] if args.classify_form == "auto" else [args.classify_form]
+    forms = [f for f in forms if f == "int8" or hdc.shift_supported("classify", F, K)]
+    cls_choice = {}
     if not args.no_autotune and not args.classify_tile:
-        tiles.append(AT.tune(AT.Shape("classify", F, K, D, N), margin=0.01))
+        for form in forms:
+            cls_choice[form] = AT.tune(AT.Shape("classify", F, K, D, N, compute=form), margin=0.01)
+            tiles.append(cls_choice[form])
     table = AT.TileTable.from_choices(tiles)
-    cls_tile_id = table.get("classify", "int8", "int8", F, K)
+    # the form whose chosen variant timed fastest (the first listed without timings)
+    cls_form = min(forms, key=lambda f: cls_choice[f].variants[cls_choice[f].chosen_name]) if cls_choice \
+        else forms[-1]
+    cls_tile_id = table.get("classify", "int8", cls_form, F, K)
     if args.classify_tile:
         cls_tile_id = {v: k for k, v in hdc.TILE_NAMES["classify"].items()}[args.classify_tile]
+    P_cls = Ps if cls_form == "int8shift" else Pd
     tiles_in_use["encode"] = table.get("encode", "int8", "int8", F, 1)
     sweep_tile = table.get("sweep", "int8", "int8", F, K)
-    cls_tile = hdc.TILE_NAMES["classify"][cls_tile_id or hdc.tile_variants("classify", "int8", "int8", F, K)[0]]
+    cls_tile = hdc.TILE_NAMES["classify"][cls_tile_id or hdc.tile_variants("classify", "int8", cls_form, F, K)[0]]
     log("tiles (%.1fs): %s" % (time.time() - t0, {c.shape.kind: (c.chosen_name, {k: round(v, 3) for k, v in
                                                                                  c.variants.items()})
                                                   for c in tiles}))
 
     # ------------------------------------------------------------ plain steps
-    plain = hdc.Prepared(Cw, D, "int8", tile=cls_tile_id)
+    plain = hdc.Prepared(Cw, D, cls_form, tile=cls_tile_id)
     labels = torch.empty(N, dtype=torch.int32, device=dev)
-    ms_step, ms_kernel, _ = event_loop(lambda: plain(Xqd, F, Pd, labels), args.steps, args.warmup)
+    ms_step, ms_kernel, _ = event_loop(lambda: plain(Xqd, F, P_cls, labels), args.steps, args.warmup)
     acc_plain = float((labels == yqd).float().mean().item())
     qps = N / (ms_step / 1e3)
     ops = 2.0 * F * D * N                      # algorithmic encode ops per launch (pad not counted)
@@ -283,13 +305,14 @@ def main():
         "data": "synthetic (seeded c2 Gaussian-mixture generator; ISOLET-shaped, no real dataset)",
         "config": {"workload": "speech-shaped HDC classify, int8 features F=617, K=26 classes, D=10240, "
                                "plain config, batch of %d fresh queries; model bundled from 6238 train vectors" % N,
-                   "F": F, "K": K, "D": D, "batch": N, "parallelism": "none (1 GPU)"},
+                   "F": F, "K": K, "D": D, "batch": N, "parallelism": "none (1 GPU)",
+                   "projection_form": cls_form},
         "accuracy_plain": acc_plain,
         "tiles": AT.to_json(tiles) if tiles else None,
         "roofline": {"bound": "mfma", "kernel": "k_encode<int8, classify>", "achieved": achieved,
                      "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
-                     "traffic": measured_traffic("k_encode_classify_speech_b262144_" + cls_tile, N, cls_tile),
-                     "tile": cls_tile,
+                     "traffic": measured_traffic(traffic_key(cls_tile, cls_form), N, cls_tile),
+                     "tile": cls_tile, "form": cls_form,
                      "traffic_unit": "bytes per launch (HBM read + write, profiles/traffic.json)",
                      "ms_per_launch": ms_kernel,
                      "ops_per_launch": ops},
@@ -341,7 +364,8 @@ def main():
         grid_res = tuner.sweep(Xsd, F, ysd, Pd, D, Cw, grid, tile=sweep_tile)
         best, plain_r = tuner.select_tuned(
             grid_res, (D, 1, 0, "int8"), 1.0,
-            timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw, tile=cls_tile_id))
+            timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw, tile=cls_tile_id,
+                                              shifted=Ps if cls_form == "int8shift" else None))
         pc_ms, sh_ms = sweep_ms_by[0], sweep_ms_by[SWEEP_SHARED]
         out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
                         "tile": hdc.TILE_NAMES["sweep"].get(sweep_tile, "built-in"),
@@ -362,9 +386,11 @@ def main():
                                                     "queries each) over the whole call; the masked Hamming "
                                                     "search is VALU work and not counted"}}
         d, k, s, tdt = best.cfg
-        tuned = hdc.Prepared(Cw, D, tdt, s, d, k, tile=cls_tile_id if tdt == "int8" else 0)
+        t_form = cls_form if tdt == "int8" else tdt
+        P_t = Ps if t_form == "int8shift" else Pd
+        tuned = hdc.Prepared(Cw, D, t_form, s, d, k, tile=cls_tile_id if tdt == "int8" else 0)
         tl = torch.empty(N, dtype=torch.int32, device=dev)
-        ms_t, ms_tk, _ = event_loop(lambda: tuned(Xqd, F, Pd, tl), args.steps, args.warmup)
+        ms_t, ms_tk, _ = event_loop(lambda: tuned(Xqd, F, P_t, tl), args.steps, args.warmup)
         acc_t = float((tl == yqd).float().mean().item())
         out["tuned"] = {"config": {"d_trunc": d, "stride": k, "start": s, "dtype": tdt},
                         "value": N / (ms_t / 1e3), "ms_per_step": ms_t, "accuracy": acc_t,
@@ -375,15 +401,15 @@ def main():
         # -------------------------------------------------------- latency at config size
         lat = {}
         nte = int(Xte.shape[0])
-        for name, prep in (("plain", plain), ("tuned", tuned)):
+        for name, prep, Pp in (("plain", plain, P_cls), ("tuned", tuned, P_t)):
             lab = torch.empty(nte, dtype=torch.int32, device=dev)
             for _ in range(10):
-                prep(Xte, F, Pd, lab)
+                prep(Xte, F, Pp, lab)
             torch.cuda.synchronize()
             ts = []
             for _ in range(args.latency_calls):
                 t = time.perf_counter()
-                prep(Xte, F, Pd, lab)
+                prep(Xte, F, Pp, lab)
                 torch.cuda.synchronize()
                 ts.append((time.perf_counter() - t) * 1e3)
             lat[name] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),

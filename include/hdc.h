@@ -44,7 +44,10 @@
  *   1's hypermatrix<D, F>).  ldp >= F rounded up to 64, a multiple of 16,
  *   P 16-byte aligned; columns [0, F) must hold +1 or -1.  D * ldp must be
  *   below 2^32 bytes (the kernels address P with 32-bit offsets); a larger
- *   projection gives HDC_ERR_UNSUPPORTED.
+ *   projection gives HDC_ERR_UNSUPPORTED.  With compute HDC_INT8_SHIFTED,
+ *   P is the shifted form written by hdc_shift_projection instead (columns
+ *   [0, F) hold p + 1, i.e. 0 or 2); the results are those of HDC_INT8 on
+ *   the +-1 projection it was made from.
  */
 #ifndef HDC_H
 #define HDC_H
@@ -77,18 +80,26 @@ typedef enum {
  *                                        parts exact in E4M3; two E4M3 MFMAs
  *                                        into fp32 sums below 2^24: exact,
  *                                        the same bits as HDC_INT8
+ *   HDC_INT8 -> HDC_INT8_SHIFTED          exact, the same bits as HDC_INT8, on
+ *                                        the shifted projection (see
+ *                                        hdc_shift_projection): int8 MFMA on
+ *                                        weights p + 1 in {0, 2}, every sum
+ *                                        started from minus the query's
+ *                                        feature sum
  *   HDC_FP32 -> HDC_FP32 / HDC_BF16 / HDC_FP8_E4M3   (F <= 256)
  * The reduced types round each feature to the compute type (round to nearest
  * even) and multiply by the exactly representable +-1 weights (Sec. 4.2
  * "Element Type Representation").  HDC_FP8_E4M3_SPLIT is a compute type
- * only (never a feature type) and is not a sweep configuration dtype. */
+ * only (never a feature type) and is not a sweep configuration dtype; so
+ * is HDC_INT8_SHIFTED. */
 typedef enum {
     HDC_INT8 = 0,
     HDC_UINT8 = 1,
     HDC_BF16 = 2,
     HDC_FP8_E4M3 = 3,
     HDC_FP32 = 4,
-    HDC_FP8_E4M3_SPLIT = 5
+    HDC_FP8_E4M3_SPLIT = 5,
+    HDC_INT8_SHIFTED = 6
 } hdc_dtype;
 
 typedef struct {
@@ -126,6 +137,24 @@ hdc_status hdc_encode_tiled(void *stream,
                             const int8_t *P, int32_t D, int64_t ldp,
                             hdc_dtype compute, hdc_dims dims,
                             uint64_t *H, int64_t ldh, int32_t tile);
+
+/* ---------------------------------------------------------------------
+ * hdc_shift_projection -- the projection in the form HDC_INT8_SHIFTED
+ * reads: out[d][f] = P[d][f] + 1 for f < F (0 or 2 for +-1 weights) and 0
+ * in the pad columns [F, ldo).  The encoding is unchanged (Sec. 2.2 Listing
+ * 1; with x the features and p a row, sum_f x_f (p_f + 1) - sum_f x_f is
+ * the same y); the shifted weights are mostly zero bits, which the matrix
+ * cores run at a higher clock than +-1.  Made once per model.
+ *   P    [D][ldp] int8, as for hdc_encode (+-1 in columns [0, F))
+ *   out  [D][ldo] int8 output, ldo >= F rounded up to 64, a multiple of
+ *        16, 16-byte aligned; D * ldo below 2^32 bytes.  out may be P
+ *        itself when ldo == ldp (in place); any other overlap with P gives
+ *        HDC_ERR_INVALID.
+ * F <= 1024.
+ * ------------------------------------------------------------------- */
+hdc_status hdc_shift_projection(void *stream,
+                                const int8_t *P, int32_t D, int32_t F, int64_t ldp,
+                                int8_t *out, int64_t ldo);
 
 /* ---------------------------------------------------------------------
  * hdc_bundle -- class bundling (Sec. 2.1: same-class hypervectors are

@@ -20,6 +20,11 @@ hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, 
     case C_BF16: return launch_encode_bf16(a, mode, tile, st);
     case C_F32: return launch_encode_f32(a, mode, tile, st);
     case C_FP8S: return launch_encode_fp8s(a, mode, tile, st);
+    case C_I8S: {
+        EncodeArgs b = a;
+        b.poff = 1;
+        return launch_encode_i8(b, mode, tile, st);
+    }
     }
     return hipErrorInvalidValue;
 }
@@ -52,6 +57,7 @@ int compute_of(hdc_dtype x, hdc_dtype c)
         if (c == HDC_BF16) return C_BF16;
         if (c == HDC_FP8_E4M3) return C_FP8;
         if (c == HDC_FP8_E4M3_SPLIT) return C_FP8S;
+        if (c == HDC_INT8_SHIFTED) return x == HDC_INT8 ? C_I8S : -1;
         return -1;
     }
     if (x == HDC_FP32) {
@@ -162,6 +168,27 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
                       int64_t ldh)
 {
     return hdc_encode_tiled(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, H, ldh, 0);
+}
+
+hdc_status hdc_shift_projection(void *stream, const int8_t *P, int32_t D, int32_t F, int64_t ldp, int8_t *out,
+                                int64_t ldo)
+{
+    if (D <= 0 || F <= 0)
+        return HDC_ERR_INVALID;
+    if (F > kMaxF)
+        return HDC_ERR_UNSUPPORTED;
+    if (!P || ldp < round_up(F, 64) || ldp % 16 || !aligned(P, 16))
+        return HDC_ERR_INVALID;
+    if (!out || ldo < round_up(F, 64) || ldo % 16 || !aligned(out, 16))
+        return HDC_ERR_INVALID;
+    if ((uint64_t)D * (uint64_t)ldo > (uint64_t)UINT32_MAX - (uint64_t)ldo)
+        return HDC_ERR_UNSUPPORTED;
+    // in place only with the same pitch: each unit is read and written by one thread
+    const uintptr_t p0 = (uintptr_t)P, p1 = p0 + (uintptr_t)((int64_t)D * ldp);
+    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)((int64_t)D * ldo);
+    if (o0 < p1 && p0 < o1 && !(o0 == p0 && ldo == ldp))
+        return HDC_ERR_INVALID;
+    return from_hip(launch_shift_projection(P, D, F, ldp, out, ldo, (hipStream_t)stream));
 }
 
 size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K)

@@ -153,6 +153,8 @@ static hipError_t launch_dma(const EncodeArgs &a, int variant, hipStream_t st)
             }
         }
     }
+    if (a.poff && (!shift_tile(KS, KT) || variant == TV_DMA_1X1))
+        return hipErrorInvalidValue;   // the shifted projection: shift_tile shapes only
     if constexpr (big_tile(KS, KT)) {
         if (variant != TV_DMA_1X1)
             return launch_one<C_I8, 0, 2, KS, KT, MODE, true, 2>(a, st);
@@ -169,7 +171,10 @@ static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStr
 {
     const int v = tile.variant;
     if constexpr (CT == C_I8 && XF == 0) {
-        if (a.x_type == X_INT8 && (v == TV_AUTO || v == TV_DMA_2X2 || v == TV_DMA_1X1 || v == TV_DMA_2X3)) {
+        const bool dma = a.x_type == X_INT8 && (v == TV_AUTO || v == TV_DMA_2X2 || v == TV_DMA_1X1 || v == TV_DMA_2X3);
+        if (a.poff && !dma)   // the shifted projection runs on direct staging only
+            return hipErrorInvalidValue;
+        if (dma) {
             if (mode == M_ENCODE)
                 return launch_dma<KS, 1, M_ENCODE>(a, v, st);
             const int kt = class_tiles(a.K);

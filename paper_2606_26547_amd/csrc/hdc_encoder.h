@@ -173,6 +173,39 @@ struct Encoder {
         }
     }
 
+    // Start of chain 0 of each query tile on the int8 path: with the
+    // shifted projection (weights p + 1 in {0, 2}, poff set) the MFMAs add
+    // sum_i x_i (p_i + 1) = y + sum_i x_i, so the chain starts from minus
+    // the query's feature sum and ends at y exactly (integer arithmetic);
+    // otherwise from 0.  Lane l holds half of every K step of query l % 32
+    // (features past F are zero in xr); the two halves are added across the
+    // lane pair.  Shifted weights are mostly zero bits: the matrix cores
+    // switch far fewer of them than on +-1 (0x01 / 0xFF) and hold a higher
+    // clock under full load.  Only the shapes of shift_tile take the
+    // shifted projection; the others start from 0.
+    static constexpr bool kShift = CT == C_I8 && DMA && QT == 2 && shift_tile(KS, KT);
+    static __device__ __forceinline__ void shift_start(acc_t (&x0)[QT], const xfrag (&xr)[QT][KS], int poff)
+    {
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt) {
+            if constexpr (kShift) {
+                int s = 0;
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        s = __builtin_amdgcn_sdot4(xr[qt][k][e], 0x01010101, s, false);
+                s += __shfl_xor(s, 32);
+                const int v = poff ? -s : 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    x0[qt][i] = v;
+            } else {
+                x0[qt] = acc_t{};
+            }
+        }
+    }
+
     // ---------------------------------------------------------------- P
     // Thread t stages row t/8 of the chunk, pieces t%8 + 8m.
     static __device__ __forceinline__ void stage_load(uint4 (&pr)[MP], const EncodeArgs &a, int c,
@@ -306,13 +339,15 @@ struct Encoder {
     // One pass over a row tile (32 dimensions) in LDS: a fixed-length,
     // branch-free K loop with PD projection fragments in flight (steps past
     // the feature count read zero-filled or finite LDS against zero
-    // features).  Chain 0 of every query tile starts from the uint8
-    // correction 128 * sum_i p_i of its rows (0 otherwise).  The hook's work
-    // (the previous row tile's epilogue, the next chunk's loads) issues
-    // between the MFMAs, while the matrix core is busy.
+    // features).  Chain 0 of every query tile starts from x0 (minus the
+    // query's feature sum on the shifted projection, else 0), or from the
+    // uint8 correction 128 * sum_i p_i of its rows.  The hook's work (the
+    // previous row tile's epilogue, the next chunk's loads) issues between
+    // the MFMAs, while the matrix core is busy.
     template <class Hook>
     static __device__ __forceinline__ void tile_mma(Parts &part, const xfrag (&xr)[QT][KS], const lds_u8 *lp,
-                                                    const lds_i32 *lcs, bool colsum, int lane, const Hook &hook)
+                                                    const lds_i32 *lcs, bool colsum, int lane, const Hook &hook,
+                                                    const acc_t (&x0)[QT])
     {
         const int g = lane >> 5, row = lane & 31;
         const lds_u8 *base = lp + row * RSB + g * (KB / 2);
@@ -326,7 +361,7 @@ struct Encoder {
         for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
             for (int k = 0; k < KC; ++k)
-                part[qt][k] = acc_t{};
+                part[qt][k] = k == 0 ? x0[qt] : acc_t{};
         if constexpr (CT == C_I8) {
             if (colsum) {
 #pragma unroll
@@ -508,6 +543,7 @@ struct Encoder {
 
         xfrag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
+        const acc_t x0[QT] = {};
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -538,7 +574,7 @@ struct Encoder {
             stage_load(pr, a, c + 1, t, npc);
             if constexpr (MODE == M_CLASSIFY)
                 cr = class_load(a, more ? c + 1 : c, t);
-            tile_mma(cur, xr, lp[b], lcs[b], colsum, lane, hook);
+            tile_mma(cur, xr, lp[b], lcs[b], colsum, lane, hook, x0);
             if constexpr (MODE == M_CLASSIFY) {
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt)
@@ -688,6 +724,8 @@ struct Encoder {
 
         xfrag xr[QT][KS];
         load_x(xr, a, qbase, lane, ks_used);
+        acc_t x0[QT];
+        shift_start(x0, xr, a.poff);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -716,7 +754,7 @@ struct Encoder {
         };
         // one row-tile pass of the current chunk into cur
         auto pass = [&](int rt, Parts &cur, const auto &hook) {
-            tile_mma(cur, xr, lp(b) + rt * kDimChunk * RSB, nullptr, false, lane, hook);
+            tile_mma(cur, xr, lp(b) + rt * kDimChunk * RSB, nullptr, false, lane, hook, x0);
             read_cf(rt);
         };
         auto loads = [&](int c) {   // loads of chunk c + NBUF - 1 into the free stage

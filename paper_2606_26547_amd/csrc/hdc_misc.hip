@@ -238,4 +238,45 @@ hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t l
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Shifted projection: out[d][f] = P[d][f] + 1 (0 or 2 for +-1 weights) for
+// f < F, 0 in the pad columns.  One thread per 16-byte unit of the output;
+// a unit that starts below F reads the same unit of P (in bounds: ldp is a
+// multiple of 16 and at least F).  Bytes are added one at a time, so no
+// carry crosses into the next weight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_shift_projection(const int8_t *__restrict__ P, int D, int F, int64_t ldp,
+                                                          int8_t *__restrict__ out, int64_t ldo)
+{
+    const int64_t upr = ldo / 16;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)D * upr)
+        return;
+    const int64_t d = idx / upr;
+    const int f0 = (int)(idx % upr) * 16;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (f0 < F) {
+        const uint4 v = *(const uint4 *)(P + d * ldp + f0);
+        const uint32_t in[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = f0 + 4 * e + j;
+                const uint32_t b = f < F ? (((in[e] >> (8 * j)) + 1u) & 0xFFu) : 0u;
+                w[e] |= b << (8 * j);
+            }
+    }
+    *(uint4 *)(out + d * ldo + f0) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+hipError_t launch_shift_projection(const int8_t *P, int D, int F, int64_t ldp, int8_t *out, int64_t ldo,
+                                   hipStream_t st)
+{
+    const int64_t total = (int64_t)D * (ldo / 16);
+    hipLaunchKernelGGL(k_shift_projection, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, D, F, ldp,
+                       out, ldo);
+    return hipGetLastError();
+}
+
 }  // namespace hdc

@@ -18,6 +18,14 @@ int encoder_variants(int ct, int x_type, int width, int kt, bool classify, int *
 {
     const int ks = width / kstep_of(ct);
     int n = 0;
+    if (ct == C_I8S) {   // the shifted projection: the shift_tile shapes only
+        if (x_type != X_INT8 || !shift_tile(ks, kt))
+            return 0;
+        out[n++] = TV_DMA_2X2;
+        if (classify && big3_tile(ks, kt))
+            out[n++] = TV_DMA_2X3;
+        return n;
+    }
     if (ct == C_I8 && x_type == X_INT8) {
         if (big_tile(ks, kt))
             out[n++] = TV_DMA_2X2;
@@ -90,12 +98,14 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
     } else {
         if (!encoder_bucket(kind, x_type, ct, F, K))
             return -1;
-        if (x_type == X_FP32 ? ct == C_I8 : ct == C_F32)
+        if (x_type == X_FP32 ? (ct == C_I8 || ct == C_I8S) : ct == C_F32)
             return -1;
         const int wi = width_index(x_type, F);
         const int width = x_type == X_FP32 ? kF32Widths[wi] : kIntWidths[wi];
         n = encoder_variants(ct, x_type, width, encoder_kt(kind == KK_ENCODE ? M_ENCODE : M_CLASSIFY, K),
                              kind == KK_CLASSIFY, v);
+        if (n == 0)   // no kernel of this shape takes the pair
+            return -1;
     }
     for (int i = 0; i < n && i < cap; ++i)
         out[i] = v[i];
@@ -104,10 +114,10 @@ int tile_variants(int kind, int x_type, int ct, int F, int K, int *out, int cap)
 
 bool tile_compiled(int kind, int x_type, int ct, int F, int K, int variant)
 {
-    if (variant == 0)
-        return true;
     int v[8];
     const int n = tile_variants(kind, x_type, ct, F, K, v, 8);
+    if (variant == 0)
+        return n > 0;
     for (int i = 0; i < n; ++i)
         if (v[i] == variant)
             return true;

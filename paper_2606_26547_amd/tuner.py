@@ -76,10 +76,16 @@ def sweep_loop(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D:
 
 
 def time_config(cfg, X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, reps: int = 5,
-                tile: int = 0) -> float:
-    """Standalone queries/s of one configuration on batch X (median of reps)."""
+                tile: int = 0, shifted: torch.Tensor | None = None) -> float:
+    """Standalone queries/s of one configuration on batch X (median of
+    reps).  With ``shifted`` (the model's projection in the form
+    hdc.shift_projection writes), int8 configurations run as "int8shift"
+    where that has kernels; ``tile`` is the int8 configurations' kernel
+    shape."""
     d, k, s, t = cfg
-    prep = hdc.Prepared(Cw, D, t, s, d, k, tile=tile if t == "int8" else 0)
+    if t == "int8" and shifted is not None and hdc.shift_supported("classify", F, Cw.shape[0]):
+        t, P = "int8shift", shifted
+    prep = hdc.Prepared(Cw, D, t, s, d, k, tile=tile if t in ("int8", "int8shift") else 0)
     labels = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
     prep(X, F, P, labels)
     torch.cuda.synchronize()

@@ -264,6 +264,18 @@ def test_tile_variants_without_device(lib):
     assert variants(CLS, FP32, INT8, 64, 2) is None               # no fp32-feature int8 kernels
     assert variants(CLS, INT8, INT8, 2000, 26) is None            # beyond the compiled widths
     assert variants(SWP, FP32, FP32, 64, 2) is None
+    # the shifted projection: the two-query-tile direct shapes from 10 K steps
+    # (F > 256) and up to two class tiles, int8 features only
+    SHIFT = 6
+    assert variants(CLS, INT8, SHIFT, 617, 26) == [1, 5]
+    assert variants(CLS, INT8, SHIFT, 640, 64) == [1]
+    assert variants(ENC, INT8, SHIFT, 617, 0) == [1]
+    assert variants(ENC, INT8, SHIFT, 300, 0) == [1]
+    assert variants(CLS, INT8, SHIFT, 256, 26) is None
+    assert variants(CLS, INT8, SHIFT, 617, 100) is None
+    assert variants(CLS, INT8, SHIFT, 1024, 10) is None
+    assert variants(CLS, UINT8, SHIFT, 617, 26) is None
+    assert variants(CLS, FP32, SHIFT, 64, 2) is None
     assert not hasattr(lib, "hdc_set_tile") and not hasattr(lib, "hdc_get_tile")
     p, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
     fake = C.c_void_p(1 << 20)
@@ -281,6 +293,17 @@ def test_tile_variants_without_device(lib):
                                      fake, None, fake, 1 << 20, None, 0, 1) == 2   # 2x2 with four class tiles
     assert lib.hdc_classify_prepared(None, fake, INT8, 0, 617, 640, fake, 1024, 640, INT8, Dims(0, 1024, 1), 100,
                                      fake, None, fake, 1 << 20, None, 0, 2) == 0
+    # shifted projection: shapes it has no kernel for are refused, tile 0 included
+    assert lib.hdc_classify_prepared(None, fake, INT8, 4, 617, 640, fake, 1024, 640, SHIFT, Dims(0, 1024, 1), 100,
+                                     fake, None, fake, 1 << 20, None, 0, 0) == 2
+    assert lib.hdc_classify_prepared(None, fake, INT8, 4, 617, 640, fake, 1024, 640, SHIFT, Dims(0, 1024, 1), 26,
+                                     fake, None, fake, 1 << 20, None, 0, 2) == 2   # 1x1: not taken
+    assert lib.hdc_classify_prepared(None, fake, UINT8, 4, 617, 640, fake, 1024, 640, SHIFT, Dims(0, 1024, 1), 26,
+                                     fake, None, fake, 1 << 20, None, 0, 0) == 2
+    assert lib.hdc_encode_tiled(None, fake, INT8, 4, 200, 256, fake, 1024, 256, SHIFT, Dims(0, 1024, 1), fake,
+                                16, 0) == 2
+    assert lib.hdc_classify_prepared(None, fake, INT8, 0, 617, 640, fake, 1024, 640, SHIFT, Dims(0, 1024, 1), 26,
+                                     fake, None, fake, 1 << 20, None, 0, 5) == 0
 
 
 

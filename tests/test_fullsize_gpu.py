@@ -106,9 +106,9 @@ def speech_batch(hdc):
 @pytest.mark.parametrize("cfg", [(10240, 1, 0), (8192, 2, 0)], ids=str)
 def test_headline_shape_every_tile_sampled(hdc, speech_batch, cfg):
     """617 features, 26 classes, D = 10240, a 2^18-query batch (the batch the
-    benchmark times), every compiled tile variant of the bucket; 2048
-    sampled rows (including the first and last tiles) against the oracle,
-    labels and distances."""
+    benchmark times), every compiled tile variant of the bucket, on the +-1
+    projection and on the shifted one; 2048 sampled rows (including the
+    first and last tiles) against the oracle, labels and distances."""
     ds, Xq, yq, Cw = speech_batch
     d_trunc, stride, start = cfg
     F, D, K = ds.F, ds.D, ds.K
@@ -117,14 +117,15 @@ def test_headline_shape_every_tile_sampled(hdc, speech_batch, cfg):
     rows = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n), g.choice(n, 1920, replace=False)]))
     lref, dref = O.classify(Xq[rows], ds.P, Cw, "int8", start, d_trunc, stride, with_dists=True)
     Xd, Pd = hdc.pad_cols(Xq), hdc.pad_cols(ds.P)
+    Ps = hdc.shift_projection(Pd, F)
     Cd = torch.as_tensor(Cw.view(np.int64)).cuda()
-    variants = hdc.tile_variants("classify", "int8", "int8", F, K)
-    assert variants
-    prep = hdc.Prepared(Cd, D, "int8", start, d_trunc, stride)
-    for v in variants:
-        say("headline shape", cfg, "variant", v)
-        prep.tile = v
-        lab, dists = prep(Xd, F, Pd, with_dists=True)
+    runs = [("int8", v, Pd) for v in hdc.tile_variants("classify", "int8", "int8", F, K)]
+    runs += [("int8shift", v, Ps) for v in hdc.tile_variants("classify", "int8", "int8shift", F, K)]
+    assert len(runs) >= 4
+    for form, v, P_ in runs:
+        say("headline shape", cfg, form, "variant", v)
+        prep = hdc.Prepared(Cd, D, form, start, d_trunc, stride, tile=v)
+        lab, dists = prep(Xd, F, P_, with_dists=True)
         torch.cuda.synchronize()
         assert np.array_equal(lab.cpu().numpy()[rows], lref), v
         assert np.array_equal(dists.cpu().numpy()[rows], dref), v

@@ -14,8 +14,10 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // CH independent accumulator chains per wave; the operands are random
-// bytes loaded once.  One MFMA = 32 x 32 x 32 multiply-adds = 65536 ops.
-template <int CH, int WPS>
+// bytes loaded once (SH: the A operand's bytes reduced to 0 or 2, the
+// shifted projection weights' statistics).  One MFMA = 32 x 32 x 32
+// multiply-adds = 65536 ops.
+template <int CH, int WPS, bool SH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS))) void k_mfma(const v4i *src, int *out,
                                                                                           int iters)
 {
@@ -24,6 +26,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS))) void
     for (int i = 0; i < 4; ++i) {
         a[i] = src[(t + 97 * i) & 65535];
         b[i] = src[(t * 7 + 31 * i) & 65535];
+        if (SH)
+            a[i] = (a[i] & 0x01010101) << 1;
     }
     v16i c[CH];
     for (int j = 0; j < CH; ++j)
@@ -87,7 +91,7 @@ double time_ms(F launch, int reps)
     return hipGetLastError() == hipSuccess ? ms / reps : -1.0;
 }
 
-template <int CH, int WPS>
+template <int CH, int WPS, bool SH>
 double mfma_rate(int blocks_per_cu, int reps)
 {
     int dev = 0, cus = 0;
@@ -105,8 +109,8 @@ double mfma_rate(int blocks_per_cu, int reps)
     }
     hipLaunchKernelGGL(k_fill, dim3(256), dim3(256), 0, 0, (uint32_t *)src, (size_t)65536 * 4);
     const int iters = 4096 / CH;
-    const double ms = time_ms([&] { hipLaunchKernelGGL((k_mfma<CH, WPS>), dim3(blocks), dim3(256), 0, 0, src, out,
-                                                       iters); }, reps);
+    const double ms = time_ms([&] { hipLaunchKernelGGL((k_mfma<CH, WPS, SH>), dim3(blocks), dim3(256), 0, 0, src,
+                                                       out, iters); }, reps);
     (void)hipFree(src);
     (void)hipFree(out);
     if (ms <= 0)
@@ -121,23 +125,36 @@ extern "C" {
 // Sustained int8 matrix-core rate in TOP/s (1e12 integer ops per second) of
 // a loop of v_mfma_i32_32x32x32_i8 on random operands: `chains` (1, 2, 4
 // or 8) independent accumulators per wave, one or two waves per SIMD.
-double hdc_ceiling_mfma_i8(int chains, int waves_per_simd, int reps)
+template <bool SH>
+double mfma_i8(int chains, int waves_per_simd, int reps)
 {
     const int b = waves_per_simd == 2 ? 2 : 1;
     if (waves_per_simd == 2) {
         switch (chains) {
-        case 2: return mfma_rate<2, 2>(b, reps);
-        case 4: return mfma_rate<4, 2>(b, reps);
+        case 2: return mfma_rate<2, 2, SH>(b, reps);
+        case 4: return mfma_rate<4, 2, SH>(b, reps);
         }
         return -1.0;
     }
     switch (chains) {
-    case 1: return mfma_rate<1, 1>(b, reps);
-    case 2: return mfma_rate<2, 1>(b, reps);
-    case 4: return mfma_rate<4, 1>(b, reps);
-    case 8: return mfma_rate<8, 1>(b, reps);
+    case 1: return mfma_rate<1, 1, SH>(b, reps);
+    case 2: return mfma_rate<2, 1, SH>(b, reps);
+    case 4: return mfma_rate<4, 1, SH>(b, reps);
+    case 8: return mfma_rate<8, 1, SH>(b, reps);
     }
     return -1.0;
+}
+
+double hdc_ceiling_mfma_i8(int chains, int waves_per_simd, int reps)
+{
+    return mfma_i8<false>(chains, waves_per_simd, reps);
+}
+
+// The same loop with the A operand's bytes 0 or 2 (random), as the shifted
+// projection weights are, the B operand random bytes as before.
+double hdc_ceiling_mfma_i8_shifted(int chains, int waves_per_simd, int reps)
+{
+    return mfma_i8<true>(chains, waves_per_simd, reps);
 }
 
 // HBM read bandwidth in GB/s of a streaming kernel over `bytes` (rounded

@@ -53,10 +53,12 @@ def test_bench_uses_the_record_only_while_it_matches():
     while the kernel's sources still hash to it, and nothing otherwise."""
     import bench
     rec = json.load(open(os.path.join(bench.ROOT, "profiles", "traffic.json")))
-    e = rec["k_encode_classify_speech_b262144_dma_2x2"]
+    key = bench.traffic_key("dma_2x3", "int8shift")
+    assert key == "k_encode_classify_speech_b262144_dma_2x3_shift"
+    e = rec[key]
     current = traffic.sources_hash(e["sources"]) == e["sha256"]
-    v = bench.measured_traffic("k_encode_classify_speech_b262144_dma_2x2", e["batch"], e["tile"])
+    v = bench.measured_traffic(key, e["batch"], e["tile"])
     assert v == (e["bytes_per_launch"] if current else None)
-    assert bench.measured_traffic("k_encode_classify_speech_b262144_dma_2x2", e["batch"] + 1, e["tile"]) is None
-    assert bench.measured_traffic("k_encode_classify_speech_b262144_dma_2x2", e["batch"], "reg_qt1") is None
+    assert bench.measured_traffic(key, e["batch"] + 1, e["tile"]) is None
+    assert bench.measured_traffic(key, e["batch"], "reg_qt1") is None
     assert bench.measured_traffic("no such key", e["batch"], e["tile"]) is None

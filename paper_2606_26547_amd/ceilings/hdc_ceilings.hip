@@ -118,13 +118,6 @@ double mfma_rate(int blocks_per_cu, int reps)
     return (double)blocks * 4 * iters * 4 * CH * 65536.0 / (ms * 1e-3) / 1e12;
 }
 
-}  // namespace
-
-extern "C" {
-
-// Sustained int8 matrix-core rate in TOP/s (1e12 integer ops per second) of
-// a loop of v_mfma_i32_32x32x32_i8 on random operands: `chains` (1, 2, 4
-// or 8) independent accumulators per wave, one or two waves per SIMD.
 template <bool SH>
 double mfma_i8(int chains, int waves_per_simd, int reps)
 {
@@ -145,6 +138,13 @@ double mfma_i8(int chains, int waves_per_simd, int reps)
     return -1.0;
 }
 
+}  // namespace
+
+extern "C" {
+
+// Sustained int8 matrix-core rate in TOP/s (1e12 integer ops per second) of
+// a loop of v_mfma_i32_32x32x32_i8 on random operands: `chains` (1, 2, 4
+// or 8) independent accumulators per wave, one or two waves per SIMD.
 double hdc_ceiling_mfma_i8(int chains, int waves_per_simd, int reps)
 {
     return mfma_i8<false>(chains, waves_per_simd, reps);

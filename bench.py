@@ -223,10 +223,11 @@ def main():
     ws_b = torch.empty(hdc.lib().hdc_bundle_workspace_bytes(Xtr.shape[0], D, K), dtype=torch.uint8, device=dev)
     Htr = torch.zeros((Xtr.shape[0], hdc.words(D)), dtype=torch.int64, device=dev)
 
-    tiles_in_use = {"encode": 0}
+    tiles_in_use = {"encode": 0, "encode_form": "int8"}
 
     def train():
-        hdc.encode(Xtr, F, Pd, D, "int8", out=Htr, tile=tiles_in_use["encode"])
+        form = tiles_in_use["encode_form"]
+        hdc.encode(Xtr, F, Ps if form == "int8shift" else Pd, D, form, out=Htr, tile=tiles_in_use["encode"])
         return hdc.bundle(Htr, D, ytr, K, ws_b)
 
     Cw, _ = train()
@@ -274,7 +275,12 @@ def main():
     if args.classify_tile:
         cls_tile_id = {v: k for k, v in hdc.TILE_NAMES["classify"].items()}[args.classify_tile]
     P_cls = Ps if cls_form == "int8shift" else Pd
-    tiles_in_use["encode"] = table.get("encode", "int8", "int8", F, 1)
+    # the training encode takes the classifier's projection form (the
+    # shifted one with its built-in 2x2 shape)
+    if cls_form == "int8shift" and hdc.shift_supported("encode", F, 1):
+        tiles_in_use.update(encode=0, encode_form="int8shift")
+    else:
+        tiles_in_use["encode"] = table.get("encode", "int8", "int8", F, 1)
     sweep_tile = table.get("sweep", "int8", "int8", F, K)
     cls_tile = hdc.TILE_NAMES["classify"][cls_tile_id or hdc.tile_variants("classify", "int8", cls_form, F, K)[0]]
     log("tiles (%.1fs): %s" % (time.time() - t0, {c.shape.kind: (c.chosen_name, {k: round(v, 3) for k, v in
@@ -330,6 +336,7 @@ def main():
         ms_train, _, _ = event_loop(train, 5, 1)
         _, ms_bundle_tr, _ = event_loop(lambda: hdc.bundle(Htr, D, ytr, K, ws_b), 20, 3)
         out["train"] = {"ms": ms_train, "n_train": int(Xtr.shape[0]), "bundle_ms": ms_bundle_tr,
+                        "encode_form": tiles_in_use["encode_form"],
                         "note": "encode of the training set + majority bundle (bundle_ms: the bundle alone, "
                                 "device time)"}
     if want("bundle"):

@@ -889,7 +889,8 @@ def serving(args, dev, dg, hdc, tuner, torch):
         res = tuner.sweep(hdc.pad_cols(Xv, dev), m.F, torch.as_tensor(yv).to(dev), m.P, m.D, m.C, grid,
                           tile=SWEEP_SHARED)
         best, plain = tuner.select_tuned(res, (m.D, 1, 0, "int8"), 1.0, max_timed=6,
-                                         timer=lambda c, m=m, Xt=Xt: tuner.time_config(c, Xt, m.F, m.P, m.D, m.C))
+                                         timer=lambda c, m=m, Xt=Xt: tuner.time_config(c, Xt, m.F, m.P, m.D, m.C,
+                                                                                       shifted=m.Ps))
         m.set_tuned(best.cfg)
         tuned_cfgs.append({"F": m.F, "K": m.K, "D": m.D, "tuned": list(best.cfg),
                            "acc_plain": plain.accuracy, "acc_tuned": best.accuracy,

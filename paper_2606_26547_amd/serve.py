@@ -201,23 +201,23 @@ class GpuExecutor:
             from . import autotune as AT
             shapes, seen = [], set()
             for i, m in enumerate(self.models):
-                for sh in [AT.Shape("classify", m.F, m.K, m.D, 2048)] + \
+                for sh in [AT.Shape("classify", m.F, m.K, m.D, 2048, compute=m.plain.compute)] + \
                         ([AT.Shape("sweep", m.F, m.K, m.D, 512, cfgs=job_cfgs(i))] if job_cfgs else []):
-                    key = (sh.kind, sh.F, sh.K, sh.D)
+                    key = (sh.kind, sh.F, sh.K, sh.D, sh.compute)
                     if key not in seen:
                         seen.add(key)
                         shapes.append(sh)
             choices = AT.autotune(shapes, reps=3)
             table = AT.TileTable.from_choices(choices)
             for m in self.models:
-                m.plain.tile = table.get("classify", "int8", "int8", m.F, m.K)
-                if m.tuned.compute == "int8":
+                m.plain.tile = table.get("classify", "int8", m.plain.compute, m.F, m.K)
+                if m.tuned.compute == m.plain.compute:
                     m.tuned.tile = m.plain.tile
                 m.sweep_tile = table.get("sweep", "int8", "int8", m.F, m.K)
         for i, m in enumerate(self.models):
             X = torch.zeros((64, m.P.shape[1]), dtype=torch.int8, device=self.dev)
-            m.plain(X, m.F, m.P)
-            m.tuned(X, m.F, m.P)
+            m.plain(X, m.F, m.plain.P)
+            m.tuned(X, m.F, m.tuned.P)
             if job_cfgs is not None:
                 y = torch.zeros(64, dtype=torch.int32, device=self.dev)
                 hdc.eval_configs(X, m.F, y, m.P, m.D, m.C, job_cfgs(i), ws=m.sweep_ws,
@@ -295,7 +295,7 @@ class GpuExecutor:
             dx = slot["dx"][:b.n * ld].view(b.n, ld)
             dx.copy_(hxt, non_blocking=True)
             prep = m.tuned if r0.tuned else m.plain
-            prep(dx, m.F, m.P, slot["dl"][:b.n])
+            prep(dx, m.F, prep.P, slot["dl"][:b.n])
             slot["hl"][:b.n].copy_(slot["dl"][:b.n], non_blocking=True)
             slot["ev"].record(stream)
         b.handle = ("infer", slot)
@@ -341,26 +341,38 @@ class ResidentModel:
         from . import hdc
         self.D, self.F, self.K = int(P.shape[0]), int(P.shape[1]), int(K)
         self.P = hdc.pad_cols(P, device)
+        # int8 configurations classify on the shifted projection (weights
+        # p + 1, the same labels) where its kernels take the model's shape
+        self.Ps = hdc.shift_projection(self.P, self.F) if hdc.shift_supported("classify", self.F, self.K) else None
         Xtr = hdc.pad_cols(X_train, device)
         H = hdc.encode(Xtr, self.F, self.P, self.D)
         self.C, _ = hdc.bundle(H, self.D, torch.as_tensor(y_train, dtype=torch.int32).to(device), self.K)
         del H, Xtr
-        self.plain = hdc.Prepared(self.C, self.D, "int8")
+        self.plain = self.prepared((self.D, 1, 0, "int8"))
         self.sweep_tile = 0       # work-item shape of configuration jobs (0: built-in)
         self.tuned_cfg = tuned_cfg or (self.D, 1, 0, "int8")
-        d, k, s, t = self.tuned_cfg
-        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k)
+        self.tuned = self.prepared(self.tuned_cfg)
         # workspace of configuration jobs (up to max_job_cfgs configurations)
         need = int(hdc.lib().hdc_eval_configs_workspace_bytes(max_job_cfgs, self.F, self.D, self.K))
         self.sweep_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
-        self.resident_bytes = (self.P.numel() + self.C.numel() * 8 + self.plain.ws.numel()
-                               + self.tuned.ws.numel() + self.sweep_ws.numel())
+        self.resident_bytes = (self.P.numel() + (self.Ps.numel() if self.Ps is not None else 0)
+                               + self.C.numel() * 8 + self.plain.ws.numel() + self.tuned.ws.numel()
+                               + self.sweep_ws.numel())
 
-    def set_tuned(self, cfg):
+    def prepared(self, cfg, tile: int = 0):
+        """The prepared classifier of configuration ``cfg``; its attribute P
+        is the projection it reads (the shifted one for int8 where the model
+        has it).  ``tile`` applies to int8 configurations."""
         from . import hdc
         d, k, s, t = cfg
+        shifted = t == "int8" and self.Ps is not None
+        prep = hdc.Prepared(self.C, self.D, "int8shift" if shifted else t, s, d, k, tile=tile if t == "int8" else 0)
+        prep.P = self.Ps if shifted else self.P
+        return prep
+
+    def set_tuned(self, cfg):
         self.tuned_cfg = cfg
-        self.tuned = hdc.Prepared(self.C, self.D, t, s, d, k, tile=self.plain.tile if t == "int8" else 0)
+        self.tuned = self.prepared(cfg, tile=self.plain.tile)
 
 
 # ---------------------------------------------------------------- server

@@ -167,7 +167,7 @@ def test_largest_serving_model(hdc, big_model, tuned):
     prep = m.tuned if tuned else m.plain
     d, k, s, t = cfg
     lref, dref = O.classify(Xq, src.P, Cref, t, s, d, k, with_dists=True)
-    lab, dists = prep(hdc.pad_cols(Xq), src.F, m.P, with_dists=True)
+    lab, dists = prep(hdc.pad_cols(Xq), src.F, prep.P, with_dists=True)
     torch.cuda.synchronize()
     assert np.array_equal(dists.cpu().numpy(), dref)
     assert np.array_equal(lab.cpu().numpy(), lref)

@@ -36,10 +36,11 @@ struct Encoder {
     // straight into LDS (global_load_lds, 16 bytes per lane), three stages
     // deep.  Each load fills 1 KiB of LDS contiguously, so a stage is NIW
     // loads per wave and the units past the 32 rows land in the stage's
-    // slack.  The rows are copied as they are: int8 +-1 for the int8 path
-    // (int8 features: uint8 ones would need column sums), or rows already
-    // in the compute type (bf16 / E4M3 +-1.0, built once by the caller) for
-    // those paths, which take either feature type.
+    // slack.  The rows are copied as they are: int8 +-1 for the int8 path,
+    // or the shifted weights 0 / 2 with poff set (int8 features: uint8 ones
+    // would need column sums), or rows already in the compute type (bf16 /
+    // E4M3 +-1.0, built once by the caller) for those paths, which take
+    // either feature type.
     // A chunk is RT row tiles of 32 dimensions (RT > 1 with DMA staging
     // only; three row tiles classify only, in two stages); its class operand
     // is RT * KT KiB.

@@ -210,9 +210,11 @@ def main():
     log("data ready in %.1fs: F=%d K=%d D=%d batch=%d" % (time.time() - t0, F, K, D, N))
 
     Pd = hdc.pad_cols(ds.P, dev)
-    # the model's projection in the shifted form (made once with the model;
-    # int8 classification on it gives the same labels and distances)
+    # the model's projection in the shifted forms (made once with the model;
+    # int8 / E4M3 classification on them gives the same labels and distances)
     Ps = hdc.shift_projection(Pd, F)
+    shifted_P = {t: hdc.shift_projection(Pd, F, compute=ts) for t, ts in hdc.SHIFTED.items()
+                 if hdc.shift_supported("classify", F, K, ts)}
     Xtr = hdc.pad_cols(ds.X_train, dev)
     ytr = torch.as_tensor(ds.y_train).to(dev)
     Xqd = hdc.pad_cols(Xq, dev)
@@ -374,7 +376,7 @@ def main():
         best, plain_r = tuner.select_tuned(
             grid_res, (D, 1, 0, "int8"), 1.0,
             timer=lambda c: tuner.time_config(c, Xqd, F, Pd, D, Cw, tile=cls_tile_id,
-                                              shifted=Ps if cls_form == "int8shift" else None))
+                                              shifted=shifted_P if cls_form == "int8shift" else None))
         pc_ms, sh_ms = sweep_ms_by[0], sweep_ms_by[SWEEP_SHARED]
         out["sweep"] = {"slots": len(slots), "distinct": len(set(slots)), "queries": int(Xsd.shape[0]),
                         "tile": hdc.TILE_NAMES["sweep"].get(sweep_tile, "built-in"),
@@ -396,7 +398,9 @@ def main():
                                                     "search is VALU work and not counted"}}
         d, k, s, tdt = best.cfg
         t_form = cls_form if tdt == "int8" else tdt
-        P_t = Ps if t_form == "int8shift" else Pd
+        if tdt == "fp8" and cls_form == "int8shift" and "fp8" in shifted_P:
+            t_form = "fp8shift"
+        P_t = shifted_P.get(tdt, Pd) if t_form.endswith("shift") else Pd
         tuned = hdc.Prepared(Cw, D, t_form, s, d, k, tile=cls_tile_id if tdt == "int8" else 0)
         tl = torch.empty(N, dtype=torch.int32, device=dev)
         ms_t, ms_tk, _ = event_loop(lambda: tuned(Xqd, F, P_t, tl), args.steps, args.warmup)
@@ -824,6 +828,14 @@ def ladder(dev, dg, hdc, tuner, torch, np_, event_loop, ds, Xte, Pd, Cw, Xqd, F,
         _, ms, _ = event_loop(lambda: prep(Xqd, F, Pd, lb), 5, 1)
         sp[t] = {"flip_rate": flip_rate(H, Hx, D), "accuracy": float((lab == yte).float().mean().item()),
                  "ms_batch": ms, "queries_per_s": Xqd.shape[0] / (ms / 1e3)}
+        ts = hdc.SHIFTED.get(t)
+        if ts and hdc.shift_supported("classify", F, Cw.shape[0], ts):
+            # the same rung on the shifted projection (identical labels)
+            Pt = hdc.shift_projection(Pd, F, compute=ts)
+            prep_s = hdc.Prepared(Cw, D, ts)
+            ls = torch.empty_like(lb)
+            _, ms_s, _ = event_loop(lambda: prep_s(Xqd, F, Pt, ls), 5, 1)
+            sp[t].update(ms_batch_shifted=ms_s, labels_equal_shifted=bool(torch.equal(ls, lb)))
     res["speech"] = sp
     log("ladder speech: %s" % {t: (round(v["flip_rate"], 5), round(v["accuracy"], 4), round(v["ms_batch"], 3))
                                for t, v in sp.items()})
@@ -890,7 +902,7 @@ def serving(args, dev, dg, hdc, tuner, torch):
                           tile=SWEEP_SHARED)
         best, plain = tuner.select_tuned(res, (m.D, 1, 0, "int8"), 1.0, max_timed=6,
                                          timer=lambda c, m=m, Xt=Xt: tuner.time_config(c, Xt, m.F, m.P, m.D, m.C,
-                                                                                       shifted=m.Ps))
+                                                                                       shifted=m.shifted))
         m.set_tuned(best.cfg)
         tuned_cfgs.append({"F": m.F, "K": m.K, "D": m.D, "tuned": list(best.cfg),
                            "acc_plain": plain.accuracy, "acc_tuned": best.accuracy,

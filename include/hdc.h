@@ -47,7 +47,9 @@
  *   projection gives HDC_ERR_UNSUPPORTED.  With compute HDC_INT8_SHIFTED,
  *   P is the shifted form written by hdc_shift_projection instead (columns
  *   [0, F) hold p + 1, i.e. 0 or 2); the results are those of HDC_INT8 on
- *   the +-1 projection it was made from.
+ *   the +-1 projection it was made from.  Likewise HDC_FP8_E4M3_SHIFTED
+ *   reads the E4M3 form (bytes 0x00 / 0x40) and gives the results of
+ *   HDC_FP8_E4M3.
  */
 #ifndef HDC_H
 #define HDC_H
@@ -86,12 +88,18 @@ typedef enum {
  *                                        weights p + 1 in {0, 2}, every sum
  *                                        started from minus the query's
  *                                        feature sum
+ *   HDC_INT8 / HDC_UINT8 -> HDC_FP8_E4M3_SHIFTED
+ *                                        the same bits as HDC_FP8_E4M3, on
+ *                                        the shifted projection in E4M3
+ *                                        bytes (0 / 2.0): E4M3 MFMA, every
+ *                                        sum started from minus the sum of
+ *                                        the query's rounded features
  *   HDC_FP32 -> HDC_FP32 / HDC_BF16 / HDC_FP8_E4M3   (F <= 256)
  * The reduced types round each feature to the compute type (round to nearest
  * even) and multiply by the exactly representable +-1 weights (Sec. 4.2
  * "Element Type Representation").  HDC_FP8_E4M3_SPLIT is a compute type
  * only (never a feature type) and is not a sweep configuration dtype; so
- * is HDC_INT8_SHIFTED. */
+ * are HDC_INT8_SHIFTED and HDC_FP8_E4M3_SHIFTED. */
 typedef enum {
     HDC_INT8 = 0,
     HDC_UINT8 = 1,
@@ -99,7 +107,8 @@ typedef enum {
     HDC_FP8_E4M3 = 3,
     HDC_FP32 = 4,
     HDC_FP8_E4M3_SPLIT = 5,
-    HDC_INT8_SHIFTED = 6
+    HDC_INT8_SHIFTED = 6,
+    HDC_FP8_E4M3_SHIFTED = 7
 } hdc_dtype;
 
 typedef struct {
@@ -139,12 +148,14 @@ hdc_status hdc_encode_tiled(void *stream,
                             uint64_t *H, int64_t ldh, int32_t tile);
 
 /* ---------------------------------------------------------------------
- * hdc_shift_projection -- the projection in the form HDC_INT8_SHIFTED
- * reads: out[d][f] = P[d][f] + 1 for f < F (0 or 2 for +-1 weights) and 0
- * in the pad columns [F, ldo).  The encoding is unchanged (Sec. 2.2 Listing
- * 1; with x the features and p a row, sum_f x_f (p_f + 1) - sum_f x_f is
- * the same y); the shifted weights are mostly zero bits, which the matrix
- * cores run at a higher clock than +-1.  Made once per model.
+ * hdc_shift_projection -- the projection in the form a shifted compute
+ * type reads: out[d][f] = P[d][f] + 1 for f < F (0 or 2 for +-1 weights),
+ * as int8 (compute = HDC_INT8_SHIFTED) or as E4M3 bytes 0x00 / 0x40
+ * (compute = HDC_FP8_E4M3_SHIFTED), and 0 in the pad columns [F, ldo).  The
+ * encoding is unchanged (Sec. 2.2 Listing 1; with x the features and p a
+ * row, sum_f x_f (p_f + 1) - sum_f x_f is the same y); the shifted weights
+ * are mostly zero bits, which the matrix cores run at a higher clock than
+ * +-1.  Made once per model.  Another compute gives HDC_ERR_UNSUPPORTED.
  *   P    [D][ldp] int8, as for hdc_encode (+-1 in columns [0, F))
  *   out  [D][ldo] int8 output, ldo >= F rounded up to 64, a multiple of
  *        16, 16-byte aligned; D * ldo below 2^32 bytes.  out may be P
@@ -154,7 +165,7 @@ hdc_status hdc_encode_tiled(void *stream,
  * ------------------------------------------------------------------- */
 hdc_status hdc_shift_projection(void *stream,
                                 const int8_t *P, int32_t D, int32_t F, int64_t ldp,
-                                int8_t *out, int64_t ldo);
+                                hdc_dtype compute, int8_t *out, int64_t ldo);
 
 /* ---------------------------------------------------------------------
  * hdc_bundle -- class bundling (Sec. 2.1: same-class hypervectors are

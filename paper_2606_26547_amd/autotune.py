@@ -73,8 +73,8 @@ def _operands(sh: Shape, seed: int):
         X[:, :sh.F] = torch.randint(lo, hi, (sh.n, sh.F), dtype=torch.int16, device="cuda", generator=g).to(dt)
     P = torch.zeros((sh.D, ld), dtype=torch.int8, device="cuda")
     P[:, :sh.F] = (torch.randint(0, 2, (sh.D, sh.F), dtype=torch.int8, device="cuda", generator=g) * 2 - 1)
-    if sh.compute == "int8shift":
-        P = hdc.shift_projection(P, sh.F)
+    if sh.compute in ("int8shift", "fp8shift"):
+        P = hdc.shift_projection(P, sh.F, compute=sh.compute)
     C = torch.randint(-(1 << 62), 1 << 62, (sh.K, (sh.D + 63) // 64), dtype=torch.int64, device="cuda",
                       generator=g)
     if sh.D % 64:

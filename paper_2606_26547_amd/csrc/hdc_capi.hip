@@ -25,6 +25,11 @@ hipError_t launch_encode(const EncodeArgs &a, int compute, int mode, Tile tile, 
         b.poff = 1;
         return launch_encode_i8(b, mode, tile, st);
     }
+    case C_FP8H: {
+        EncodeArgs b = a;
+        b.poff = 1;
+        return launch_encode_fp8(b, mode, tile, st);
+    }
     }
     return hipErrorInvalidValue;
 }
@@ -58,6 +63,7 @@ int compute_of(hdc_dtype x, hdc_dtype c)
         if (c == HDC_FP8_E4M3) return C_FP8;
         if (c == HDC_FP8_E4M3_SPLIT) return C_FP8S;
         if (c == HDC_INT8_SHIFTED) return x == HDC_INT8 ? C_I8S : -1;
+        if (c == HDC_FP8_E4M3_SHIFTED) return C_FP8H;
         return -1;
     }
     if (x == HDC_FP32) {
@@ -170,11 +176,13 @@ hdc_status hdc_encode(void *stream, const void *X, hdc_dtype x_type, int64_t n, 
     return hdc_encode_tiled(stream, X, x_type, n, F, ldx, P, D, ldp, compute, dims, H, ldh, 0);
 }
 
-hdc_status hdc_shift_projection(void *stream, const int8_t *P, int32_t D, int32_t F, int64_t ldp, int8_t *out,
-                                int64_t ldo)
+hdc_status hdc_shift_projection(void *stream, const int8_t *P, int32_t D, int32_t F, int64_t ldp, hdc_dtype compute,
+                                int8_t *out, int64_t ldo)
 {
     if (D <= 0 || F <= 0)
         return HDC_ERR_INVALID;
+    if (compute != HDC_INT8_SHIFTED && compute != HDC_FP8_E4M3_SHIFTED)
+        return HDC_ERR_UNSUPPORTED;
     if (F > kMaxF)
         return HDC_ERR_UNSUPPORTED;
     if (!P || ldp < round_up(F, 64) || ldp % 16 || !aligned(P, 16))
@@ -188,7 +196,8 @@ hdc_status hdc_shift_projection(void *stream, const int8_t *P, int32_t D, int32_
     const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)((int64_t)D * ldo);
     if (o0 < p1 && p0 < o1 && !(o0 == p0 && ldo == ldp))
         return HDC_ERR_INVALID;
-    return from_hip(launch_shift_projection(P, D, F, ldp, out, ldo, (hipStream_t)stream));
+    return from_hip(launch_shift_projection(P, D, F, ldp, compute == HDC_FP8_E4M3_SHIFTED, out, ldo,
+                                            (hipStream_t)stream));
 }
 
 size_t hdc_bundle_workspace_bytes(int64_t n, int32_t nbits, int32_t K)

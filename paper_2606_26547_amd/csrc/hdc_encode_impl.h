@@ -185,6 +185,26 @@ static hipError_t launch_bucket(const EncodeArgs &a, int mode, Tile tile, hipStr
             return launch_dma<KS, 4, M_CLASSIFY>(a, v, st);
         }
     }
+    if constexpr (CT == C_FP8 && XF == 0) {
+        // E4M3 on the shifted projection (rows of E4M3 bytes 0 / 2.0, poff
+        // set): the direct-staged 2x2 shape, shift8_tile widths only
+        if (a.poff) {
+            if (v != TV_AUTO && v != TV_DMA_2X2)
+                return hipErrorInvalidValue;
+            if constexpr (shift8_tile(KS, 2)) {
+                if (mode == M_ENCODE)
+                    return launch_one<C_FP8, 0, 1, KS, 1, M_ENCODE, true, 1>(a, st);
+                const int kt = class_tiles(a.K);
+                if (kt == 1)
+                    return launch_one<C_FP8, 0, 1, KS, 1, M_CLASSIFY, true, 1>(a, st);
+                if (kt == 2)
+                    return launch_one<C_FP8, 0, 1, KS, 2, M_CLASSIFY, true, 1>(a, st);
+            }
+            return hipErrorInvalidValue;
+        }
+    }
+    if (a.poff)
+        return hipErrorInvalidValue;
     constexpr int QM = qt2_fits(CT, KS) ? 2 : 1;
     const int qt = (v == TV_REG_QT1 || QM == 1) ? 1 : 2;
     if (mode == M_ENCODE) {

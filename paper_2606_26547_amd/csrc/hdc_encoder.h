@@ -182,14 +182,28 @@ struct Encoder {
     // (features past F are zero in xr); the two halves are added across the
     // lane pair.  Shifted weights are mostly zero bits: the matrix cores
     // switch far fewer of them than on +-1 (0x01 / 0xFF) and hold a higher
-    // clock under full load.  Only the shapes of shift_tile take the
-    // shifted projection; the others start from 0.
-    static constexpr bool kShift = CT == C_I8 && DMA && QT == 2 && shift_tile(KS, KT);
+    // clock under full load.  The E4M3 path (weights 0 / 2.0) takes minus
+    // the sum of its rounded features from the matrix cores (an all -1.0
+    // operand against the query fragments; integers below 2^24, exact in
+    // fp32).  Only the shapes of shift_tile / shift8_tile take the shifted
+    // projection; the others start from 0.
+    static constexpr bool kShift = DMA && ((CT == C_I8 && QT == 2 && shift_tile(KS, KT)) ||
+                                           (CT == C_FP8 && shift8_tile(KS, KT)));
     static __device__ __forceinline__ void shift_start(acc_t (&x0)[QT], const xfrag (&xr)[QT][KS], int poff)
     {
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt) {
-            if constexpr (kShift) {
+            if constexpr (kShift && CT == C_FP8) {
+                const int m1 = poff ? (int)0xB8B8B8B8u : 0;   // E4M3 -1.0 bytes, or zeros
+                frag neg;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    neg[i] = m1;
+                x0[qt] = acc_t{};
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    mma(x0[qt], neg, xr[qt][k]);
+            } else if constexpr (kShift) {
                 int s = 0;
 #pragma unroll
                 for (int k = 0; k < KS; ++k)
@@ -727,6 +741,13 @@ struct Encoder {
         load_x(xr, a, qbase, lane, ks_used);
         acc_t x0[QT];
         shift_start(x0, xr, a.poff);
+        if constexpr (kShift && CT == C_FP8) {
+            // the E4M3 start values come from 16-pass MFMAs: wait states
+            // before anything reads them (as in the epilogue)
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll

@@ -10,11 +10,12 @@ namespace hdc {
 
 // Encoding compute type of a kernel instantiation.  C_FP8S is E4M3 on
 // integer features split into a multiple of 16 and a remainder in [0, 16)
-// (both exact in E4M3), two MFMAs per projection fragment.  C_I8S is the
-// int8 path on the shifted projection p + 1 in {0, 2} (int8 features, direct
-// staging only): its kernels are the int8 ones with EncodeArgs::poff set.
-enum Compute : int { C_I8 = 0, C_BF16 = 1, C_FP8 = 2, C_F32 = 3, C_FP8S = 4, C_I8S = 5 };
-constexpr int kComputeTypes = 6;
+// (both exact in E4M3), two MFMAs per projection fragment.  C_I8S and
+// C_FP8H are the int8 and E4M3 paths on the shifted projection p + 1 in
+// {0, 2} (byte features, direct staging only): their kernels are the int8
+// and E4M3 ones with EncodeArgs::poff set.
+enum Compute : int { C_I8 = 0, C_BF16 = 1, C_FP8 = 2, C_F32 = 3, C_FP8S = 4, C_I8S = 5, C_FP8H = 6 };
+constexpr int kComputeTypes = 7;
 
 // Feature storage type.
 enum XType : int { X_INT8 = 0, X_UINT8 = 1, X_FP32 = 2 };
@@ -135,10 +136,17 @@ constexpr bool big3_tile(int ks, int kt) { return ks <= 20 && kt == 1; }
 // 256) up, which run one wave per SIMD and have registers to spare for the
 // start values of their accumulators.
 constexpr bool shift_tile(int ks, int kt) { return ks >= 10 && big_tile(ks, kt); }
+// The E4M3 path on the shifted projection (C_FP8H): the direct-staged 2x2
+// shape from 5 to 10 K steps of 64 features (256 < F <= 640), up to two
+// class tiles.
+constexpr bool shift8_tile(int ks, int kt) { return ks >= 5 && ks <= 10 && kt <= 2; }
 // Two query tiles per wave fit beside the accumulators (register staging).
 constexpr bool qt2_fits(int ct, int ks) { return (ct == C_I8 && ks <= 16) || (ct == C_F32 && ks <= 64); }
 // K step (features per MFMA) of a compute type.
-constexpr int kstep_of(int ct) { return ct == C_I8 || ct == C_I8S ? 32 : (ct == C_FP8 || ct == C_FP8S) ? 64 : ct == C_BF16 ? 16 : 2; }
+constexpr int kstep_of(int ct)
+{
+    return ct == C_I8 || ct == C_I8S ? 32 : (ct == C_FP8 || ct == C_FP8S || ct == C_FP8H) ? 64 : ct == C_BF16 ? 16 : 2;
+}
 
 // Compiled feature widths of the encoder (integer features / fp32
 // features); a launch uses the smallest width >= F.
@@ -192,8 +200,8 @@ hipError_t launch_group_count(int mode, const uint64_t *H, int64_t n, int nbits,
 hipError_t launch_adc_argmax(const uint64_t *Q, int64_t n, int64_t ldq, const uint64_t *C, int K, int64_t ldc,
                              int start, int end, int stride, int res, int step, int floor_, int ceil_,
                              int32_t *label, int32_t *max_score, int32_t *scores, hipStream_t st);
-hipError_t launch_shift_projection(const int8_t *P, int D, int F, int64_t ldp, int8_t *out, int64_t ldo,
-                                   hipStream_t st);
+hipError_t launch_shift_projection(const int8_t *P, int D, int F, int64_t ldp, bool e4m3, int8_t *out,
+                                   int64_t ldo, hipStream_t st);
 hipError_t launch_gather_cols(const void *X, int elem, int64_t n, int64_t ldx, int start, int stride, int nf,
                               void *Y, int64_t ldy, hipStream_t st);
 hipError_t launch_level_quantize(const float *X, int64_t n, int F, int64_t ldx, const float *lo, const float *hi,

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_convert(const void *__restrict__ X, int
         const uint32_t b = ((const uint8_t *)X)[i * ldx + f];
         v = byte_value(b, 0, x_type == X_INT8);
     }
-    if (compute == C_FP8)
+    if (compute == C_FP8 || compute == C_FP8H)
         v = __builtin_amdgcn_cvt_f32_fp8((int)fp8x4(v, 0.f, 0.f, 0.f), 0);
     else if (compute == C_FP8S) {   // integer features: the two E4M3 parts, added back
         uint32_t hi, lo;
@@ -240,13 +240,14 @@ hipError_t launch_convert(const void *X, int x_type, int64_t n, int F, int64_t l
 
 // ---------------------------------------------------------------------------
 // Shifted projection: out[d][f] = P[d][f] + 1 (0 or 2 for +-1 weights) for
-// f < F, 0 in the pad columns.  One thread per 16-byte unit of the output;
-// a unit that starts below F reads the same unit of P (in bounds: ldp is a
-// multiple of 16 and at least F).  Bytes are added one at a time, so no
-// carry crosses into the next weight.
+// f < F, 0 in the pad columns; as E4M3 bytes (2.0 = 0x40, 0 = 0x00) when
+// e4m3 is set.  One thread per 16-byte unit of the output; a unit that
+// starts below F reads the same unit of P (in bounds: ldp is a multiple of
+// 16 and at least F).  Bytes are handled one at a time, so no carry
+// crosses into the next weight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_shift_projection(const int8_t *__restrict__ P, int D, int F, int64_t ldp,
-                                                          int8_t *__restrict__ out, int64_t ldo)
+                                                          bool e4m3, int8_t *__restrict__ out, int64_t ldo)
 {
     const int64_t upr = ldo / 16;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -263,19 +264,20 @@ __global__ __launch_bounds__(256) void k_shift_projection(const int8_t *__restri
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int f = f0 + 4 * e + j;
-                const uint32_t b = f < F ? (((in[e] >> (8 * j)) + 1u) & 0xFFu) : 0u;
+                const uint32_t s = ((in[e] >> (8 * j)) + 1u) & 0xFFu;   // p + 1
+                const uint32_t b = f >= F ? 0u : !e4m3 ? s : (s == 2u ? 0x40u : 0u);
                 w[e] |= b << (8 * j);
             }
     }
     *(uint4 *)(out + d * ldo + f0) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-hipError_t launch_shift_projection(const int8_t *P, int D, int F, int64_t ldp, int8_t *out, int64_t ldo,
-                                   hipStream_t st)
+hipError_t launch_shift_projection(const int8_t *P, int D, int F, int64_t ldp, bool e4m3, int8_t *out,
+                                   int64_t ldo, hipStream_t st)
 {
     const int64_t total = (int64_t)D * (ldo / 16);
     hipLaunchKernelGGL(k_shift_projection, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, D, F, ldp,
-                       out, ldo);
+                       e4m3, out, ldo);
     return hipGetLastError();
 }
 

@@ -18,6 +18,12 @@ int encoder_variants(int ct, int x_type, int width, int kt, bool classify, int *
 {
     const int ks = width / kstep_of(ct);
     int n = 0;
+    if (ct == C_FP8H) {   // E4M3 on the shifted projection: the direct 2x2 shape
+        if (x_type == X_FP32 || !shift8_tile(ks, kt))
+            return 0;
+        out[n++] = TV_DMA_2X2;
+        return n;
+    }
     if (ct == C_I8S) {   // the shifted projection: the shift_tile shapes only
         if (x_type != X_INT8 || !shift_tile(ks, kt))
             return 0;

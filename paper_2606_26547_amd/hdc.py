@@ -27,9 +27,11 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-INT8, UINT8, BF16, FP8_E4M3, FP32, FP8_SPLIT, INT8_SHIFTED = 0, 1, 2, 3, 4, 5, 6
+INT8, UINT8, BF16, FP8_E4M3, FP32, FP8_SPLIT, INT8_SHIFTED, FP8_SHIFTED = 0, 1, 2, 3, 4, 5, 6, 7
 DTYPE = {"int8": INT8, "uint8": UINT8, "bf16": BF16, "fp8": FP8_E4M3, "fp32": FP32, "fp8split": FP8_SPLIT,
-         "int8shift": INT8_SHIFTED}
+         "int8shift": INT8_SHIFTED, "fp8shift": FP8_SHIFTED}
+# the shifted compute type of each plain one (hdc_shift_projection)
+SHIFTED = {"int8": "int8shift", "fp8": "fp8shift"}
 STATUS = {0: "HDC_OK", 1: "HDC_ERR_INVALID", 2: "HDC_ERR_UNSUPPORTED", 3: "HDC_ERR_WORKSPACE",
           4: "HDC_ERR_DEVICE"}
 EXPORTS = ["hdc_status_string", "hdc_dims_count", "hdc_encode", "hdc_encode_tiled", "hdc_bundle_workspace_bytes",
@@ -117,7 +119,7 @@ _lib.hdc_adc_prepare.argtypes = [_p, _p, _i32, _i64, Dims, _p, _sz]
 _lib.hdc_adc_argmax_prepared.argtypes = [_p, _p, _i64, _i64, _i32, Dims, Adc, _p, _p, _p, _p, _sz]
 _lib.hdc_tile_variants.restype = _i32
 _lib.hdc_tile_variants.argtypes = [C.c_int, C.c_int, C.c_int, _i32, _i32, _p, _i32]
-_lib.hdc_shift_projection.argtypes = [_p, _p, _i32, _i32, _i64, _p, _i64]
+_lib.hdc_shift_projection.argtypes = [_p, _p, _i32, _i32, _i64, C.c_int, _p, _i64]
 _lib.hdc_feature_perforate.argtypes = [_p, _p, C.c_int, _i64, _i32, _i64, Dims, _p, _i64]
 _lib.hdc_level_quantize.argtypes = [_p, _p, _i64, _i32, _i64, _p, _p, _i32, _p, _i64]
 _lib.hdc_level_id_encode.argtypes = [_p, _p, _i64, _i32, _i64, _p, _i64, _p, _i32, _i64, _i32, _p, _i64]
@@ -196,20 +198,22 @@ def encode(X: torch.Tensor, F: int, P: torch.Tensor, D: int, compute="int8", sta
     return out
 
 
-def shift_supported(kind: str, F: int, K: int) -> bool:
-    """Whether compute "int8shift" (int8 features) has kernels for the
-    (kind, F, K) bucket."""
+def shift_supported(kind: str, F: int, K: int, compute: str = "int8shift", x_type: str = "int8") -> bool:
+    """Whether a shifted compute type ("int8shift", "fp8shift") has kernels
+    for the (kind, x_type, F, K) bucket."""
     buf = (C.c_int32 * 8)()
-    return _lib.hdc_tile_variants(KERNEL[kind], INT8, INT8_SHIFTED, F, K, buf, 8) > 0
+    return _lib.hdc_tile_variants(KERNEL[kind], DTYPE[x_type], DTYPE[compute], F, K, buf, 8) > 0
 
 
-def shift_projection(P: torch.Tensor, F: int, out: torch.Tensor | None = None) -> torch.Tensor:
-    """hdc_shift_projection: the projection as compute "int8shift" reads it
-    (p + 1 in the F feature columns, 0 in the pad columns), same layout."""
+def shift_projection(P: torch.Tensor, F: int, out: torch.Tensor | None = None,
+                     compute: str = "int8shift") -> torch.Tensor:
+    """hdc_shift_projection: the projection as the shifted compute type
+    reads it (p + 1 in the F feature columns, as int8 for "int8shift" or
+    E4M3 bytes for "fp8shift"; 0 in the pad columns), same layout."""
     if out is None:
         out = torch.empty_like(P)
-    _check(_lib.hdc_shift_projection(_stream(), _ptr(P), P.shape[0], F, P.shape[1], _ptr(out), out.shape[1]),
-           "hdc_shift_projection")
+    _check(_lib.hdc_shift_projection(_stream(), _ptr(P), P.shape[0], F, P.shape[1], DTYPE[compute], _ptr(out),
+                                     out.shape[1]), "hdc_shift_projection")
     return out
 
 

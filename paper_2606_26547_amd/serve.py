@@ -341,9 +341,11 @@ class ResidentModel:
         from . import hdc
         self.D, self.F, self.K = int(P.shape[0]), int(P.shape[1]), int(K)
         self.P = hdc.pad_cols(P, device)
-        # int8 configurations classify on the shifted projection (weights
-        # p + 1, the same labels) where its kernels take the model's shape
-        self.Ps = hdc.shift_projection(self.P, self.F) if hdc.shift_supported("classify", self.F, self.K) else None
+        # int8 and E4M3 configurations classify on the shifted projection
+        # (weights p + 1, the same labels) where its kernels take the
+        # model's shape: compute type -> that form of the projection
+        self.shifted = {t: hdc.shift_projection(self.P, self.F, compute=ts) for t, ts in hdc.SHIFTED.items()
+                        if hdc.shift_supported("classify", self.F, self.K, ts)}
         Xtr = hdc.pad_cols(X_train, device)
         H = hdc.encode(Xtr, self.F, self.P, self.D)
         self.C, _ = hdc.bundle(H, self.D, torch.as_tensor(y_train, dtype=torch.int32).to(device), self.K)
@@ -355,19 +357,22 @@ class ResidentModel:
         # workspace of configuration jobs (up to max_job_cfgs configurations)
         need = int(hdc.lib().hdc_eval_configs_workspace_bytes(max_job_cfgs, self.F, self.D, self.K))
         self.sweep_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
-        self.resident_bytes = (self.P.numel() + (self.Ps.numel() if self.Ps is not None else 0)
+        self.resident_bytes = (self.P.numel() + sum(p.numel() for p in self.shifted.values())
                                + self.C.numel() * 8 + self.plain.ws.numel() + self.tuned.ws.numel()
                                + self.sweep_ws.numel())
 
     def prepared(self, cfg, tile: int = 0):
         """The prepared classifier of configuration ``cfg``; its attribute P
-        is the projection it reads (the shifted one for int8 where the model
-        has it).  ``tile`` applies to int8 configurations."""
+        is the projection it reads (the shifted one for int8 / E4M3 where the
+        model has it).  ``tile`` applies to int8 configurations."""
         from . import hdc
         d, k, s, t = cfg
-        shifted = t == "int8" and self.Ps is not None
-        prep = hdc.Prepared(self.C, self.D, "int8shift" if shifted else t, s, d, k, tile=tile if t == "int8" else 0)
-        prep.P = self.Ps if shifted else self.P
+        if t in self.shifted:
+            prep = hdc.Prepared(self.C, self.D, hdc.SHIFTED[t], s, d, k, tile=tile if t == "int8" else 0)
+            prep.P = self.shifted[t]
+        else:
+            prep = hdc.Prepared(self.C, self.D, t, s, d, k, tile=tile if t == "int8" else 0)
+            prep.P = self.P
         return prep
 
     def set_tuned(self, cfg):

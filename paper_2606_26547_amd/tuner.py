@@ -76,16 +76,17 @@ def sweep_loop(X: torch.Tensor, F: int, truth: torch.Tensor, P: torch.Tensor, D:
 
 
 def time_config(cfg, X: torch.Tensor, F: int, P: torch.Tensor, D: int, Cw: torch.Tensor, reps: int = 5,
-                tile: int = 0, shifted: torch.Tensor | None = None) -> float:
+                tile: int = 0, shifted: dict | None = None) -> float:
     """Standalone queries/s of one configuration on batch X (median of
-    reps).  With ``shifted`` (the model's projection in the form
-    hdc.shift_projection writes), int8 configurations run as "int8shift"
-    where that has kernels; ``tile`` is the int8 configurations' kernel
-    shape."""
+    reps).  ``shifted`` maps a compute type ("int8", "fp8") to the model's
+    projection in the shifted form hdc.shift_projection writes for it; such
+    configurations run on it as "int8shift" / "fp8shift".  ``tile`` is the
+    int8 configurations' kernel shape."""
     d, k, s, t = cfg
-    if t == "int8" and shifted is not None and hdc.shift_supported("classify", F, Cw.shape[0]):
-        t, P = "int8shift", shifted
-    prep = hdc.Prepared(Cw, D, t, s, d, k, tile=tile if t in ("int8", "int8shift") else 0)
+    plain_t = t
+    if shifted and t in shifted:
+        t, P = hdc.SHIFTED[t], shifted[t]
+    prep = hdc.Prepared(Cw, D, t, s, d, k, tile=tile if plain_t == "int8" else 0)
     labels = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
     prep(X, F, P, labels)
     torch.cuda.synchronize()

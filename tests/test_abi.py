@@ -276,6 +276,16 @@ def test_tile_variants_without_device(lib):
     assert variants(CLS, INT8, SHIFT, 1024, 10) is None
     assert variants(CLS, UINT8, SHIFT, 617, 26) is None
     assert variants(CLS, FP32, SHIFT, 64, 2) is None
+    # E4M3 on the shifted projection: the direct 2x2 shape, 256 < F <= 640,
+    # byte features of either kind, up to two class tiles
+    SHIFT8 = 7
+    assert variants(CLS, INT8, SHIFT8, 617, 26) == [1]
+    assert variants(CLS, UINT8, SHIFT8, 300, 64) == [1]
+    assert variants(ENC, INT8, SHIFT8, 640, 0) == [1]
+    assert variants(CLS, INT8, SHIFT8, 256, 26) is None
+    assert variants(CLS, INT8, SHIFT8, 784, 10) is None
+    assert variants(CLS, INT8, SHIFT8, 617, 100) is None
+    assert variants(CLS, FP32, SHIFT8, 64, 2) is None
     assert not hasattr(lib, "hdc_set_tile") and not hasattr(lib, "hdc_get_tile")
     p, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
     fake = C.c_void_p(1 << 20)

@@ -64,15 +64,26 @@ def test_shift_projection_layout(hdc):
     hdc.shift_projection(Q, F, out=Q)
     torch.cuda.synchronize()
     assert np.array_equal(Q.cpu().numpy(), ref)
+    # the E4M3 form: 2.0 = 0x40 where p = +1, 0 where p = -1 and in the pad
+    E = hdc.shift_projection(Pd, F, compute="fp8shift")
+    torch.cuda.synchronize()
+    refe = np.zeros(Pd.shape, np.uint8)
+    refe[:, :F] = np.where(P > 0, 0x40, 0)
+    assert np.array_equal(E.cpu().numpy().view(np.uint8), refe)
     lib = hdc.lib()
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    I8S, FP8 = hdc.DTYPE["int8shift"], hdc.DTYPE["fp8"]
     # overlap with another pitch, misaligned pitch, F past the pitch: refused before any launch
-    assert lib.hdc_shift_projection(st, C.c_void_p(W.data_ptr()), D // 2, F, 1024, C.c_void_p(W.data_ptr() + 64),
-                                    640) == 1
-    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, F, 640, C.c_void_p(W.data_ptr()), 648) == 1
-    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, 700, 640, C.c_void_p(W.data_ptr()), 1024) == 1
-    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, 1025, 640, C.c_void_p(W.data_ptr()),
+    assert lib.hdc_shift_projection(st, C.c_void_p(W.data_ptr()), D // 2, F, 1024, I8S,
+                                    C.c_void_p(W.data_ptr() + 64), 640) == 1
+    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, F, 640, I8S, C.c_void_p(W.data_ptr()),
+                                    648) == 1
+    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, 700, 640, I8S, C.c_void_p(W.data_ptr()),
+                                    1024) == 1
+    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, 1025, 640, I8S, C.c_void_p(W.data_ptr()),
                                     1024) == 2
+    assert lib.hdc_shift_projection(st, C.c_void_p(Pd.data_ptr()), D, F, 640, FP8, C.c_void_p(W.data_ptr()),
+                                    1024) == 2                # not a shifted type
 
 
 CLS_SHIFT = [
@@ -186,3 +197,50 @@ def test_shifted_refuses_what_it_does_not_run(hdc):
     with pytest.raises(hdc.HDCError) as e:
         hdc.classify(hdc.pad_cols(Xs), 200, hdc.shift_projection(hdc.pad_cols(Psm), 200), 256, Cd, "int8shift")
     assert e.value.code == 2
+
+
+CLS_SHIFT8 = [
+    # n, F, D, K, x_type, (start, d_trunc, stride)
+    (1, 617, 1024, 26, "int8", None),
+    (63, 617, 2048, 26, "int8", (0, 1000, 1)),
+    (700, 617, 4096, 26, "int8", (3, 4096, 2)),
+    (130, 300, 1536, 40, "int8", (1, 1500, 3)),
+    (257, 512, 2000, 64, "uint8", None),
+    (90, 640, 1100, 7, "uint8", (0, 1100, 7)),
+]
+
+
+@pytest.mark.parametrize("case", CLS_SHIFT8, ids=str)
+def test_classify_fp8_shifted_equals_fp8(hdc, case):
+    """E4M3 on the shifted projection: labels and distances equal to the
+    oracle's E4M3 classification (features rounded to E4M3, +-1 weights,
+    exact sums) on the +-1 projection, split and unsplit launches."""
+    n, F, D, K, xt, dims = case
+    start, d_trunc, stride = dims or (0, D, 1)
+    X, P = dg.random_case(n, F, D, xt, seed=5 * n + F)
+    Cw = class_words(K, D, n + 2 * K)
+    lref, dref = O.classify(X, P, Cw, "fp8", start, d_trunc, stride, with_dists=True)
+    Xd, Cd = hdc.pad_cols(X), dev(Cw.view(np.int64))
+    Pe = hdc.shift_projection(hdc.pad_cols(P), F, compute="fp8shift")
+    assert hdc.tile_variants("classify", xt, "fp8shift", F, K) == [1]
+    for split in (True, False):
+        say("classify fp8 shifted", case, "split", split)
+        lab, dist = hdc.classify(Xd, F, Pe, D, Cd, "fp8shift", start, d_trunc, stride, with_dists=True,
+                                 split=split)
+        torch.cuda.synchronize()
+        assert np.array_equal(dist.cpu().numpy(), dref), split
+        assert np.array_equal(lab.cpu().numpy(), lref), split
+
+
+@pytest.mark.parametrize("case", [(65, 617, 2048, "int8", (0, 1000, 1)), (300, 640, 1100, "uint8", (3, 1100, 7)),
+                                  (520, 617, 10240, "int8", None)], ids=str)
+def test_encode_fp8_shifted_equals_fp8(hdc, case):
+    n, F, D, xt, dims = case
+    start, end, stride = dims or (0, D, 1)
+    say("encode fp8 shifted", case)
+    X, P = dg.random_case(n, F, D, xt, seed=13 * n + F)
+    ref = O.encode(X, P, "fp8", start, end, stride)
+    Pe = hdc.shift_projection(hdc.pad_cols(P), F, compute="fp8shift")
+    H = hdc.encode(hdc.pad_cols(X), F, Pe, D, "fp8shift", start, end, stride)
+    torch.cuda.synchronize()
+    assert np.array_equal(H.cpu().numpy().view(np.uint64), ref)

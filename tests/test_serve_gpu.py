@@ -98,3 +98,28 @@ def test_warm_with_tile_tuning_keeps_labels(setup):
     after = run_alone(serve, models, [serve.Request(model=m, X=X) for m, X in reqs])
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cfg", [(10240, 1, 0, "int8"), (5120, 2, 0, "int8"), (10240, 1, 0, "fp8"),
+                                 (4096, 2, 1, "fp8"), (8192, 2, 0, "bf16")], ids=str)
+def test_resident_model_forms_against_oracle(setup, cfg):
+    """The 617-feature model keeps shifted projections for int8 and E4M3:
+    its prepared classifiers of those types read them (the others the +-1
+    projection), and every configuration served through the executor gives
+    the oracle's labels."""
+    serve, srcs, models = setup
+    print("[case] resident model forms", cfg, flush=True)
+    src, m = srcs[2], models[2]
+    assert set(m.shifted) == {"int8", "fp8"}
+    m.set_tuned(cfg)
+    d, k, s, t = cfg
+    assert m.tuned.compute == {"int8": "int8shift", "fp8": "fp8shift"}.get(t, t)
+    assert (m.tuned.P is m.shifted[t]) if t in m.shifted else (m.tuned.P is m.P)
+    X, _ = src.queries(777, 55)
+    ex = serve.GpuExecutor(models)
+    srv = serve.Server(ex, budget=1 << 34)
+    got = srv.submit(serve.Request(model=2, X=X, tuned=True)).result(timeout=60)
+    srv.close()
+    C = m.C.cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, O.classify(X, src.P, C, t, s, d, k))
+    m.set_tuned((src.D // 2, 2, 0, "int8"))

@@ -185,10 +185,11 @@ struct Encoder {
     // clock under full load.  The E4M3 path (weights 0 / 2.0) takes minus
     // the sum of its rounded features from the matrix cores (an all -1.0
     // operand against the query fragments; integers below 2^24, exact in
-    // fp32).  Only the shapes of shift_tile / shift8_tile take the shifted
-    // projection; the others start from 0.
+    // fp32).  Only the shapes the shifted types launch take the shifted
+    // projection (int8: two query tiles, shift_tile; E4M3: one query tile,
+    // shift8_tile); the others start from 0.
     static constexpr bool kShift = DMA && ((CT == C_I8 && QT == 2 && shift_tile(KS, KT)) ||
-                                           (CT == C_FP8 && shift8_tile(KS, KT)));
+                                           (CT == C_FP8 && QT == 1 && shift8_tile(KS, KT)));
     static __device__ __forceinline__ void shift_start(acc_t (&x0)[QT], const xfrag (&xr)[QT][KS], int poff)
     {
 #pragma unroll

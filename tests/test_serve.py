@@ -231,8 +231,9 @@ def test_automatic_gc_is_off_while_serving_and_restored():
 
 
 def test_gpu_executor_staging_copy():
-    """The executor's staging copy writes each request at its offset and
-    zeroes the pad columns, as one plain copy would."""
+    """The executor's staging copy writes each request at its offset, as
+    one plain copy would, and leaves the pad columns (which the kernels
+    ignore) alone."""
     import torch
 
     from paper_2606_26547_amd.serve import GpuExecutor
@@ -244,6 +245,6 @@ def test_gpu_executor_staging_copy():
     b = SimpleNamespace(requests=reqs, offsets=offs, n=sum(r.n for r in reqs))
     hxt = torch.full((b.n, 64), 7, dtype=torch.int8)
     ex._stage(hxt, b, 37, 64)
-    ref = np.zeros((b.n, 64), np.int8)
+    ref = np.full((b.n, 64), 7, np.int8)
     ref[:, :37] = np.concatenate([r.X for r in reqs])
     assert np.array_equal(hxt.numpy(), ref)
